@@ -1,0 +1,199 @@
+/*
+ * fmt.h -- C ABI of the free-mesh transform (FMT) library for MI355X (gfx950).
+ *
+ * The library fits a scattered-data interpolant by top-down octree scoping of
+ * the residual and evaluates it at new points (Challacombe, "A N-Body Solver
+ * for Free Mesh Interpolation", arXiv:1511.01353):
+ *
+ *   fit  : Alg. 1 (recursive octree decomposition of the residual) with
+ *          Alg. 2 (least-squares moments of one node) at every node;
+ *   eval : the practical transform f'_q = Lambda'_q . F_p of Section 2, summed
+ *          over the root-to-leaf chain of nodes that hold the query.
+ *
+ * Conventions shared by every call:
+ *   - Points live in a box [box_lo, box_hi] (default the unit cube).  The
+ *     root node is the box; a node of depth d has side h = (hi - lo) / 2^d per
+ *     axis.  Cells at the finest depth D are
+ *       q = clamp(floor((x - lo) * (2^D / (hi - lo))), 0, 2^D - 1)
+ *     evaluated in float64; a point on a split plane belongs to the upper
+ *     child, a point at x = hi to the last cell.  Keys interleave the cell bits
+ *     from the top level down, x highest in each triple.
+ *   - Basis: all monomials of total degree <= p in graded order (degree 0;
+ *     then x, y, z; then the six of degree 2 with the x exponent descending,
+ *     then y descending; ...), Lambda_{lmn}(u) = u^l v^m w^n / (l! m! n!) in
+ *     the node frame u = (x - c) * (2 / h) (Section 2, geometric moments;
+ *     calL = (p+1)(p+2)(p+3)/6 basis functions).
+ *   - A child octant is fitted iff its depth is <= max_depth, it holds at
+ *     least calL points, and its RMS residual after the parent's fit exceeds
+ *     tol (strict), as Alg. 1 tests it.  The root is always fitted.
+ *   - Device pointers are HIP device addresses; host pointers are ordinary
+ *     host memory.  Every call says which it takes.  `stream` is a
+ *     hipStream_t passed as void* (NULL = the null stream).
+ *   - Calls return fmt_status; on failure fmt_last_error() (thread-local)
+ *     holds a message.  No C++ exception crosses this boundary.
+ *   - The library never keeps a caller's pointer after a call returns; the
+ *     caller keeps inputs valid until the stream has passed the call's work.
+ */
+#ifndef FMT_H
+#define FMT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMT_MAX_P 8          /* largest supported total degree (calL = 165) */
+#define FMT_MAX_DEPTH 10     /* deepest supported level; keys use 3*D bits */
+#define FMT_MAX_LEVELS (FMT_MAX_DEPTH + 1)
+
+typedef enum {
+  FMT_OK = 0,
+  FMT_E_INVALID_ARG = 1,     /* bad option, size, dtype or NULL pointer */
+  FMT_E_DOMAIN = 2,          /* a point is NaN/inf or outside [box_lo, box_hi] */
+  FMT_E_UNDERDETERMINED = 3, /* the root holds fewer than calL points */
+  FMT_E_OOM = 4,             /* device allocation failed; nothing leaked */
+  FMT_E_NUMERIC = 5,         /* a non-finite coefficient was produced */
+  FMT_E_DEVICE = 6,          /* a HIP runtime call failed */
+  FMT_E_BUSY = 7             /* reserved for callers that admit work by budget */
+} fmt_status;
+
+typedef enum { FMT_F32 = 0, FMT_F64 = 1 } fmt_dtype;
+
+typedef enum {
+  /* every step in float64: Gram on float64 MFMA, Cholesky, refinement */
+  FMT_PATH_FP64 = 0,
+  /* Gram of the monomials on float32 MFMA (float32 accumulation within a
+     chunk of points, chunks summed in float64); float64 Cholesky; float64
+     refinement sweeps (residual, Lambda^T r) recover float64 accuracy */
+  FMT_PATH_MIXED = 1
+} fmt_path;
+
+typedef struct {
+  int p;               /* maximum total degree, 0..FMT_MAX_P */
+  double tol;          /* tau: split tolerance on the octant RMS residual, >= 0 */
+  int max_depth;       /* D, 0..FMT_MAX_DEPTH; the root is depth 0 */
+  int path;            /* fmt_path */
+  int refine_steps;    /* iterative-refinement sweeps per node, 0..8 */
+  double box_lo[3];    /* root box; default 0 */
+  double box_hi[3];    /* default 1; box_hi > box_lo on every axis */
+} fmt_fit_opts;
+
+typedef struct fmt_tree fmt_tree;   /* opaque; its storage lives in device memory */
+
+typedef struct {
+  int64_t nodes;                          /* nodes in this tree */
+  int64_t n_points;                       /* points it was fitted on (0 if imported) */
+  int32_t depth;                          /* deepest level present */
+  int32_t p;                              /* total degree */
+  int32_t L;                              /* calL */
+  int32_t max_depth;                      /* D */
+  int32_t path;                           /* fmt_path */
+  int32_t rank_deficient_nodes;           /* nodes where a Cholesky pivot was deflated */
+  int64_t per_level[FMT_MAX_LEVELS];      /* nodes at each depth */
+  int64_t device_bytes;                   /* device memory held by the tree's forest */
+} fmt_tree_info;
+
+/* Fill `opts` with the defaults: p = 4, tol = 1e-8, max_depth = 6,
+   path = FMT_PATH_FP64, refine_steps = 1, box = [0,1]^3. */
+void fmt_default_opts(fmt_fit_opts* opts);
+
+/*
+ * Fit one problem (Alg. 1 at the root, Alg. 2 at every node).
+ *   x, y, z, f : device arrays of n values of `dtype` (SoA coordinates and the
+ *                sampled function).  f is not modified.
+ *   n          : number of points, calL <= n < 2^31.
+ *   out        : receives a new tree; release it with fmt_tree_destroy.
+ * The call validates options synchronously, then runs the fit on `stream`;
+ * it returns after the tree is complete (the host reads small per-level
+ * counts).  Errors: INVALID_ARG, UNDERDETERMINED (n < calL), DOMAIN, OOM,
+ * NUMERIC, DEVICE.  On error *out is NULL.
+ */
+fmt_status fmt_fit(const fmt_fit_opts* opts, const void* x, const void* y, const void* z,
+                   const void* f, int64_t n, int dtype, void* stream, fmt_tree** out);
+
+/*
+ * Fit `count` independent problems in one pass: one sort of composite keys
+ * (problem id above the Morton bits) and one launch per level and kernel that
+ * covers every problem's nodes at that level.
+ *   opts       : host array of `count` options.  Problems may differ in p,
+ *                path and box; they are grouped by (p, path, max_depth,
+ *                refine_steps) and each group runs as one batched pass.
+ *   x,y,z,f    : host arrays of `count` device pointers.
+ *   n          : host array of `count` sizes (each >= its calL).
+ *   out        : host array of `count` tree handles, filled on success.
+ * Trees of one group share device storage; each handle keeps it alive.
+ * Errors as fmt_fit; on error no handle is returned.
+ */
+fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const void* const* y,
+                         const void* const* z, const void* const* f, const int64_t* n,
+                         int count, int dtype, void* stream, fmt_tree** out);
+
+/*
+ * Evaluate a tree at nq query points (Section 2, f'_q = Lambda'_q F_p, summed
+ * over the existing root-to-leaf chain).
+ *   qx,qy,qz   : device arrays of nq values of `dtype`.
+ *   out        : device array of nq float64 results.
+ *   sort_queries: 0 = evaluate in input order; 1 = sort queries by key first
+ *                (coherent coefficient reads; results still in input order);
+ *                -1 = let the library choose.
+ * Queries outside the box follow the clamped cell path; their polynomials
+ * are evaluated at the true coordinates.  Asynchronous on `stream`.
+ * Errors: INVALID_ARG, OOM, DEVICE.
+ */
+fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const void* qz,
+                    int64_t nq, int dtype, double* out, int sort_queries, void* stream);
+
+/* Wait for all work of the tree's forest and report device-side status
+   (DOMAIN for points outside the box, NUMERIC for non-finite coefficients). */
+fmt_status fmt_tree_wait(const fmt_tree* tree);
+
+/* Host-side summary of a tree. */
+fmt_status fmt_tree_get_info(const fmt_tree* tree, fmt_tree_info* info);
+
+/*
+ * Copy the tree's nodes to host buffers (any pointer may be NULL).  Nodes are
+ * in (level, prefix) order; each buffer holds info.nodes entries (coeffs:
+ * info.nodes * info.L float64 in graded order, the Lambda basis).
+ *   prefix : the node's key prefix (Morton bits of its cell, 3*level bits)
+ *   begin  : first position of its points in the key-sorted point order
+ *   count  : its point count
+ */
+fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t* prefix,
+                                 uint32_t* begin, uint32_t* count, double* coeffs);
+
+/*
+ * Copy per-point results to host buffers of info.n_points entries, indexed by
+ * the caller's input index (any pointer may be NULL):
+ *   keys     : Morton key of the point's cell at depth D
+ *   order    : order[i] = input index of the i-th point in key order (stable)
+ *   leaf     : index (in export order) of the deepest node holding the point
+ *   residual : final residual f - fitted value (float64)
+ */
+fmt_status fmt_tree_export_points(const fmt_tree* tree, uint32_t* keys, uint32_t* order,
+                                  uint32_t* leaf, double* residual);
+
+/*
+ * Rebuild an evaluable tree from exported nodes (checkpoint / resume):
+ * `opts` supplies p, max_depth and the box; level, prefix and coeffs are host
+ * arrays of `nodes` entries as fmt_tree_export_nodes writes them.  Every
+ * non-root node's parent must be present.  Errors: INVALID_ARG, OOM, DEVICE.
+ */
+fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_t* level,
+                           const uint32_t* prefix, const double* coeffs, void* stream,
+                           fmt_tree** out);
+
+/* Release a tree (NULL is ignored).  Waits for the forest's pending work. */
+void fmt_tree_destroy(fmt_tree* tree);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* fmt_last_error(void);
+
+/* Library version string. */
+const char* fmt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMT_H */

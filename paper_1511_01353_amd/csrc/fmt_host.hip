@@ -1,0 +1,748 @@
+// Host runtime of the FMT library: the level loop that drives the kernels,
+// forests (the device storage of one fit or one batch of fits), and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fmt_common.h"
+#include "k_level.h"
+#include "k_sort.h"
+
+using namespace fmt;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+namespace {
+
+thread_local std::string g_last_error;
+
+struct FmtError : std::runtime_error {
+  fmt_status code;
+  FmtError(fmt_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(fmt_status c, const std::string& m) { throw FmtError(c, m); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    fail(FMT_E_OOM, std::string(what) + ": out of device memory");
+  }
+  fail(FMT_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(x) hip_check((x), #x)
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) n = 256;
+    hip_check(hipMalloc(&p, n), "hipMalloc");
+    bytes = n;
+  }
+  // grow-only reallocation (contents are not kept)
+  void reserve(size_t n) {
+    if (n > bytes) alloc(std::max(n, bytes + bytes / 2));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return (T*)p; }
+};
+
+// Reusable scratch of the level loop, one set per stream (fits on one stream
+// are serialised by the stream itself; different streams never share).
+struct Workspace {
+  DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz;
+  DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status, params, ptrs;
+  uint32_t* host_counters = nullptr;
+  std::mutex mu;
+  Workspace() { hip_check(hipHostMalloc((void**)&host_counters, 64, hipHostMallocDefault), "hipHostMalloc"); }
+  ~Workspace() {
+    if (host_counters) (void)hipHostFree(host_counters);
+  }
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace& workspace_for(hipStream_t s) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_ws_mu);
+  auto& w = g_ws[{dev, s}];
+  if (!w) w.reset(new Workspace());
+  return *w;
+}
+
+// ---------------------------------------------------------------------------
+// forests and trees
+// ---------------------------------------------------------------------------
+struct ProblemInfo {
+  ProblemParams prm;
+  uint32_t root;    // node index of the root
+  int64_t n;
+};
+
+struct Forest {
+  int p = 0, L = 0, D = 0, path = 0, dtype = 0, refine = 0;
+  int nprob = 0;
+  int pbits = 0;                         // problem-id bits above the Morton bits
+  uint32_t nodes = 0;
+  std::vector<uint32_t> level_start, level_count;
+  std::vector<ProblemInfo> probs;
+  // node table (exact size)
+  DevBuf nb_begin, nb_count, nb_prefix, nb_level, nb_problem, nb_parent, nb_first_child, nb_child_mask, nb_flags,
+      nb_geo, nb_coef;
+  // per point, key order
+  DevBuf skey, order, resid;
+  uint32_t ntot = 0;
+  hipStream_t stream = nullptr;
+  uint32_t device_status = 0;
+  int device = 0;
+  // host copies made on first export
+  std::mutex host_mu;
+  bool host_ready = false;
+  std::vector<uint32_t> h_begin, h_count, h_prefix, h_level, h_problem, h_flags;
+  std::vector<double> h_coef;
+
+  NodeTable table() const {
+    NodeTable t;
+    t.begin = nb_begin.as<uint32_t>();
+    t.count = nb_count.as<uint32_t>();
+    t.prefix = nb_prefix.as<uint32_t>();
+    t.level = nb_level.as<uint32_t>();
+    t.problem = nb_problem.as<uint32_t>();
+    t.parent = nb_parent.as<uint32_t>();
+    t.first_child = nb_first_child.as<uint32_t>();
+    t.child_mask = nb_child_mask.as<uint32_t>();
+    t.flags = nb_flags.as<uint32_t>();
+    t.geo = nb_geo.as<double>();
+    t.coef = nb_coef.as<double>();
+    return t;
+  }
+  size_t device_bytes() const {
+    return nb_begin.bytes + nb_count.bytes + nb_prefix.bytes + nb_level.bytes + nb_problem.bytes + nb_parent.bytes +
+           nb_first_child.bytes + nb_child_mask.bytes + nb_flags.bytes + nb_geo.bytes + nb_coef.bytes + skey.bytes +
+           order.bytes + resid.bytes;
+  }
+  void alloc_nodes(uint32_t cap) {
+    const size_t u = sizeof(uint32_t) * (size_t)cap;
+    nb_begin.alloc(u); nb_count.alloc(u); nb_prefix.alloc(u); nb_level.alloc(u); nb_problem.alloc(u);
+    nb_parent.alloc(u); nb_first_child.alloc(u); nb_child_mask.alloc(u); nb_flags.alloc(u);
+    nb_geo.alloc(sizeof(double) * 6 * (size_t)cap);
+    nb_coef.alloc(sizeof(double) * (size_t)L * (size_t)cap);
+  }
+  void fetch_host() {
+    std::lock_guard<std::mutex> g(host_mu);
+    if (host_ready) return;
+    HIPCHK(hipStreamSynchronize(stream));
+    auto get = [&](std::vector<uint32_t>& v, const DevBuf& b) {
+      v.resize(nodes);
+      if (nodes) HIPCHK(hipMemcpy(v.data(), b.p, sizeof(uint32_t) * nodes, hipMemcpyDeviceToHost));
+    };
+    get(h_begin, nb_begin); get(h_count, nb_count); get(h_prefix, nb_prefix); get(h_level, nb_level);
+    get(h_problem, nb_problem); get(h_flags, nb_flags);
+    h_coef.resize((size_t)nodes * L);
+    if (nodes) HIPCHK(hipMemcpy(h_coef.data(), nb_coef.p, sizeof(double) * nodes * L, hipMemcpyDeviceToHost));
+    host_ready = true;
+  }
+};
+
+}  // namespace
+
+struct fmt_tree {
+  std::shared_ptr<Forest> forest;
+  int problem = 0;
+  std::vector<uint32_t> nodes;   // this tree's node indices in (level, prefix) order (filled lazily)
+  bool nodes_ready = false;
+  std::mutex mu;
+};
+
+namespace {
+
+const int kRefineMax = 8;
+
+int ceil_log2(int k) {
+  int b = 0;
+  while ((1 << b) < k) ++b;
+  return b;
+}
+
+void validate_opts(const fmt_fit_opts& o) {
+  if (o.p < 0 || o.p > FMT_MAX_P) fail(FMT_E_INVALID_ARG, "p out of range 0..FMT_MAX_P");
+  if (o.max_depth < 0 || o.max_depth > FMT_MAX_DEPTH) fail(FMT_E_INVALID_ARG, "max_depth out of range 0..10");
+  if (!(o.tol >= 0.0) || std::isinf(o.tol)) fail(FMT_E_INVALID_ARG, "tol must be finite and >= 0");
+  if (o.path != FMT_PATH_FP64 && o.path != FMT_PATH_MIXED) fail(FMT_E_INVALID_ARG, "unknown path");
+  if (o.refine_steps < 0 || o.refine_steps > kRefineMax) fail(FMT_E_INVALID_ARG, "refine_steps out of range 0..8");
+  for (int a = 0; a < 3; ++a)
+    if (!(o.box_hi[a] > o.box_lo[a]) || !std::isfinite(o.box_lo[a]) || !std::isfinite(o.box_hi[a]))
+      fail(FMT_E_INVALID_ARG, "box_hi must exceed box_lo on every axis");
+}
+
+ProblemParams make_params(const fmt_fit_opts& o, uint32_t n, uint32_t offset) {
+  ProblemParams P;
+  for (int a = 0; a < 3; ++a) {
+    P.lo[a] = o.box_lo[a];
+    P.hi[a] = o.box_hi[a];
+    P.qscale[a] = std::ldexp(1.0, o.max_depth) / (o.box_hi[a] - o.box_lo[a]);
+  }
+  P.n = n;
+  P.offset = offset;
+  return P;
+}
+
+struct FitInput {
+  const void *x, *y, *z, *f;
+  int64_t n;
+};
+
+// One batched pass of Alg. 1 over `in.size()` problems sharing p, D, path
+// and refinement count.
+std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_fit_opts>& per,
+                                  const std::vector<FitInput>& in, int dtype, hipStream_t s) {
+  auto F = std::make_shared<Forest>();
+  F->p = o.p;
+  F->L = basis_size(o.p);
+  F->D = o.max_depth;
+  F->path = o.path;
+  F->dtype = dtype;
+  F->refine = o.refine_steps;
+  F->nprob = (int)in.size();
+  F->stream = s;
+  HIPCHK(hipGetDevice(&F->device));
+  const int K = F->nprob;
+  F->pbits = K > 1 ? ceil_log2(K) : 0;
+  if (3 * F->D + F->pbits > 32) fail(FMT_E_INVALID_ARG, "too many problems for the key width at this depth");
+  const uint32_t L = (uint32_t)F->L;
+  uint64_t ntot = 0;
+  std::vector<ProblemParams> prm(K);
+  std::vector<PtrSet> ptrs(K);
+  std::vector<double> tols(K);
+  for (int k = 0; k < K; ++k) {
+    if (in[k].n < (int64_t)L) fail(FMT_E_UNDERDETERMINED, "the root holds fewer than calL points");
+    if (!in[k].x || !in[k].y || !in[k].z || !in[k].f) fail(FMT_E_INVALID_ARG, "NULL input pointer");
+    prm[k] = make_params(per[k], (uint32_t)in[k].n, (uint32_t)ntot);
+    ptrs[k] = PtrSet{in[k].x, in[k].y, in[k].z, in[k].f};
+    tols[k] = per[k].tol;
+    ntot += (uint64_t)in[k].n;
+    if (ntot >= (1ull << 31)) fail(FMT_E_INVALID_ARG, "total point count must stay below 2^31");
+  }
+  for (int k = 1; k < K; ++k)
+    if (tols[k] != tols[0]) fail(FMT_E_INVALID_ARG, "one batched pass needs one tolerance");
+  const uint32_t N = (uint32_t)ntot;
+  F->ntot = N;
+  const size_t esz = dtype == FMT_F32 ? 4 : 8;
+
+  Workspace& W = workspace_for(s);
+  std::lock_guard<std::mutex> wlock(W.mu);
+
+  // per-point storage kept by the forest
+  F->skey.alloc(4ull * N);
+  F->order.alloc(4ull * N);
+  F->resid.alloc(8ull * N);
+  W.keys_alt.reserve(4ull * N);
+  W.vals_alt.reserve(4ull * N);
+  W.sort_scratch.reserve(4 * radix_sort_scratch_words(N));
+  W.px.reserve(esz * N);
+  W.py.reserve(esz * N);
+  W.pz.reserve(esz * N);
+  W.params.reserve(sizeof(ProblemParams) * K);
+  W.ptrs.reserve(sizeof(PtrSet) * K);
+  W.status.reserve(64);
+  W.counters.reserve(64);
+  HIPCHK(hipMemcpyAsync(W.params.p, prm.data(), sizeof(ProblemParams) * K, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(W.ptrs.p, ptrs.data(), sizeof(PtrSet) * K, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
+  const ProblemParams* d_prm = W.params.as<ProblemParams>();
+
+  // K1 keys, K2 sort, K3 gather
+  HIPCHK(launch_keygen(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->D, N, F->skey.as<uint32_t>(),
+                       W.status.as<uint32_t>(), s));
+  bool in_alt = false;
+  HIPCHK(radix_sort(F->skey.as<uint32_t>(), F->order.as<uint32_t>(), W.keys_alt.as<uint32_t>(),
+                    W.vals_alt.as<uint32_t>(), N, 3 * F->D + F->pbits, true, W.sort_scratch.as<uint32_t>(), s,
+                    &in_alt));
+  if (in_alt) {
+    HIPCHK(hipMemcpyAsync(F->skey.p, W.keys_alt.p, 4ull * N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(F->order.p, W.vals_alt.p, 4ull * N, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(launch_gather(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->order.as<uint32_t>(), N, W.px.p, W.py.p, W.pz.p,
+                       F->resid.as<double>(), s));
+
+  // node capacity: at depth d at most min(K 8^d, N / L) nodes
+  uint64_t cap = 0;
+  for (int d = 0; d <= F->D; ++d) {
+    uint64_t a = (uint64_t)K << std::min(3 * d, 40);
+    cap += std::min<uint64_t>(a, d == 0 ? (uint64_t)K : std::max<uint64_t>(N / L, 1));
+  }
+  if (cap >= (1ull << 31)) fail(FMT_E_INVALID_ARG, "node capacity overflow");
+  Forest tmp;   // workspace node table with the capacity bound
+  tmp.L = F->L;
+  tmp.alloc_nodes((uint32_t)cap);
+  NodeTable nt = tmp.table();
+  HIPCHK(launch_roots(nt, d_prm, K, s));
+
+  // level 0 chunk offsets
+  std::vector<uint32_t> off0(K + 1, 0);
+  for (int k = 0; k < K; ++k) off0[k + 1] = off0[k] + (uint32_t)((in[k].n + CHUNK - 1) / CHUNK);
+  W.chunk_a.reserve(4ull * (K + 1));
+  HIPCHK(hipMemcpyAsync(W.chunk_a.p, off0.data(), 4ull * (K + 1), hipMemcpyHostToDevice, s));
+
+  uint32_t nnodes = (uint32_t)K, nchunks = off0[K], node0 = 0;
+  F->level_start.clear();
+  F->level_count.clear();
+  DevBuf* cur_off = &W.chunk_a;
+  DevBuf* next_off = &W.chunk_b;
+  const size_t gpd = gram_partial_doubles(F->p), fd = factor_doubles(F->p);
+  for (int d = 0; d <= F->D && nnodes > 0; ++d) {
+    F->level_start.push_back(node0);
+    F->level_count.push_back(nnodes);
+    W.partial.reserve(8ull * gpd * nchunks);
+    if (F->refine > 0) {
+      W.fac.reserve(8ull * fd * nnodes);
+      W.part_b.reserve(8ull * L * nchunks);
+    }
+    W.part_ss.reserve(8ull * 8 * nchunks);
+    W.cbeg.reserve(4ull * 8 * nnodes);
+    W.ccnt.reserve(4ull * 8 * nnodes);
+    W.nact.reserve(4ull * nnodes);
+    next_off->reserve(4ull * (8ull * nnodes + 1));
+
+    LevelArgs a;
+    a.nt = nt;
+    a.node0 = node0;
+    a.nnodes = nnodes;
+    a.chunk_off = cur_off->as<uint32_t>();
+    a.nchunks = nchunks;
+    a.px = W.px.p;
+    a.py = W.py.p;
+    a.pz = W.pz.p;
+    a.r = F->resid.as<double>();
+    a.skey = F->skey.as<uint32_t>();
+    a.level = d;
+    a.D = F->D;
+    a.tol = tols[0];
+
+    HIPCHK(launch_gram(F->p, F->path, dtype, a, W.partial.as<double>(), s));
+    HIPCHK(launch_solve(F->p, a, W.partial.as<double>(), F->refine > 0 ? W.fac.as<double>() : nullptr, s));
+    for (int it = 0; it < F->refine; ++it) {
+      HIPCHK(launch_refine_sweep(F->p, dtype, a, W.part_b.as<double>(), s));
+      HIPCHK(launch_refine_solve(F->p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
+    }
+    HIPCHK(launch_residual(F->p, dtype, a, W.part_ss.as<double>(), s));
+    if (d == F->D) {
+      node0 += nnodes;
+      break;
+    }
+    HIPCHK(launch_children(F->p, a, W.part_ss.as<double>(), W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(),
+                           W.nact.as<uint32_t>(), s));
+    const uint32_t next0 = node0 + nnodes;
+    HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
+                       next_off->as<uint32_t>(), W.counters.as<uint32_t>(), s));
+    HIPCHK(hipMemcpyAsync(W.host_counters, W.counters.p, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    node0 = next0;
+    nnodes = W.host_counters[0];
+    nchunks = W.host_counters[1];
+    std::swap(cur_off, next_off);
+  }
+  F->nodes = node0;
+  HIPCHK(launch_check_coef(F->p, nt, F->nodes, W.status.as<uint32_t>(), s));
+
+  // compact the node table into the forest
+  F->alloc_nodes(std::max<uint32_t>(F->nodes, 1));
+  auto cp = [&](DevBuf& dst, const DevBuf& src, size_t bytes) {
+    if (bytes) HIPCHK(hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyDeviceToDevice, s));
+  };
+  const size_t un = 4ull * F->nodes;
+  cp(F->nb_begin, tmp.nb_begin, un); cp(F->nb_count, tmp.nb_count, un); cp(F->nb_prefix, tmp.nb_prefix, un);
+  cp(F->nb_level, tmp.nb_level, un); cp(F->nb_problem, tmp.nb_problem, un); cp(F->nb_parent, tmp.nb_parent, un);
+  cp(F->nb_first_child, tmp.nb_first_child, un); cp(F->nb_child_mask, tmp.nb_child_mask, un);
+  cp(F->nb_flags, tmp.nb_flags, un);
+  cp(F->nb_geo, tmp.nb_geo, 48ull * F->nodes);
+  cp(F->nb_coef, tmp.nb_coef, 8ull * L * F->nodes);
+  HIPCHK(hipMemcpyAsync(W.host_counters + 4, W.status.p, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  F->device_status = W.host_counters[4];
+
+  F->probs.resize(K);
+  for (int k = 0; k < K; ++k) {
+    F->probs[k].prm = prm[k];
+    F->probs[k].root = (uint32_t)k;
+    F->probs[k].n = in[k].n;
+  }
+  if (F->device_status & STATUS_DOMAIN) fail(FMT_E_DOMAIN, "a point is NaN or outside the box");
+  if (F->device_status & STATUS_NONFINITE) fail(FMT_E_NUMERIC, "a non-finite coefficient was produced");
+  return F;
+}
+
+fmt_status guard(const std::function<void()>& body) {
+  try {
+    body();
+    g_last_error.clear();
+    return FMT_OK;
+  } catch (const FmtError& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host out of memory";
+    return FMT_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return FMT_E_DEVICE;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return FMT_E_DEVICE;
+  }
+}
+
+void ensure_tree_nodes(fmt_tree* t) {
+  std::lock_guard<std::mutex> g(t->mu);
+  if (t->nodes_ready) return;
+  Forest& F = *t->forest;
+  F.fetch_host();
+  t->nodes.clear();
+  for (uint32_t i = 0; i < F.nodes; ++i)
+    if ((int)F.h_problem[i] == t->problem) t->nodes.push_back(i);
+  t->nodes_ready = true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void fmt_default_opts(fmt_fit_opts* o) {
+  if (!o) return;
+  o->p = 4;
+  o->tol = 1e-8;
+  o->max_depth = 6;
+  o->path = FMT_PATH_FP64;
+  o->refine_steps = 1;
+  for (int a = 0; a < 3; ++a) {
+    o->box_lo[a] = 0.0;
+    o->box_hi[a] = 1.0;
+  }
+}
+
+const char* fmt_last_error(void) { return g_last_error.c_str(); }
+
+const char* fmt_version(void) { return "fmt-mi355x 0.1 (gfx950)"; }
+
+fmt_status fmt_fit(const fmt_fit_opts* opts, const void* x, const void* y, const void* z, const void* f, int64_t n,
+                   int dtype, void* stream, fmt_tree** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!opts || !out) fail(FMT_E_INVALID_ARG, "NULL opts or out");
+    if (dtype != FMT_F32 && dtype != FMT_F64) fail(FMT_E_INVALID_ARG, "dtype must be FMT_F32 or FMT_F64");
+    validate_opts(*opts);
+    if (n < 0) fail(FMT_E_INVALID_ARG, "negative n");
+    std::vector<fmt_fit_opts> per(1, *opts);
+    std::vector<FitInput> in(1, FitInput{x, y, z, f, n});
+    auto F = fit_group(*opts, per, in, dtype, (hipStream_t)stream);
+    fmt_tree* t = new fmt_tree();
+    t->forest = F;
+    t->problem = 0;
+    *out = t;
+  });
+}
+
+fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const void* const* y, const void* const* z,
+                         const void* const* f, const int64_t* n, int count, int dtype, void* stream,
+                         fmt_tree** out) {
+  return guard([&] {
+    if (!opts || !x || !y || !z || !f || !n || !out) fail(FMT_E_INVALID_ARG, "NULL argument");
+    if (count <= 0) fail(FMT_E_INVALID_ARG, "count must be positive");
+    if (dtype != FMT_F32 && dtype != FMT_F64) fail(FMT_E_INVALID_ARG, "dtype must be FMT_F32 or FMT_F64");
+    for (int k = 0; k < count; ++k) {
+      out[k] = nullptr;
+      validate_opts(opts[k]);
+      if (n[k] < 0) fail(FMT_E_INVALID_ARG, "negative n");
+    }
+    // group by (p, path, max_depth, refine_steps, tol)
+    std::map<std::tuple<int, int, int, int, double>, std::vector<int>> groups;
+    for (int k = 0; k < count; ++k)
+      groups[std::make_tuple(opts[k].p, opts[k].path, opts[k].max_depth, opts[k].refine_steps, opts[k].tol)]
+          .push_back(k);
+    std::vector<fmt_tree*> made(count, nullptr);
+    try {
+      for (auto& kv : groups) {
+        const std::vector<int>& ids = kv.second;
+        std::vector<fmt_fit_opts> per;
+        std::vector<FitInput> in;
+        for (int k : ids) {
+          per.push_back(opts[k]);
+          in.push_back(FitInput{x[k], y[k], z[k], f[k], n[k]});
+        }
+        auto F = fit_group(per[0], per, in, dtype, (hipStream_t)stream);
+        for (size_t j = 0; j < ids.size(); ++j) {
+          fmt_tree* t = new fmt_tree();
+          t->forest = F;
+          t->problem = (int)j;
+          made[ids[j]] = t;
+        }
+      }
+    } catch (...) {
+      for (auto* t : made) delete t;
+      throw;
+    }
+    for (int k = 0; k < count; ++k) out[k] = made[k];
+  });
+}
+
+fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const void* qz, int64_t nq, int dtype,
+                    double* out, int sort_queries, void* stream) {
+  return guard([&] {
+    if (!tree) fail(FMT_E_INVALID_ARG, "NULL tree");
+    if (dtype != FMT_F32 && dtype != FMT_F64) fail(FMT_E_INVALID_ARG, "dtype must be FMT_F32 or FMT_F64");
+    if (nq < 0 || nq >= (1ll << 31)) fail(FMT_E_INVALID_ARG, "nq out of range");
+    if (nq == 0) return;
+    if (!qx || !qy || !qz || !out) fail(FMT_E_INVALID_ARG, "NULL query or output pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const Forest& F = *tree->forest;
+    EvalTree t;
+    t.nt = F.table();
+    t.root = F.probs[tree->problem].root;
+    t.D = F.D;
+    t.prm = F.probs[tree->problem].prm;
+    const uint32_t n = (uint32_t)nq;
+    const bool sort = sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) && F.nodes > 64);
+    if (!sort) {
+      HIPCHK(launch_eval(F.p, dtype, t, qx, qy, qz, nullptr, nullptr, n, out, s));
+      return;
+    }
+    const size_t esz = dtype == FMT_F32 ? 4 : 8;
+    const size_t words = radix_sort_scratch_words(n);
+    const size_t bytes = 16ull * n + 4 * words + 3 * esz * n + 1024;
+    char* base = nullptr;
+    HIPCHK(hipMallocAsync((void**)&base, bytes, s));
+    uint32_t* k0 = (uint32_t*)base;
+    uint32_t* v0 = k0 + n;
+    uint32_t* k1 = v0 + n;
+    uint32_t* v1 = k1 + n;
+    uint32_t* scr = v1 + n;
+    char* cbase = (char*)(scr + words);
+    cbase = (char*)(((uintptr_t)cbase + 255) & ~(uintptr_t)255);
+    void* sx = cbase;
+    void* sy = cbase + esz * n;
+    void* sz = cbase + 2 * esz * n;
+    hipError_t e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, F.D, k0, s);
+    bool in_alt = false;
+    if (e == hipSuccess) e = radix_sort(k0, v0, k1, v1, n, 3 * F.D, true, scr, s, &in_alt);
+    uint32_t* ks = in_alt ? k1 : k0;
+    uint32_t* vs = in_alt ? v1 : v0;
+    if (e == hipSuccess) e = launch_permute3(dtype, qx, qy, qz, vs, n, sx, sy, sz, s);
+    if (e == hipSuccess) e = launch_eval(F.p, dtype, t, sx, sy, sz, vs, ks, n, out, s);
+    hipError_t e2 = hipFreeAsync(base, s);
+    hip_check(e, "eval");
+    hip_check(e2, "hipFreeAsync");
+  });
+}
+
+fmt_status fmt_tree_wait(const fmt_tree* tree) {
+  return guard([&] {
+    if (!tree) fail(FMT_E_INVALID_ARG, "NULL tree");
+    HIPCHK(hipStreamSynchronize(tree->forest->stream));
+    HIPCHK(hipDeviceSynchronize());
+    const uint32_t st = tree->forest->device_status;
+    if (st & STATUS_DOMAIN) fail(FMT_E_DOMAIN, "a point is NaN or outside the box");
+    if (st & STATUS_NONFINITE) fail(FMT_E_NUMERIC, "a non-finite coefficient was produced");
+  });
+}
+
+fmt_status fmt_tree_get_info(const fmt_tree* tree, fmt_tree_info* info) {
+  return guard([&] {
+    if (!tree || !info) fail(FMT_E_INVALID_ARG, "NULL argument");
+    fmt_tree* t = const_cast<fmt_tree*>(tree);
+    ensure_tree_nodes(t);
+    Forest& F = *t->forest;
+    std::memset(info, 0, sizeof(*info));
+    info->nodes = (int64_t)t->nodes.size();
+    info->n_points = F.probs[t->problem].n;
+    info->p = F.p;
+    info->L = F.L;
+    info->max_depth = F.D;
+    info->path = F.path;
+    int depth = 0, rd = 0;
+    for (uint32_t i : t->nodes) {
+      const int lv = (int)F.h_level[i];
+      info->per_level[lv] += 1;
+      depth = std::max(depth, lv);
+      if (F.h_flags[i] & FLAG_DEFLATED) ++rd;
+    }
+    info->depth = depth;
+    info->rank_deficient_nodes = rd;
+    info->device_bytes = (int64_t)F.device_bytes();
+  });
+}
+
+fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t* prefix, uint32_t* begin,
+                                 uint32_t* count, double* coeffs) {
+  return guard([&] {
+    if (!tree) fail(FMT_E_INVALID_ARG, "NULL tree");
+    fmt_tree* t = const_cast<fmt_tree*>(tree);
+    ensure_tree_nodes(t);
+    Forest& F = *t->forest;
+    const uint32_t off = F.probs[t->problem].prm.offset;
+    for (size_t j = 0; j < t->nodes.size(); ++j) {
+      const uint32_t i = t->nodes[j];
+      if (level) level[j] = (uint8_t)F.h_level[i];
+      if (prefix) prefix[j] = F.h_prefix[i];
+      if (begin) begin[j] = F.h_begin[i] - off;
+      if (count) count[j] = F.h_count[i];
+      if (coeffs) std::memcpy(coeffs + j * F.L, F.h_coef.data() + (size_t)i * F.L, sizeof(double) * F.L);
+    }
+  });
+}
+
+fmt_status fmt_tree_export_points(const fmt_tree* tree, uint32_t* keys, uint32_t* order, uint32_t* leaf,
+                                  double* residual) {
+  return guard([&] {
+    if (!tree) fail(FMT_E_INVALID_ARG, "NULL tree");
+    fmt_tree* t = const_cast<fmt_tree*>(tree);
+    ensure_tree_nodes(t);
+    Forest& F = *t->forest;
+    const ProblemInfo& P = F.probs[t->problem];
+    const uint32_t n = (uint32_t)P.n, off = P.prm.offset;
+    if (n == 0) return;
+    std::vector<uint32_t> sk(n), so(n);
+    std::vector<double> sr(n);
+    HIPCHK(hipStreamSynchronize(F.stream));
+    HIPCHK(hipMemcpy(sk.data(), F.skey.as<uint32_t>() + off, 4ull * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(so.data(), F.order.as<uint32_t>() + off, 4ull * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(sr.data(), F.resid.as<double>() + off, 8ull * n, hipMemcpyDeviceToHost));
+    const uint32_t kmask = 3 * F.D >= 32 ? 0xffffffffu : ((1u << (3 * F.D)) - 1u);
+    std::vector<uint32_t> sleaf(n, 0);
+    for (size_t j = 0; j < t->nodes.size(); ++j) {   // deeper nodes come later and overwrite
+      const uint32_t i = t->nodes[j];
+      const uint32_t b = F.h_begin[i] - off, c = F.h_count[i];
+      for (uint32_t q = b; q < b + c; ++q) sleaf[q] = (uint32_t)j;
+    }
+    for (uint32_t q = 0; q < n; ++q) {
+      const uint32_t inp = so[q] - off;
+      if (keys) keys[inp] = sk[q] & kmask;
+      if (order) order[q] = inp;
+      if (leaf) leaf[inp] = sleaf[q];
+      if (residual) residual[inp] = sr[q];
+    }
+  });
+}
+
+fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_t* level, const uint32_t* prefix,
+                           const double* coeffs, void* stream, fmt_tree** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!opts || !out || !level || !prefix || !coeffs) fail(FMT_E_INVALID_ARG, "NULL argument");
+    validate_opts(*opts);
+    if (nodes < 1 || nodes >= (1ll << 31)) fail(FMT_E_INVALID_ARG, "node count out of range");
+    hipStream_t s = (hipStream_t)stream;
+    auto F = std::make_shared<Forest>();
+    F->p = opts->p;
+    F->L = basis_size(opts->p);
+    F->D = opts->max_depth;
+    F->path = opts->path;
+    F->nprob = 1;
+    F->stream = s;
+    HIPCHK(hipGetDevice(&F->device));
+    const int L = F->L;
+    std::vector<int64_t> idx(nodes);
+    for (int64_t i = 0; i < nodes; ++i) {
+      idx[i] = i;
+      if (level[i] > F->D) fail(FMT_E_INVALID_ARG, "node level above max_depth");
+      if (level[i] < 10 && (prefix[i] >> (3 * level[i])) != 0) fail(FMT_E_INVALID_ARG, "prefix wider than its level");
+    }
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      return level[a] != level[b] ? level[a] < level[b] : prefix[a] < prefix[b];
+    });
+    if (level[idx[0]] != 0 || (nodes > 1 && level[idx[1]] == 0)) fail(FMT_E_INVALID_ARG, "exactly one root needed");
+    const uint32_t M = (uint32_t)nodes;
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> pos;
+    for (uint32_t j = 0; j < M; ++j) {
+      auto key = std::make_pair((uint32_t)level[idx[j]], prefix[idx[j]]);
+      if (pos.count(key)) fail(FMT_E_INVALID_ARG, "duplicate node");
+      pos[key] = j;
+    }
+    std::vector<uint32_t> hb(M, 0), hc(M, 0), hp(M), hl(M), hprob(M, 0), hpar(M), hfc(M, 0), hcm(M, 0), hf(M, 0);
+    std::vector<double> hcoef((size_t)M * L);
+    for (uint32_t j = 0; j < M; ++j) {
+      const int64_t i = idx[j];
+      hp[j] = prefix[i];
+      hl[j] = level[i];
+      std::memcpy(hcoef.data() + (size_t)j * L, coeffs + i * L, sizeof(double) * L);
+      if (hl[j] == 0) {
+        hpar[j] = j;
+        continue;
+      }
+      auto it = pos.find(std::make_pair(hl[j] - 1, hp[j] >> 3));
+      if (it == pos.end()) fail(FMT_E_INVALID_ARG, "a node's parent is missing");
+      const uint32_t par = it->second;
+      hpar[j] = par;
+      if (hcm[par] == 0) hfc[par] = j;
+      hcm[par] |= 1u << (hp[j] & 7u);
+    }
+    F->alloc_nodes(M);
+    F->nodes = M;
+    auto up = [&](DevBuf& b, const void* h, size_t bytes) {
+      HIPCHK(hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, s));
+    };
+    up(F->nb_begin, hb.data(), 4ull * M); up(F->nb_count, hc.data(), 4ull * M); up(F->nb_prefix, hp.data(), 4ull * M);
+    up(F->nb_level, hl.data(), 4ull * M); up(F->nb_problem, hprob.data(), 4ull * M);
+    up(F->nb_parent, hpar.data(), 4ull * M); up(F->nb_first_child, hfc.data(), 4ull * M);
+    up(F->nb_child_mask, hcm.data(), 4ull * M); up(F->nb_flags, hf.data(), 4ull * M);
+    up(F->nb_coef, hcoef.data(), 8ull * M * L);
+    ProblemParams prm = make_params(*opts, 0, 0);
+    DevBuf dprm(sizeof(ProblemParams));
+    up(dprm, &prm, sizeof(ProblemParams));
+    HIPCHK(launch_node_geo(F->table(), dprm.as<ProblemParams>(), M, s));
+    HIPCHK(hipStreamSynchronize(s));
+    F->probs.resize(1);
+    F->probs[0].prm = prm;
+    F->probs[0].root = 0;
+    F->probs[0].n = 0;
+    F->level_start.assign(1, 0);
+    fmt_tree* t = new fmt_tree();
+    t->forest = F;
+    t->problem = 0;
+    *out = t;
+  });
+}
+
+void fmt_tree_destroy(fmt_tree* tree) {
+  if (!tree) return;
+  (void)hipStreamSynchronize(tree->forest->stream);
+  delete tree;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Per-level kernels of the octree fit (Alg. 1 / Alg. 2) and the evaluator.
+#pragma once
+
+#include "fmt_common.h"
+
+namespace fmt {
+
+// Everything a level kernel needs.  Work items are (node, chunk) pairs: node k
+// of the level owns chunks [chunk_off[k], chunk_off[k+1]); chunk j of a node
+// covers its sorted points [begin + j*CHUNK, min(begin + count, begin + (j+1)*CHUNK)).
+struct LevelArgs {
+  NodeTable nt;
+  uint32_t node0;            // first node of the level in the table
+  uint32_t nnodes;           // nodes in the level
+  const uint32_t* chunk_off; // nnodes + 1 entries
+  uint32_t nchunks;
+  const void* px;            // key-sorted coordinates (input dtype)
+  const void* py;
+  const void* pz;
+  double* r;                 // key-sorted residual
+  const uint32_t* skey;      // key-sorted keys
+  int level;                 // depth of this level
+  int D;                     // maximum depth
+  double tol;                // split tolerance
+};
+
+struct EvalTree {
+  NodeTable nt;
+  uint32_t root;
+  int D;
+  ProblemParams prm;
+};
+
+// Doubles of one chunk's partial Gram (upper-triangular 16x16 blocks of the
+// augmented (L+1) x (L+1) matrix [Lambda | r]^T [Lambda | r]).
+size_t gram_partial_doubles(int p);
+// Doubles of one node's stored factor (packed lower Cholesky factor, pivots,
+// equilibration scales).
+size_t factor_doubles(int p);
+
+hipError_t launch_node_geo(const NodeTable& nt, const ProblemParams* prm, uint32_t n, hipStream_t s);
+hipError_t launch_roots(const NodeTable& nt, const ProblemParams* prm, int nprob, hipStream_t s);
+hipError_t launch_gram(int p, int path, int dtype, const LevelArgs& a, double* partial, hipStream_t s);
+hipError_t launch_solve(int p, const LevelArgs& a, const double* partial, double* fac, hipStream_t s);
+hipError_t launch_refine_sweep(int p, int dtype, const LevelArgs& a, double* part_b, hipStream_t s);
+hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s);
+hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s);
+hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
+                           uint32_t* nact, hipStream_t s);
+hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
+                       uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, hipStream_t s);
+hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
+hipError_t launch_eval(int p, int dtype, const EvalTree& t, const void* qx, const void* qy, const void* qz,
+                       const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out, hipStream_t s);
+
+// Device helpers shared by the level kernels ---------------------------------
+
+// Node k of a level owning chunk g: chunk_off[k] <= g < chunk_off[k+1].
+__device__ __forceinline__ uint32_t chunk_node(const uint32_t* chunk_off, uint32_t nnodes, uint32_t g) {
+  uint32_t lo = 0, hi = nnodes - 1;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi + 1) >> 1;
+    if (chunk_off[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_point(const void* px, const void* py, const void* pz, uint32_t i, double& x,
+                                           double& y, double& z) {
+  x = (double)((const T*)px)[i];
+  y = (double)((const T*)py)[i];
+  z = (double)((const T*)pz)[i];
+}
+
+}  // namespace fmt
+
+// Instantiate F<P> for the runtime order p (0..FMT_MAX_P).
+#define FMT_DISPATCH_P(p, F, ...)                  \
+  switch (p) {                                      \
+    case 0: return F<0>(__VA_ARGS__);               \
+    case 1: return F<1>(__VA_ARGS__);               \
+    case 2: return F<2>(__VA_ARGS__);               \
+    case 3: return F<3>(__VA_ARGS__);               \
+    case 4: return F<4>(__VA_ARGS__);               \
+    case 5: return F<5>(__VA_ARGS__);               \
+    case 6: return F<6>(__VA_ARGS__);               \
+    case 7: return F<7>(__VA_ARGS__);               \
+    case 8: return F<8>(__VA_ARGS__);               \
+    default: return hipErrorInvalidValue;           \
+  }

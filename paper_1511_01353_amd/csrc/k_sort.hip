@@ -1,0 +1,321 @@
+// Morton keys, stable LSD radix sort of (key, index) pairs, and the gather of
+// points into key order.
+//
+// Keys replace the per-node octant ordering of Alg. 1: sorting once by the
+// interleaved cell bits puts the points of every octree node, at every
+// depth, in one contiguous range, children in octant order.
+#include "k_sort.h"
+
+namespace fmt {
+
+__device__ __forceinline__ uint32_t find_problem(const ProblemParams* prm, int nprob, uint32_t g) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prm[mid].offset <= g) lo = mid; else hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_keygen(const PtrSet* ptrs, const ProblemParams* prm,
+                                                int nprob, int depth, uint32_t total,
+                                                uint32_t* keys, uint32_t* status) {
+  uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  uint32_t k = nprob == 1 ? 0u : find_problem(prm, nprob, g);
+  const ProblemParams& P = prm[k];
+  uint32_t i = g - P.offset;
+  const T* X = (const T*)ptrs[k].x;
+  const T* Y = (const T*)ptrs[k].y;
+  const T* Z = (const T*)ptrs[k].z;
+  double x = (double)X[i], y = (double)Y[i], z = (double)Z[i];
+  bool bad = false;
+  // domain: finite and inside the closed box
+  if (!(x >= P.lo[0] && x <= P.hi[0] && y >= P.lo[1] && y <= P.hi[1] && z >= P.lo[2] && z <= P.hi[2]))
+    bad = true;
+  uint32_t cmax = (1u << depth) - 1u;
+  uint32_t qx = cell_of(x, P.lo[0], P.qscale[0], cmax, &bad);
+  uint32_t qy = cell_of(y, P.lo[1], P.qscale[1], cmax, &bad);
+  uint32_t qz = cell_of(z, P.lo[2], P.qscale[2], cmax, &bad);
+  uint32_t key = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+  if (nprob > 1) key |= k << (3 * depth);
+  keys[g] = key;
+  if (bad) atomicOr(status, STATUS_DOMAIN);
+}
+
+// Query keys for evaluation of one tree: same cell rule, no domain check
+// (outside queries follow the clamped path).
+template <typename T>
+__global__ void __launch_bounds__(256) k_query_keys(const T* qx, const T* qy, const T* qz, uint32_t nq,
+                                                    ProblemParams P, int depth, uint32_t* keys) {
+  uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nq) return;
+  bool bad = false;
+  uint32_t cmax = (1u << depth) - 1u;
+  uint32_t a = cell_of((double)qx[g], P.lo[0], P.qscale[0], cmax, &bad);
+  uint32_t b = cell_of((double)qy[g], P.lo[1], P.qscale[1], cmax, &bad);
+  uint32_t c = cell_of((double)qz[g], P.lo[2], P.qscale[2], cmax, &bad);
+  keys[g] = (spread3(a) << 2) | (spread3(b) << 1) | spread3(c);
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort, one pass per RADIX_BITS digit.
+// Tile t of SORT_TILE keys is handled by block t; inside the tile, wave w
+// owns the contiguous quarter [w*TILE/4, (w+1)*TILE/4) and walks it in rounds
+// of 64 keys.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n,
+                                                             int shift, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[RADIX];
+  for (int i = threadIdx.x; i < RADIX; i += SORT_THREADS) h[i] = 0;
+  __syncthreads();
+  uint32_t base = blockIdx.x * SORT_TILE;
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    uint32_t i = base + j * SORT_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) hist[d * gridDim.x + blockIdx.x] = h[d];
+}
+
+// Exclusive scan of m words by one workgroup of 1024 threads (each thread
+// owns a contiguous segment).  Writes the total to *total if non-null.
+__global__ void __launch_bounds__(1024) k_scan_1wg(uint32_t* __restrict__ data, uint32_t m,
+                                                   uint32_t* __restrict__ total) {
+  __shared__ uint32_t s[1024];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t seg = (m + 1023u) / 1024u;
+  const uint32_t b = min(m, tid * seg), e = min(m, b + seg);
+  uint32_t sum = 0;
+  for (uint32_t i = b; i < e; ++i) sum += data[i];
+  s[tid] = sum;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    uint32_t v = tid >= off ? s[tid - off] : 0u;
+    __syncthreads();
+    s[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = s[tid] - sum;
+  for (uint32_t i = b; i < e; ++i) {
+    uint32_t v = data[i];
+    data[i] = run;
+    run += v;
+  }
+  if (tid == 1023 && total) *total = s[1023];
+}
+
+template <bool FIRST>
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                                const uint32_t* __restrict__ vin,
+                                                                uint32_t* __restrict__ kout,
+                                                                uint32_t* __restrict__ vout, uint32_t n,
+                                                                int shift,
+                                                                const uint32_t* __restrict__ offs) {
+  constexpr int WAVES = SORT_THREADS / 64;
+  constexpr int QUARTER = SORT_TILE / WAVES;
+  constexpr int ROUNDS = QUARTER / 64;
+  __shared__ uint32_t wcnt[WAVES][RADIX];
+  __shared__ uint32_t lofs[RADIX];
+  __shared__ uint32_t goff[RADIX];
+  __shared__ uint32_t sk[SORT_TILE];
+  __shared__ uint32_t sv[SORT_TILE];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < WAVES * RADIX; i += SORT_THREADS) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+
+  const uint64_t below_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t base = blockIdx.x * SORT_TILE + w * QUARTER;
+  uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
+#pragma unroll
+  for (int j = 0; j < ROUNDS; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t d = (k >> shift) & (RADIX - 1);
+    // lanes of this wave holding the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RADIX_BITS; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & below_mask);
+    const uint32_t c = wcnt[w][d];
+    rank[j] = c + before;
+    // the lowest lane of each digit group advances the wave's running count;
+    // every lane of the group read the old value in the load above
+    __builtin_amdgcn_wave_barrier();
+    if (valid && before == 0) wcnt[w][d] = c + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    key[j] = k;
+    val[j] = FIRST ? i : (valid ? vin[i] : 0u);
+  }
+  __syncthreads();
+  // per digit: wave bases and the tile-local digit start
+  if (tid < RADIX) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) {
+      uint32_t c = wcnt[ww][tid];
+      wcnt[ww][tid] = run;
+      run += c;
+    }
+    lofs[tid] = run;   // digit total for now
+    goff[tid] = offs[tid * gridDim.x + blockIdx.x];
+  }
+  __syncthreads();
+  // exclusive scan of the 256 digit totals (Hillis-Steele in place)
+  uint32_t mine = tid < RADIX ? lofs[tid] : 0u;
+  for (int off = 1; off < RADIX; off <<= 1) {
+    uint32_t v = (tid < RADIX && tid >= off) ? lofs[tid - off] : 0u;
+    __syncthreads();
+    if (tid < RADIX) lofs[tid] += v;
+    __syncthreads();
+  }
+  if (tid < RADIX) lofs[tid] -= mine;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ROUNDS; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    if (i < n) {
+      const uint32_t d = (key[j] >> shift) & (RADIX - 1);
+      const uint32_t pos = lofs[d] + wcnt[w][d] + rank[j];
+      sk[pos] = key[j];
+      sv[pos] = val[j];
+    }
+  }
+  __syncthreads();
+  const uint32_t tile0 = blockIdx.x * SORT_TILE;
+  const uint32_t tn = min((uint32_t)SORT_TILE, n - tile0);
+  for (uint32_t i = tid; i < tn; i += SORT_THREADS) {
+    const uint32_t k = sk[i];
+    const uint32_t d = (k >> shift) & (RADIX - 1);
+    const uint32_t o = goff[d] + (i - lofs[d]);
+    kout[o] = k;
+    vout[o] = sv[i];
+  }
+}
+
+// Gather points into key order; the residual starts as the sampled values.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(const PtrSet* ptrs, const ProblemParams* prm, int nprob,
+                                                const uint32_t* __restrict__ order, uint32_t total,
+                                                T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
+                                                double* __restrict__ r) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  uint32_t g = order[i];
+  uint32_t k = nprob == 1 ? 0u : find_problem(prm, nprob, g);
+  uint32_t j = g - prm[k].offset;
+  px[i] = ((const T*)ptrs[k].x)[j];
+  py[i] = ((const T*)ptrs[k].y)[j];
+  pz[i] = ((const T*)ptrs[k].z)[j];
+  r[i] = (double)((const T*)ptrs[k].f)[j];
+}
+
+// Permute query coordinates into key order (for coherent evaluation).
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute3(const T* __restrict__ x, const T* __restrict__ y,
+                                                  const T* __restrict__ z, const uint32_t* __restrict__ order,
+                                                  uint32_t n, T* __restrict__ ox, T* __restrict__ oy,
+                                                  T* __restrict__ oz) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t g = order[i];
+  ox[i] = x[g];
+  oy[i] = y[g];
+  oz[i] = z[g];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_keygen(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, int depth,
+                         uint32_t total, uint32_t* keys, uint32_t* status, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  if (dtype == FMT_F32)
+    hipLaunchKernelGGL(k_keygen<float>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, depth,
+                       total, keys, status);
+  else
+    hipLaunchKernelGGL(k_keygen<double>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, depth,
+                       total, keys, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_keys(int dtype, const void* qx, const void* qy, const void* qz, uint32_t nq,
+                             const ProblemParams& P, int depth, uint32_t* keys, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  if (dtype == FMT_F32)
+    hipLaunchKernelGGL(k_query_keys<float>, dim3(blocks_for(nq, 256)), dim3(256), 0, s, (const float*)qx,
+                       (const float*)qy, (const float*)qz, nq, P, depth, keys);
+  else
+    hipLaunchKernelGGL(k_query_keys<double>, dim3(blocks_for(nq, 256)), dim3(256), 0, s, (const double*)qx,
+                       (const double*)qy, (const double*)qz, nq, P, depth, keys);
+  return hipGetLastError();
+}
+
+size_t radix_sort_scratch_words(uint32_t n) {
+  uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+  return (size_t)RADIX * tiles + 16;
+}
+
+hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
+                      int bits, bool vals_are_iota, uint32_t* scratch, hipStream_t s, bool* result_in_alt) {
+  *result_in_alt = false;
+  if (n == 0) return hipSuccess;
+  const uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+  uint32_t* hist = scratch;
+  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
+  if (passes < 1) passes = 1;   // at least one pass so that the index array is written
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * RADIX_BITS;
+    hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
+    hipLaunchKernelGGL(k_scan_1wg, dim3(1), dim3(1024), 0, s, hist, (uint32_t)(RADIX * tiles),
+                       (uint32_t*)nullptr);
+    if (p == 0 && vals_are_iota)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
+                         hist);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
+                         hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint32_t* t = ki; ki = ko; ko = t;
+    t = vi; vi = vo; vo = t;
+    *result_in_alt = !*result_in_alt;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_gather(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, const uint32_t* order,
+                         uint32_t total, void* px, void* py, void* pz, double* r, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  if (dtype == FMT_F32)
+    hipLaunchKernelGGL(k_gather<float>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, order,
+                       total, (float*)px, (float*)py, (float*)pz, r);
+  else
+    hipLaunchKernelGGL(k_gather<double>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, order,
+                       total, (double*)px, (double*)py, (double*)pz, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute3(int dtype, const void* x, const void* y, const void* z, const uint32_t* order,
+                           uint32_t n, void* ox, void* oy, void* oz, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == FMT_F32)
+    hipLaunchKernelGGL(k_permute3<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const float*)x,
+                       (const float*)y, (const float*)z, order, n, (float*)ox, (float*)oy, (float*)oz);
+  else
+    hipLaunchKernelGGL(k_permute3<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const double*)x,
+                       (const double*)y, (const double*)z, order, n, (double*)ox, (double*)oy, (double*)oz);
+  return hipGetLastError();
+}
+
+}  // namespace fmt

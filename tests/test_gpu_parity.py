@@ -1,0 +1,236 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Bars:
+  * keys, point order, point-to-leaf assignment and tree topology: bit-exact;
+  * float64 path: fitted values and evaluations within RMS 1e-10 of the oracle;
+  * mixed path (float32 MFMA Gram, float64 solve + refinement): fitted values
+    within RMS 1e-6 relative to RMS(f) of the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+FP64_RMS = 1e-10
+MIXED_REL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def fmt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1511_01353_amd as m
+    m.load_library()
+    return m
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_fit(fmt, pr, path=0, refine=1, box=None):
+    kw = dict(p=pr.p, tol=pr.tol, max_depth=pr.max_depth, path=path, refine_steps=refine)
+    if box is not None:
+        kw["box_lo"], kw["box_hi"] = box
+    o = fmt.fmt_default_opts(**kw)
+    return fmt.fmt_fit(o, dev(pr.x), dev(pr.y), dev(pr.z), dev(pr.f))
+
+
+def oracle_fit(pr, box=None):
+    lo, hi = box if box is not None else ((0, 0, 0), (1, 1, 1))
+    return oracle.fit(pr.x, pr.y, pr.z, pr.f, pr.p, pr.tol, pr.max_depth, lo, hi)
+
+
+def compare_topology(tr, ot):
+    nodes = tr.export_nodes()
+    pts = tr.export_points()
+    assert len(nodes["level"]) == ot.nodes, (len(nodes["level"]), ot.nodes)
+    np.testing.assert_array_equal(nodes["level"].astype(np.int64), ot.level)
+    np.testing.assert_array_equal(nodes["prefix"].astype(np.int64), ot.prefix)
+    np.testing.assert_array_equal(nodes["begin"].astype(np.int64), ot.begin)
+    np.testing.assert_array_equal(nodes["count"].astype(np.int64), ot.count)
+    np.testing.assert_array_equal(pts["keys"].astype(np.int64), ot.keys)
+    np.testing.assert_array_equal(pts["order"].astype(np.int64), ot.order)
+    np.testing.assert_array_equal(pts["leaf"].astype(np.int64), ot.leaf)
+    return nodes, pts
+
+
+def fitted_rms(pr, pts, ot):
+    f = pr.f.astype(np.float64)
+    return oracle.rms((f - pts["residual"]) - (f - ot.residual))
+
+
+def print_case(name, pr):
+    print(f"[case] {name} n={pr.n} p={pr.p} tol={pr.tol} D={pr.max_depth} dtype={pr.dtype}", flush=True)
+
+
+@pytest.mark.parametrize("n,p,depth,tol,seed,dtype", [
+    (4096, 4, 3, 0.0, 1000, np.float64),       # the small configuration: uniform depth 3
+    (20000, 3, 4, 1e-6, 11, np.float64),
+    (30001, 6, 3, 1e-8, 12, np.float32),       # ragged: not a multiple of any tile
+    (9000, 2, 5, 1e-5, 13, np.float32),
+    (5000, 0, 3, 0.0, 14, np.float64),
+    (3000, 5, 2, 1e-7, 15, np.float64),
+])
+def test_fp64_path_matches_oracle(fmt, n, p, depth, tol, seed, dtype):
+    pr = synthetic.small_problem(n, p, seed, tol=tol, depth=depth, dtype=dtype, nq=5000)
+    print_case("fp64", pr)
+    tr = run_fit(fmt, pr)
+    ot = oracle_fit(pr)
+    nodes, pts = compare_topology(tr, ot)
+    assert fitted_rms(pr, pts, ot) <= FP64_RMS
+    ok = ~ot.rank_deficient
+    scale = np.maximum(np.abs(ot.coeffs[ok]), 1.0)
+    assert np.max(np.abs(nodes["coeffs"][ok] - ot.coeffs[ok]) / scale) < 1e-7
+    for sort in (0, 1):
+        got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz), sort_queries=sort).cpu().numpy()
+        want = oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)
+        assert oracle.rms(got - want) <= FP64_RMS, sort
+    tr.close()
+
+
+def test_config1_workload(fmt):
+    pr = synthetic.config1()
+    print_case("config1", pr)
+    tr = run_fit(fmt, pr)
+    ot = oracle_fit(pr)
+    compare_topology(tr, ot)
+    info = tr.info()
+    assert info.nodes == 73 and info.depth == 2
+    got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
+    assert oracle.rms(got - oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)) <= FP64_RMS
+
+
+@pytest.mark.parametrize("seed,p", [(21, 4), (22, 6)])
+def test_mixed_path_matches_oracle(fmt, seed, p):
+    pr = synthetic.small_problem(40000, p, seed, tol=1e-7, depth=4, dtype=np.float32, nq=4000)
+    print_case("mixed", pr)
+    tr = run_fit(fmt, pr, path=1, refine=2)
+    ot = oracle_fit(pr)
+    nodes, pts = compare_topology(tr, ot)
+    ref = oracle.rms(pr.f.astype(np.float64))
+    assert fitted_rms(pr, pts, ot) <= MIXED_REL * ref
+    got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
+    assert oracle.rms(got - oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)) <= MIXED_REL * ref
+
+
+def test_clustered_points_on_faces(fmt):
+    pr = synthetic.small_problem(30000, 4, 31, tol=1e-7, depth=5, dtype=np.float32, clustered=True, nq=3000)
+    print_case("clustered", pr)
+    assert np.any(pr.x == 0.0) or np.any(pr.x == 1.0)
+    tr = run_fit(fmt, pr)
+    ot = oracle_fit(pr)
+    _, pts = compare_topology(tr, ot)
+    assert fitted_rms(pr, pts, ot) <= FP64_RMS
+
+
+def test_points_on_split_planes_and_faces(fmt):
+    rng = np.random.default_rng(41)
+    k = rng.integers(0, 17, size=(3, 3000))
+    x, y, z = (k / 16.0).astype(np.float64)
+    f = np.cos(3 * x) * np.sin(2 * y) + z
+    pr = synthetic.Problem(x=x, y=y, z=z, f=f, p=2, tol=1e-9, max_depth=4)
+    print_case("planes", pr)
+    tr = run_fit(fmt, pr)
+    ot = oracle_fit(pr)
+    _, pts = compare_topology(tr, ot)
+    assert fitted_rms(pr, pts, ot) <= FP64_RMS
+
+
+def test_general_box(fmt):
+    rng = np.random.default_rng(43)
+    lo, hi = (-1.0, -2.0, 0.5), (1.0, 3.0, 0.75)
+    x = rng.uniform(lo[0], hi[0], 8000)
+    y = rng.uniform(lo[1], hi[1], 8000)
+    z = rng.uniform(lo[2], hi[2], 8000)
+    f = np.exp(-x * x) * y + 4 * z
+    pr = synthetic.Problem(x=x, y=y, z=z, f=f, p=3, tol=1e-9, max_depth=3)
+    tr = run_fit(fmt, pr, box=(lo, hi))
+    ot = oracle_fit(pr, box=(lo, hi))
+    _, pts = compare_topology(tr, ot)
+    assert fitted_rms(pr, pts, ot) <= FP64_RMS
+
+
+def test_interpolation_at_n_equals_L(fmt):
+    p = 3
+    L = oracle.basis_size(p)
+    rng = np.random.default_rng(47)
+    x, y, z = rng.uniform(0, 1, (3, L))
+    f = np.cos(5 * x) + y * z
+    pr = synthetic.Problem(x=x, y=y, z=z, f=f, p=p, tol=0.0, max_depth=3)
+    tr = run_fit(fmt, pr)
+    ot = oracle_fit(pr)
+    _, pts = compare_topology(tr, ot)
+    assert oracle.max_abs(pts["residual"]) < 1e-8
+
+
+def test_polynomial_reproduced_and_root_only(fmt):
+    rng = np.random.default_rng(53)
+    x, y, z = rng.uniform(0, 1, (3, 20000))
+    f = 1 + x - 2 * y * z + 0.5 * x ** 3 * y - z ** 4 + x * y * z * (x + y)
+    pr = synthetic.Problem(x=x, y=y, z=z, f=f, p=5, tol=1e-11, max_depth=4)
+    tr = run_fit(fmt, pr)
+    assert tr.info().nodes == 1
+    pts = tr.export_points()
+    assert oracle.rms(pts["residual"]) < 1e-13
+
+
+def test_errors(fmt):
+    x, y, z = synthetic.uniform_points(200, 1)
+    f = x.copy()
+    o = fmt.fmt_default_opts(p=6)   # calL = 84
+    with pytest.raises(fmt.FmtError) as e:
+        fmt.fmt_fit(o, dev(x[:83]), dev(y[:83]), dev(z[:83]), dev(f[:83]))
+    assert e.value.status == fmt.FMT_E_UNDERDETERMINED
+    x2 = x.copy()
+    x2[5] = 1.25
+    with pytest.raises(fmt.FmtError) as e:
+        fmt.fmt_fit(fmt.fmt_default_opts(p=2), dev(x2), dev(y), dev(z), dev(f))
+    assert e.value.status == fmt.FMT_E_DOMAIN
+    x2[5] = np.nan
+    with pytest.raises(fmt.FmtError) as e:
+        fmt.fmt_fit(fmt.fmt_default_opts(p=2), dev(x2), dev(y), dev(z), dev(f))
+    assert e.value.status == fmt.FMT_E_DOMAIN
+
+
+def test_deterministic(fmt):
+    pr = synthetic.small_problem(50000, 4, 61, tol=1e-7, depth=4, dtype=np.float32)
+    a = run_fit(fmt, pr).export_points()["residual"]
+    b = run_fit(fmt, pr).export_points()["residual"]
+    np.testing.assert_array_equal(a, b)
+
+
+def test_export_import_roundtrip(fmt):
+    pr = synthetic.small_problem(20000, 4, 67, tol=1e-7, depth=4, dtype=np.float64, nq=3000)
+    tr = run_fit(fmt, pr)
+    nodes = tr.export_nodes()
+    o = fmt.fmt_default_opts(p=pr.p, max_depth=pr.max_depth)
+    perm = np.random.default_rng(1).permutation(len(nodes["level"]))
+    t2 = fmt.fmt_tree_import(o, nodes["level"][perm], nodes["prefix"][perm], nodes["coeffs"][perm])
+    a = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz), sort_queries=0).cpu().numpy()
+    b = t2.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz), sort_queries=0).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+
+
+def test_batch_equals_single_fits(fmt):
+    probs = synthetic.config3(seed0=3000, count=6, nlo=2e3, nhi=3e4, nq=500)
+    opts = [fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth) for pr in probs]
+    trees = fmt.fmt_fit_batch(opts, [dev(p.x) for p in probs], [dev(p.y) for p in probs],
+                              [dev(p.z) for p in probs], [dev(p.f) for p in probs])
+    for pr, tb in zip(probs, trees):
+        ts = run_fit(fmt, pr)
+        a, b = tb.export_points(), ts.export_points()
+        np.testing.assert_array_equal(a["keys"], b["keys"])
+        np.testing.assert_array_equal(a["leaf"], b["leaf"])
+        np.testing.assert_array_equal(a["residual"], b["residual"])
+        na, nb = tb.export_nodes(), ts.export_nodes()
+        np.testing.assert_array_equal(na["coeffs"], nb["coeffs"])
+        ot = oracle_fit(pr)
+        compare_topology(tb, ot)
+        qa = tb.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
+        assert oracle.rms(qa - oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)) <= FP64_RMS
