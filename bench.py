@@ -1,0 +1,260 @@
+"""Benchmark of the octree-scoped free-mesh interpolant on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input: fit N points
+(keys, sort, gather, per-level Gram / solve / refinement / residual /
+topology) and evaluate the fresh tree at Nq queries.  Default workload: N = 2^20
+uniform points in the unit cube (float32 storage), values from a seeded sum of
+four anisotropic Gaussian bumps, p = 6 (calL = 84), depth <= 6, tol 1e-8,
+Nq = 2^22 uniform queries.  Inputs are device-resident before timing starts.
+
+Prints one JSON line (rank 0).  `value` is fit points/s of the headline path;
+eval points/s, both paths' errors against the true function, step latency
+percentiles, the roofline of the dominant kernel and the CPU oracle baseline
+ride along in the same line.
+"""
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+
+def gram_flops_per_point(L: int) -> float:
+    # symmetric Gram L(L+1) + right-hand side 2L + basis generation L
+    return L * (L + 1) + 2 * L + L
+
+
+def basis_count(p: int) -> int:
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def moment_flops_per_point(p: int) -> float:
+    # one multiply-add per power moment (|gamma| <= 2p), per r-weighted moment
+    # (|alpha| <= p) and for r^2, one product u^a v^b per run, and the powers
+    nm, nb = basis_count(2 * p), basis_count(p)
+    runs = (2 * p + 1) * (2 * p + 2) // 2 + (p + 1) * (p + 2) // 2
+    return 2.0 * (nm + nb + 1) + runs + 3 * 2 * p
+
+
+def refine_flops_per_point(p: int) -> float:
+    # r' = r - Lambda F (about 2L) and the r'-weighted moments (2L + runs + powers)
+    L = basis_count(p)
+    return 2.0 * L + 2.0 * L + (p + 1) * (p + 2) // 2 + 3 * 2 * p
+
+
+def solve_flops_per_node(L: int) -> float:
+    # Cholesky L^3/3 + forward and back substitution 2L^2
+    return L ** 3 / 3.0 + 2.0 * L * L
+
+
+def eval_flops_per_query_node(L: int) -> float:
+    return 2 * L + L
+
+
+def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, steps: int, key_passes: int):
+    """Achieved rate of each kernel class over the timed steps: algorithmic work
+    (flops or bytes per unit times the units the launches covered) divided by
+    the summed launch durations measured with HIP events."""
+    out = {}
+    def add(name, bound, per_unit, unit, peak):
+        st = kern.get(name)
+        if not st or st["ms_per_step"] <= 0:
+            return
+        sec = st["ms_per_step"] * steps / 1e3
+        work = st["units"] * per_unit
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        ach = work / sec / scale
+        out[name] = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak,
+                         avg_launch_ms=st["avg_launch_ms"], work_per_unit=per_unit,
+                         units_per_step=st["units"] / steps)
+    if path == "mixed":
+        add("gram", "mfma", gram_flops_per_point(L), "TFLOP/s", PEAK_TFLOPS["fp32"])
+    else:
+        add("gram", "alu", moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("solve", "alu", solve_flops_per_node(L), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("refine_solve", "alu", 2.0 * L * L, "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("refine_sweep", "alu", refine_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    # residual: coordinates + residual read, residual written, key read
+    add("residual", "hbm", 3 * coord_bytes + 8 + 8 + 4, "GB/s", PEAK_HBM_GBS)
+    # sort: per pass read and write key and index
+    add("sort", "hbm", 16.0 * key_passes, "GB/s", PEAK_HBM_GBS)
+    add("eval_sort", "hbm", 16.0 * key_passes, "GB/s", PEAK_HBM_GBS)
+    add("gather", "hbm", 4 + 3 * coord_bytes + coord_bytes + 3 * coord_bytes + 8, "GB/s", PEAK_HBM_GBS)
+    return out
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--path", choices=["fp64", "mixed"], default="fp64", help="headline path")
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--nq", type=int, default=1 << 22)
+    ap.add_argument("--sort-queries", type=int, default=-1)
+    ap.add_argument("--mixed-refine", type=int, default=3)
+    ap.add_argument("--fp64-refine", type=int, default=1)
+    ap.add_argument("--no-compare", action="store_true", help="time only the headline path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 17)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus N with N > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1511_01353_amd as fmt
+    import synthetic
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    fmt.load_library()
+    torch.cuda.set_device(0)
+    pr = synthetic.config2(n=args.n, nq=args.nq)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    X, Y, Z, Fv = dev(pr.x), dev(pr.y), dev(pr.z), dev(pr.f)
+    QX, QY, QZ = dev(pr.qx), dev(pr.qy), dev(pr.qz)
+    out = torch.empty(args.nq, dtype=torch.float64, device="cuda")
+    L = (pr.p + 1) * (pr.p + 2) * (pr.p + 3) // 6
+    paths = [args.path] if args.no_compare else [args.path] + [p for p in ("fp64", "mixed") if p != args.path]
+    results = {}
+    for path in paths:
+        opts = fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth,
+                                    path=fmt.FMT_PATH_MIXED if path == "mixed" else fmt.FMT_PATH_FP64,
+                                    refine_steps=args.mixed_refine if path == "mixed" else args.fp64_refine)
+
+        def step():
+            t0 = time.perf_counter()
+            tree = fmt.fmt_fit(opts, X, Y, Z, Fv)          # returns with the tree complete
+            t1 = time.perf_counter()
+            tree.eval(QX, QY, QZ, out=out, sort_queries=args.sort_queries)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            return tree, t1 - t0, t2 - t1
+
+        for _ in range(args.warmup):
+            tree, _, _ = step()
+            tree.close()
+        timed = path == args.path
+        fmt.fmt_profile_reset()
+        fmt.fmt_profile_enable(True)
+        torch.cuda.synchronize()
+        fit_t, eval_t = [], []
+        T0 = time.perf_counter()
+        for _ in range(args.steps):
+            tree, a, b = step()
+            fit_t.append(a)
+            eval_t.append(b)
+            last = tree
+        torch.cuda.synchronize()
+        T1 = time.perf_counter()
+        fmt.fmt_profile_enable(False)
+        prof = fmt.fmt_profile_read()
+        info = last.info()
+        fq = out.cpu().numpy()
+        e_rms = float(np.sqrt(np.mean((fq - pr.qf_true) ** 2)))
+        e_inf = float(np.max(np.abs(fq - pr.qf_true)))
+        last.close()
+        results[path] = dict(
+            fit_pts_per_s=args.n * len(fit_t) / sum(fit_t),
+            eval_pts_per_s=args.nq * len(eval_t) / sum(eval_t),
+            fit_ms_p50=1e3 * statistics.median(fit_t),
+            fit_ms_p99=1e3 * float(np.percentile(fit_t, 99)),
+            eval_ms_p50=1e3 * statistics.median(eval_t),
+            eval_ms_p99=1e3 * float(np.percentile(eval_t, 99)),
+            step_ms=1e3 * (T1 - T0) / args.steps,
+            E_rms=e_rms, E_inf=e_inf, nodes=int(info.nodes),
+            per_level=[int(info.per_level[i]) for i in range(info.depth + 1)],
+            kernels={k: dict(launches=v[0], ms_per_step=v[1] / args.steps,
+                             avg_launch_ms=(v[1] / v[0] if v[0] else 0.0), units=v[2])
+                     for k, v in prof.items() if v[0]},
+        )
+        if timed:
+            headline = results[path]
+            headline["wall_s"] = T1 - T0
+
+    h = results[args.path]
+    key_passes = max(1, (3 * pr.max_depth + 7) // 8)
+    roofs = kernel_rooflines(h["kernels"], pr.p, L, args.path, pr.x.dtype.itemsize, args.steps, key_passes)
+    # the dominant kernel of the headline path's step
+    dom = max(h["kernels"].items(), key=lambda kv: kv[1]["ms_per_step"])[0]
+    roof = dict(kernel=dom, **roofs[dom]) if dom in roofs else dict(kernel=dom, bound=None, achieved=None,
+                                                                    peak=None, unit=None, frac=None)
+    roof["traffic"] = None
+    gram_roof = roofs.get("gram")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(pr, args.cpu_sample)
+
+    cmp = None
+    if "fp64" in results and "mixed" in results:
+        cmp = dict(E_rms_ratio_minus_1=results["mixed"]["E_rms"] / results["fp64"]["E_rms"] - 1.0)
+    line = {
+        "metric": "fit pts/s & eval pts/s at fixed RMS err, mixed vs FP64 GPU; p50/p99 latency",
+        "value": h["fit_pts_per_s"],
+        "unit": "fit points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["step_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.path == "fp64" else "f32-mfma+f64",
+        "data": "synthetic (seeded uniform points, 4-bump anisotropic Gaussian values)",
+        "config": {"workload": "single large fit + eval: N=2^20 uniform fp32 points in [0,1]^3, 4 Gaussian bumps, "
+                               "p=6 (L=84), depth<=6, tol=1e-8; eval 2^22 queries",
+                   "n": args.n, "nq": args.nq, "p": pr.p, "max_depth": pr.max_depth, "tol": pr.tol,
+                   "path": args.path},
+        "eval_pts_per_s": h["eval_pts_per_s"],
+        "latency_ms": {"fit_p50": h["fit_ms_p50"], "fit_p99": h["fit_ms_p99"], "eval_p50": h["eval_ms_p50"],
+                       "eval_p99": h["eval_ms_p99"]},
+        "roofline": roof,
+        "rooflines": roofs,
+        "paths": {k: {kk: vv for kk, vv in v.items() if kk != "kernels"} for k, v in results.items()},
+        "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in st.items()}
+                    for k, st in h["kernels"].items()},
+        "mixed_vs_fp64": cmp,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def cpu_baseline(pr, sample: int):
+    """The FP64 oracle on the first `sample` points of the same workload (host cores)."""
+    import numpy as np
+
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    n = min(sample, pr.n)
+    t0 = time.perf_counter()
+    oracle.fit(pr.x[:n], pr.y[:n], pr.z[:n], pr.f[:n], pr.p, pr.tol, pr.max_depth)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "fit points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} points of the same workload (p={pr.p}, depth<={pr.max_depth}, tol={pr.tol}); "
+                      f"{dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -61,13 +61,22 @@ typedef enum {
 typedef enum { FMT_F32 = 0, FMT_F64 = 1 } fmt_dtype;
 
 typedef enum {
-  /* every step in float64: Gram on float64 MFMA, Cholesky, refinement */
+  /* every step in float64: normal equations (power moments on the vector
+     ALUs, or the Gram on float64 MFMA), Cholesky, refinement */
   FMT_PATH_FP64 = 0,
   /* Gram of the monomials on float32 MFMA (float32 accumulation within a
      chunk of points, chunks summed in float64); float64 Cholesky; float64
      refinement sweeps (residual, Lambda^T r) recover float64 accuracy */
   FMT_PATH_MIXED = 1
 } fmt_path;
+
+typedef enum {
+  /* power moments M_gamma = sum u^gamma (|gamma| <= 2p) accumulated on the
+     float64 vector ALUs; Gram entries are M_{alpha+beta} / (alpha! beta!) */
+  FMT_GRAM_MOMENTS = 0,
+  /* the Gram [Lambda|r]^T [Lambda|r] formed on float64 MFMA */
+  FMT_GRAM_MFMA = 1
+} fmt_gram;
 
 typedef struct {
   int p;               /* maximum total degree, 0..FMT_MAX_P */
@@ -77,6 +86,8 @@ typedef struct {
   int refine_steps;    /* iterative-refinement sweeps per node, 0..8 */
   double box_lo[3];    /* root box; default 0 */
   double box_hi[3];    /* default 1; box_hi > box_lo on every axis */
+  int gram;            /* fmt_gram: how the float64 path forms the normal
+                          equations (the mixed path always uses MFMA) */
 } fmt_fit_opts;
 
 typedef struct fmt_tree fmt_tree;   /* opaque; its storage lives in device memory */
@@ -95,7 +106,8 @@ typedef struct {
 } fmt_tree_info;
 
 /* Fill `opts` with the defaults: p = 4, tol = 1e-8, max_depth = 6,
-   path = FMT_PATH_FP64, refine_steps = 1, box = [0,1]^3. */
+   path = FMT_PATH_FP64, refine_steps = 1, box = [0,1]^3,
+   gram = FMT_GRAM_MOMENTS. */
 void fmt_default_opts(fmt_fit_opts* opts);
 
 /*
@@ -158,9 +170,13 @@ fmt_status fmt_tree_get_info(const fmt_tree* tree, fmt_tree_info* info);
  *   prefix : the node's key prefix (Morton bits of its cell, 3*level bits)
  *   begin  : first position of its points in the key-sorted point order
  *   count  : its point count
+ *   flags  : bit 0 set if a Cholesky pivot was deflated (the node's points
+ *            do not determine every basis coefficient: the fitted values at
+ *            the points are unique, the polynomial away from them is not);
+ *            bit 1 set if a coefficient was not finite
  */
 fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t* prefix,
-                                 uint32_t* begin, uint32_t* count, double* coeffs);
+                                 uint32_t* begin, uint32_t* count, uint32_t* flags, double* coeffs);
 
 /*
  * Copy per-point results to host buffers of info.n_points entries, indexed by
@@ -182,6 +198,29 @@ fmt_status fmt_tree_export_points(const fmt_tree* tree, uint32_t* keys, uint32_t
 fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_t* level,
                            const uint32_t* prefix, const double* coeffs, void* stream,
                            fmt_tree** out);
+
+/*
+ * Kernel timing (a profiling aid, not part of the method).  While enabled,
+ * every kernel launch of fit and eval is bracketed by HIP events recorded on
+ * the launch's own stream; fmt_profile_read waits for those events and
+ * accumulates, per kernel class, the launch count, the summed duration in
+ * milliseconds and the summed work units (points for point sweeps, nodes for
+ * per-node kernels, queries for eval).
+ */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double units;
+} fmt_kernel_stat;
+
+/* Turn timing on (nonzero) or off; returns the previous setting. */
+int fmt_profile_enable(int on);
+/* Clear the accumulated table. */
+void fmt_profile_reset(void);
+/* Copy up to max_entries rows (one per kernel class) into `out`; returns the
+   number written, or the number of classes if out is NULL. */
+int fmt_profile_read(fmt_kernel_stat* out, int max_entries);
 
 /* Release a tree (NULL is ignored).  Waits for the forest's pending work. */
 void fmt_tree_destroy(fmt_tree* tree);

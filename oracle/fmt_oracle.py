@@ -26,8 +26,10 @@ What is computed (all arithmetic IEEE float64; float32 inputs promoted exactly):
   the QR of the augmented matrix [Lambda | r] (its last column), which is the
   same Householder process without forming Q; tall nodes are factored in row
   blocks and the stacked triangles re-factored (a streamed QR), so memory stays
-  O(calL^2) per block.  A numerically rank-deficient R (coplanar points) is
-  solved in the minimum-norm sense instead (the fitted values stay unique).
+  O(calL^2) per block.  A numerically rank-deficient R -- condition number of
+  the column-equilibrated triangle above 1/(1e3 eps), e.g. coplanar points on
+  a clipped face -- is solved in the minimum-norm sense instead (the fitted
+  values stay unique).
 * Octants are taken from the integer cell of each point at the finest depth D:
   q = clamp(floor((x - lo) * (2^D / (hi - lo))), 0, 2^D - 1) per axis, and the
   octant at depth d+1 is the three bits (x highest) of the cells at that depth.
@@ -149,13 +151,13 @@ def mesh_to_moments(u, v, w, r, p: int, block: int = QR_BLOCK_ROWS):
     R = tri[0] if len(tri) == 1 else _qr_r(np.vstack(tri))
     Rl = R[:L, :L]
     z = R[:L, L]
-    # rank test on the column-equilibrated triangle
-    d = np.abs(np.diag(Rl)) / np.sqrt(np.maximum(colnorm2, np.finfo(np.float64).tiny))
-    rank_def = bool(np.any(d <= 1e3 * EPS))
+    # numerical rank: condition number of the column-equilibrated triangle
+    scale = 1.0 / np.sqrt(np.maximum(colnorm2, np.finfo(np.float64).tiny))
+    sv = np.linalg.svd(Rl * scale[None, :], compute_uv=False)
+    rank_def = bool(sv[-1] <= 1e3 * EPS * sv[0])
     if not rank_def:
         F = scipy.linalg.solve_triangular(Rl, z, lower=False)
     else:
-        scale = 1.0 / np.sqrt(np.maximum(colnorm2, np.finfo(np.float64).tiny))
         G, *_ = np.linalg.lstsq(Rl * scale[None, :], z, rcond=1e3 * EPS)
         F = G * scale
     return F, rank_def

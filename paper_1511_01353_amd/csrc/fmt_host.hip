@@ -46,6 +46,69 @@ void hip_check(hipError_t e, const char* what) {
 #define HIPCHK(x) hip_check((x), #x)
 
 // ---------------------------------------------------------------------------
+// kernel timing: events around each launch on its own stream, resolved when
+// the caller reads the table
+// ---------------------------------------------------------------------------
+struct ProfRecord {
+  int kernel;
+  hipEvent_t a, b;
+  double units;   // points (or queries) the launch covered
+};
+const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce", "solve", "refine_sweep",
+                              "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval"};
+enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
+       KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COUNT };
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof_pending;
+struct ProfAcc {
+  int64_t launches = 0;
+  double ms = 0, units = 0;
+};
+ProfAcc g_prof_acc[KN_COUNT];
+
+struct ProfScope {
+  bool on;
+  int kernel;
+  double units;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int k, double u, hipStream_t st) : kernel(k), units(u), s(st) {
+    {
+      std::lock_guard<std::mutex> g(g_prof_mu);
+      on = g_prof_on;
+    }
+    if (on) {
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      HIPCHK(hipEventRecord(a, s));
+    }
+  }
+  ~ProfScope() {
+    if (!on) return;
+    if (hipEventRecord(b, s) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_pending.push_back(ProfRecord{kernel, a, b, units});
+  }
+};
+
+void prof_resolve() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto& r : g_prof_pending) {
+    (void)hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      g_prof_acc[r.kernel].launches += 1;
+      g_prof_acc[r.kernel].ms += ms;
+      g_prof_acc[r.kernel].units += r.units;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+}
+
+// ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
 struct DevBuf {
@@ -114,11 +177,11 @@ struct ProblemInfo {
 };
 
 struct Forest {
-  int p = 0, L = 0, D = 0, path = 0, dtype = 0, refine = 0;
+  int p = 0, L = 0, D = 0, path = 0, dtype = 0, refine = 0, gram = 0;
   int nprob = 0;
   int pbits = 0;                         // problem-id bits above the Morton bits
   uint32_t nodes = 0;
-  std::vector<uint32_t> level_start, level_count;
+  std::vector<uint32_t> level_start, level_count, level_points;
   std::vector<ProblemInfo> probs;
   // node table (exact size)
   DevBuf nb_begin, nb_count, nb_prefix, nb_level, nb_problem, nb_parent, nb_first_child, nb_child_mask, nb_flags,
@@ -204,6 +267,7 @@ void validate_opts(const fmt_fit_opts& o) {
   if (!(o.tol >= 0.0) || std::isinf(o.tol)) fail(FMT_E_INVALID_ARG, "tol must be finite and >= 0");
   if (o.path != FMT_PATH_FP64 && o.path != FMT_PATH_MIXED) fail(FMT_E_INVALID_ARG, "unknown path");
   if (o.refine_steps < 0 || o.refine_steps > kRefineMax) fail(FMT_E_INVALID_ARG, "refine_steps out of range 0..8");
+  if (o.gram != FMT_GRAM_MOMENTS && o.gram != FMT_GRAM_MFMA) fail(FMT_E_INVALID_ARG, "unknown gram method");
   for (int a = 0; a < 3; ++a)
     if (!(o.box_hi[a] > o.box_lo[a]) || !std::isfinite(o.box_lo[a]) || !std::isfinite(o.box_hi[a]))
       fail(FMT_E_INVALID_ARG, "box_hi must exceed box_lo on every axis");
@@ -237,6 +301,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   F->path = o.path;
   F->dtype = dtype;
   F->refine = o.refine_steps;
+  F->gram = o.path == FMT_PATH_MIXED ? FMT_GRAM_MFMA : o.gram;
   F->nprob = (int)in.size();
   F->stream = s;
   HIPCHK(hipGetDevice(&F->device));
@@ -285,19 +350,29 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
   const ProblemParams* d_prm = W.params.as<ProblemParams>();
 
-  // K1 keys, K2 sort, K3 gather
-  HIPCHK(launch_keygen(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->D, N, F->skey.as<uint32_t>(),
-                       W.status.as<uint32_t>(), s));
-  bool in_alt = false;
-  HIPCHK(radix_sort(F->skey.as<uint32_t>(), F->order.as<uint32_t>(), W.keys_alt.as<uint32_t>(),
-                    W.vals_alt.as<uint32_t>(), N, 3 * F->D + F->pbits, true, W.sort_scratch.as<uint32_t>(), s,
-                    &in_alt));
-  if (in_alt) {
-    HIPCHK(hipMemcpyAsync(F->skey.p, W.keys_alt.p, 4ull * N, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(F->order.p, W.vals_alt.p, 4ull * N, hipMemcpyDeviceToDevice, s));
+  // K1 keys, K2 sort, K3 gather.  With an odd number of sort passes the keys
+  // start in the alternate buffer so that the sorted result lands in the
+  // forest's arrays.
+  const int key_bits = 3 * F->D + F->pbits;
+  const bool odd = (radix_sort_passes(key_bits) & 1) != 0;
+  uint32_t* k_in = odd ? W.keys_alt.as<uint32_t>() : F->skey.as<uint32_t>();
+  uint32_t* v_in = odd ? W.vals_alt.as<uint32_t>() : F->order.as<uint32_t>();
+  uint32_t* k_out = odd ? F->skey.as<uint32_t>() : W.keys_alt.as<uint32_t>();
+  uint32_t* v_out = odd ? F->order.as<uint32_t>() : W.vals_alt.as<uint32_t>();
+  {
+    ProfScope ps(KN_KEYGEN, N, s);
+    HIPCHK(launch_keygen(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->D, N, k_in, W.status.as<uint32_t>(), s));
   }
-  HIPCHK(launch_gather(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->order.as<uint32_t>(), N, W.px.p, W.py.p, W.pz.p,
-                       F->resid.as<double>(), s));
+  bool in_alt = false;
+  ProfScope* sort_scope = new ProfScope(KN_SORT, N, s);
+  HIPCHK(radix_sort(k_in, v_in, k_out, v_out, N, key_bits, true, W.sort_scratch.as<uint32_t>(), s, &in_alt));
+  if (in_alt != odd) fail(FMT_E_DEVICE, "internal: sort result in an unexpected buffer");
+  delete sort_scope;
+  {
+    ProfScope ps(KN_GATHER, N, s);
+    HIPCHK(launch_gather(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->order.as<uint32_t>(), N, W.px.p, W.py.p,
+                         W.pz.p, F->resid.as<double>(), s));
+  }
 
   // node capacity: at depth d at most min(K 8^d, N / L) nodes
   uint64_t cap = 0;
@@ -319,18 +394,22 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   HIPCHK(hipMemcpyAsync(W.chunk_a.p, off0.data(), 4ull * (K + 1), hipMemcpyHostToDevice, s));
 
   uint32_t nnodes = (uint32_t)K, nchunks = off0[K], node0 = 0;
+  uint32_t level_points = N;
   F->level_start.clear();
   F->level_count.clear();
   DevBuf* cur_off = &W.chunk_a;
   DevBuf* next_off = &W.chunk_b;
-  const size_t gpd = gram_partial_doubles(F->p), fd = factor_doubles(F->p);
+  const bool use_moments = F->gram == FMT_GRAM_MOMENTS;
+  const size_t gpd = use_moments ? moment_partial_doubles(F->p) : gram_partial_doubles(F->p);
+  const size_t fd = factor_doubles(F->p);
+  const size_t rbd = moment_refine_doubles(F->p);
   for (int d = 0; d <= F->D && nnodes > 0; ++d) {
     F->level_start.push_back(node0);
     F->level_count.push_back(nnodes);
     W.partial.reserve(8ull * gpd * nchunks);
     if (F->refine > 0) {
       W.fac.reserve(8ull * fd * nnodes);
-      W.part_b.reserve(8ull * L * nchunks);
+      W.part_b.reserve(8ull * rbd * nchunks);
     }
     W.part_ss.reserve(8ull * 8 * nchunks);
     W.cbeg.reserve(4ull * 8 * nnodes);
@@ -353,44 +432,85 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     a.D = F->D;
     a.tol = tols[0];
 
-    HIPCHK(launch_gram(F->p, F->path, dtype, a, W.partial.as<double>(), s));
-    HIPCHK(launch_solve(F->p, a, W.partial.as<double>(), F->refine > 0 ? W.fac.as<double>() : nullptr, s));
+    const bool multi = nchunks > nnodes;   // some node spans several chunks
+    {
+      ProfScope ps(KN_GRAM, level_points, s);
+      if (use_moments) HIPCHK(launch_moments(F->p, 0, dtype, a, W.partial.as<double>(), s));
+      else HIPCHK(launch_gram(F->p, F->path, dtype, a, W.partial.as<double>(), s));
+    }
+    if (multi) {
+      ProfScope ps(KN_REDUCE, nchunks, s);
+      HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), (uint32_t)gpd, s));
+    }
+    {
+      ProfScope ps(KN_SOLVE, nnodes, s);
+      double* fac = F->refine > 0 ? W.fac.as<double>() : nullptr;
+      if (use_moments) HIPCHK(launch_solve_moments(F->p, a, W.partial.as<double>(), fac, s));
+      else HIPCHK(launch_solve(F->p, a, W.partial.as<double>(), fac, s));
+    }
     for (int it = 0; it < F->refine; ++it) {
-      HIPCHK(launch_refine_sweep(F->p, dtype, a, W.part_b.as<double>(), s));
+      {
+        ProfScope ps(KN_RSWEEP, level_points, s);
+        HIPCHK(launch_moments(F->p, 1, dtype, a, W.part_b.as<double>(), s));
+        if (multi) HIPCHK(launch_chunk_reduce(a, W.part_b.as<double>(), (uint32_t)rbd, s));
+      }
+      ProfScope ps(KN_RSOLVE, nnodes, s);
       HIPCHK(launch_refine_solve(F->p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
     }
-    HIPCHK(launch_residual(F->p, dtype, a, W.part_ss.as<double>(), s));
+    {
+      ProfScope ps(KN_RESID, level_points, s);
+      HIPCHK(launch_residual(F->p, dtype, a, W.part_ss.as<double>(), s));
+      if (multi && d < F->D) HIPCHK(launch_chunk_reduce(a, W.part_ss.as<double>(), 8, s));
+    }
+    F->level_points.push_back(level_points);
     if (d == F->D) {
       node0 += nnodes;
       break;
     }
-    HIPCHK(launch_children(F->p, a, W.part_ss.as<double>(), W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(),
-                           W.nact.as<uint32_t>(), s));
+    {
+      ProfScope ps(KN_CHILD, nnodes, s);
+      HIPCHK(launch_children(F->p, a, W.part_ss.as<double>(), W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(),
+                             W.nact.as<uint32_t>(), s));
+    }
     const uint32_t next0 = node0 + nnodes;
-    HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
-                       next_off->as<uint32_t>(), W.counters.as<uint32_t>(), s));
-    HIPCHK(hipMemcpyAsync(W.host_counters, W.counters.p, 8, hipMemcpyDeviceToHost, s));
+    {
+      ProfScope ps(KN_EMIT, nnodes, s);
+      HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
+                         next_off->as<uint32_t>(), W.counters.as<uint32_t>(), s));
+    }
+    HIPCHK(hipMemcpyAsync(W.host_counters, W.counters.p, 12, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     node0 = next0;
     nnodes = W.host_counters[0];
     nchunks = W.host_counters[1];
+    level_points = W.host_counters[2];
     std::swap(cur_off, next_off);
   }
   F->nodes = node0;
   HIPCHK(launch_check_coef(F->p, nt, F->nodes, W.status.as<uint32_t>(), s));
 
-  // compact the node table into the forest
-  F->alloc_nodes(std::max<uint32_t>(F->nodes, 1));
-  auto cp = [&](DevBuf& dst, const DevBuf& src, size_t bytes) {
-    if (bytes) HIPCHK(hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyDeviceToDevice, s));
-  };
-  const size_t un = 4ull * F->nodes;
-  cp(F->nb_begin, tmp.nb_begin, un); cp(F->nb_count, tmp.nb_count, un); cp(F->nb_prefix, tmp.nb_prefix, un);
-  cp(F->nb_level, tmp.nb_level, un); cp(F->nb_problem, tmp.nb_problem, un); cp(F->nb_parent, tmp.nb_parent, un);
-  cp(F->nb_first_child, tmp.nb_first_child, un); cp(F->nb_child_mask, tmp.nb_child_mask, un);
-  cp(F->nb_flags, tmp.nb_flags, un);
-  cp(F->nb_geo, tmp.nb_geo, 48ull * F->nodes);
-  cp(F->nb_coef, tmp.nb_coef, 8ull * L * F->nodes);
+  // hand the node table to the forest; copy it down to its exact size only
+  // when the capacity bound would hold much more memory than the nodes need
+  const size_t per_node = 4ull * 9 + 48ull + 8ull * L;
+  if ((uint64_t)cap * per_node <= (64ull << 20) || (uint64_t)cap <= 2ull * F->nodes) {
+    F->nb_begin = std::move(tmp.nb_begin); F->nb_count = std::move(tmp.nb_count);
+    F->nb_prefix = std::move(tmp.nb_prefix); F->nb_level = std::move(tmp.nb_level);
+    F->nb_problem = std::move(tmp.nb_problem); F->nb_parent = std::move(tmp.nb_parent);
+    F->nb_first_child = std::move(tmp.nb_first_child); F->nb_child_mask = std::move(tmp.nb_child_mask);
+    F->nb_flags = std::move(tmp.nb_flags); F->nb_geo = std::move(tmp.nb_geo); F->nb_coef = std::move(tmp.nb_coef);
+  } else {
+    F->alloc_nodes(std::max<uint32_t>(F->nodes, 1));
+    auto cp = [&](DevBuf& dst, const DevBuf& src, size_t bytes) {
+      if (bytes) HIPCHK(hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyDeviceToDevice, s));
+    };
+    const size_t un = 4ull * F->nodes;
+    cp(F->nb_begin, tmp.nb_begin, un); cp(F->nb_count, tmp.nb_count, un); cp(F->nb_prefix, tmp.nb_prefix, un);
+    cp(F->nb_level, tmp.nb_level, un); cp(F->nb_problem, tmp.nb_problem, un); cp(F->nb_parent, tmp.nb_parent, un);
+    cp(F->nb_first_child, tmp.nb_first_child, un); cp(F->nb_child_mask, tmp.nb_child_mask, un);
+    cp(F->nb_flags, tmp.nb_flags, un);
+    cp(F->nb_geo, tmp.nb_geo, 48ull * F->nodes);
+    cp(F->nb_coef, tmp.nb_coef, 8ull * L * F->nodes);
+  }
   HIPCHK(hipMemcpyAsync(W.host_counters + 4, W.status.p, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   F->device_status = W.host_counters[4];
@@ -455,6 +575,7 @@ void fmt_default_opts(fmt_fit_opts* o) {
     o->box_lo[a] = 0.0;
     o->box_hi[a] = 1.0;
   }
+  o->gram = FMT_GRAM_MOMENTS;
 }
 
 const char* fmt_last_error(void) { return g_last_error.c_str(); }
@@ -492,9 +613,10 @@ fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const v
       if (n[k] < 0) fail(FMT_E_INVALID_ARG, "negative n");
     }
     // group by (p, path, max_depth, refine_steps, tol)
-    std::map<std::tuple<int, int, int, int, double>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int, double, int>, std::vector<int>> groups;
     for (int k = 0; k < count; ++k)
-      groups[std::make_tuple(opts[k].p, opts[k].path, opts[k].max_depth, opts[k].refine_steps, opts[k].tol)]
+      groups[std::make_tuple(opts[k].p, opts[k].path, opts[k].max_depth, opts[k].refine_steps, opts[k].tol,
+                             opts[k].gram)]
           .push_back(k);
     std::vector<fmt_tree*> made(count, nullptr);
     try {
@@ -540,6 +662,7 @@ fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const 
     const uint32_t n = (uint32_t)nq;
     const bool sort = sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) && F.nodes > 64);
     if (!sort) {
+      ProfScope ps(KN_EVAL, n, s);
       HIPCHK(launch_eval(F.p, dtype, t, qx, qy, qz, nullptr, nullptr, n, out, s));
       return;
     }
@@ -558,13 +681,23 @@ fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const 
     void* sx = cbase;
     void* sy = cbase + esz * n;
     void* sz = cbase + 2 * esz * n;
-    hipError_t e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, F.D, k0, s);
+    hipError_t e;
+    {
+      ProfScope ps(KN_EKEYS, n, s);
+      e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, F.D, k0, s);
+    }
     bool in_alt = false;
-    if (e == hipSuccess) e = radix_sort(k0, v0, k1, v1, n, 3 * F.D, true, scr, s, &in_alt);
+    {
+      ProfScope ps(KN_ESORT, n, s);
+      if (e == hipSuccess) e = radix_sort(k0, v0, k1, v1, n, 3 * F.D, true, scr, s, &in_alt);
+    }
     uint32_t* ks = in_alt ? k1 : k0;
     uint32_t* vs = in_alt ? v1 : v0;
-    if (e == hipSuccess) e = launch_permute3(dtype, qx, qy, qz, vs, n, sx, sy, sz, s);
-    if (e == hipSuccess) e = launch_eval(F.p, dtype, t, sx, sy, sz, vs, ks, n, out, s);
+    {
+      ProfScope ps(KN_EVAL, n, s);
+      if (e == hipSuccess) e = launch_permute3(dtype, qx, qy, qz, vs, n, sx, sy, sz, s);
+      if (e == hipSuccess) e = launch_eval(F.p, dtype, t, sx, sy, sz, vs, ks, n, out, s);
+    }
     hipError_t e2 = hipFreeAsync(base, s);
     hip_check(e, "eval");
     hip_check(e2, "hipFreeAsync");
@@ -609,7 +742,7 @@ fmt_status fmt_tree_get_info(const fmt_tree* tree, fmt_tree_info* info) {
 }
 
 fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t* prefix, uint32_t* begin,
-                                 uint32_t* count, double* coeffs) {
+                                 uint32_t* count, uint32_t* flags, double* coeffs) {
   return guard([&] {
     if (!tree) fail(FMT_E_INVALID_ARG, "NULL tree");
     fmt_tree* t = const_cast<fmt_tree*>(tree);
@@ -622,6 +755,7 @@ fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t*
       if (prefix) prefix[j] = F.h_prefix[i];
       if (begin) begin[j] = F.h_begin[i] - off;
       if (count) count[j] = F.h_count[i];
+      if (flags) flags[j] = F.h_flags[i];
       if (coeffs) std::memcpy(coeffs + j * F.L, F.h_coef.data() + (size_t)i * F.L, sizeof(double) * F.L);
     }
   });
@@ -737,6 +871,35 @@ fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_
     t->problem = 0;
     *out = t;
   });
+}
+
+int fmt_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  const int prev = g_prof_on ? 1 : 0;
+  g_prof_on = on != 0;
+  return prev;
+}
+
+void fmt_profile_reset(void) {
+  prof_resolve();
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto& a : g_prof_acc) a = ProfAcc();
+}
+
+int fmt_profile_read(fmt_kernel_stat* out, int max_entries) {
+  prof_resolve();
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  int n = 0;
+  for (int k = 0; k < KN_COUNT && n < max_entries; ++k) {
+    if (!out) break;
+    std::memset(&out[n], 0, sizeof(fmt_kernel_stat));
+    std::snprintf(out[n].name, sizeof(out[n].name), "%s", kKernelNames[k]);
+    out[n].launches = g_prof_acc[k].launches;
+    out[n].ms = g_prof_acc[k].ms;
+    out[n].units = g_prof_acc[k].units;
+    ++n;
+  }
+  return out ? n : KN_COUNT;
 }
 
 void fmt_tree_destroy(fmt_tree* tree) {

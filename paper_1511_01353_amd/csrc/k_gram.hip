@@ -77,19 +77,16 @@ __device__ __forceinline__ void write_cols(TT* tile, int lane, const double (&pu
   }
 }
 
+// Partial Gram of points [start, end) of a node into `out`, basis values and
+// products in TT.  Float32 products accumulate in float32 over one batch of 64
+// points and are then added into float64 registers.
 template <int P, typename TIN, typename TT>
-__global__ void __launch_bounds__(256) k_gram(LevelArgs a, double* __restrict__ partial) {
+__device__ __forceinline__ void gram_body(const LevelArgs& a, TT* tile, uint32_t start, uint32_t end,
+                                          const double* geo, double* __restrict__ out) {
   using S = GramShape<P>;
   using M = Mfma<TT>;
-  __shared__ TT tile[S::LP * S::PS];
+  constexpr bool NARROW = sizeof(TT) < sizeof(double);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const uint32_t g = blockIdx.x;
-  const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
-  const uint32_t node = a.node0 + k;
-  const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
-  const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
-  const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
-  const double* geo = a.nt.geo + 6 * (size_t)node;
   const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
 
   // blocks (t1, t2), t1 <= t2, enumerated row by row; wave w owns j = w + 4*jj
@@ -102,8 +99,15 @@ __global__ void __launch_bounds__(256) k_gram(LevelArgs a, double* __restrict__ 
     t2s[jj] = t1 + rem;
   }
   typename M::acc_t acc[S::MAXPW];
+  double wide[NARROW ? S::MAXPW : 1][4];
 #pragma unroll
-  for (int jj = 0; jj < S::MAXPW; ++jj) acc[jj] = typename M::acc_t{0, 0, 0, 0};
+  for (int jj = 0; jj < S::MAXPW; ++jj) {
+    acc[jj] = typename M::acc_t{0, 0, 0, 0};
+    if constexpr (NARROW) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) wide[jj][i] = 0.0;
+    }
+  }
 
   for (uint32_t bs = start; bs < end; bs += S::PB) {
     const uint32_t pt = bs + lane;
@@ -143,16 +147,51 @@ __global__ void __launch_bounds__(256) k_gram(LevelArgs a, double* __restrict__ 
         }
       }
     }
+    if constexpr (NARROW) {
+#pragma unroll
+      for (int jj = 0; jj < S::MAXPW; ++jj) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wide[jj][i] += (double)acc[jj][i];
+        acc[jj] = typename M::acc_t{0, 0, 0, 0};
+      }
+    }
   }
-  double* out = partial + (size_t)g * S::NPAIR * 256;
 #pragma unroll
   for (int jj = 0; jj < S::MAXPW; ++jj) {
     const int j = w + 4 * jj;
     if (j < S::NPAIR) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out[j * 256 + M::row(lane, i) * 16 + (lane & 15)] = (double)acc[jj][i];
+      for (int i = 0; i < 4; ++i) {
+        double val;
+        if constexpr (NARROW) val = wide[jj][i]; else val = (double)acc[jj][i];
+        out[j * 256 + M::row(lane, i) * 16 + (lane & 15)] = val;
+      }
     }
   }
+}
+
+// MIXED = false: float64 basis values and products.  MIXED = true: float32
+// products, except for nodes with fewer than MIXED_WIDE_RATIO * calL points
+// (near-interpolating nodes whose Gram is too ill-conditioned for a float32
+// preconditioner), which take the float64 route.
+constexpr int MIXED_WIDE_RATIO = 4;
+
+template <int P, typename TIN, bool MIXED>
+__global__ void __launch_bounds__(256) k_gram(LevelArgs a, double* __restrict__ partial) {
+  using S = GramShape<P>;
+  __shared__ double tile[S::LP * S::PS];
+  const uint32_t g = blockIdx.x;
+  const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
+  const uint32_t node = a.node0 + k;
+  const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
+  const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
+  const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
+  const double* geo = a.nt.geo + 6 * (size_t)node;
+  double* out = partial + (size_t)g * S::NPAIR * 256;
+  if (MIXED && nc >= (uint32_t)(MIXED_WIDE_RATIO * S::L))
+    gram_body<P, TIN, float>(a, reinterpret_cast<float*>(tile), start, end, geo, out);
+  else
+    gram_body<P, TIN, double>(a, tile, start, end, geo, out);
 }
 
 template <int P>
@@ -160,11 +199,11 @@ static hipError_t gram_impl(int path, int dtype, const LevelArgs& a, double* par
   if (a.nchunks == 0) return hipSuccess;
   dim3 grid(a.nchunks), block(256);
   if (path == FMT_PATH_MIXED) {
-    if (dtype == FMT_F32) hipLaunchKernelGGL((k_gram<P, float, float>), grid, block, 0, s, a, partial);
-    else hipLaunchKernelGGL((k_gram<P, double, float>), grid, block, 0, s, a, partial);
+    if (dtype == FMT_F32) hipLaunchKernelGGL((k_gram<P, float, true>), grid, block, 0, s, a, partial);
+    else hipLaunchKernelGGL((k_gram<P, double, true>), grid, block, 0, s, a, partial);
   } else {
-    if (dtype == FMT_F32) hipLaunchKernelGGL((k_gram<P, float, double>), grid, block, 0, s, a, partial);
-    else hipLaunchKernelGGL((k_gram<P, double, double>), grid, block, 0, s, a, partial);
+    if (dtype == FMT_F32) hipLaunchKernelGGL((k_gram<P, float, false>), grid, block, 0, s, a, partial);
+    else hipLaunchKernelGGL((k_gram<P, double, false>), grid, block, 0, s, a, partial);
   }
   return hipGetLastError();
 }

@@ -38,11 +38,19 @@ size_t gram_partial_doubles(int p);
 // equilibration scales).
 size_t factor_doubles(int p);
 
+// Sum each multi-chunk node's chunk partials (`width` doubles per chunk) into
+// its first chunk slot.
+hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, hipStream_t s);
 hipError_t launch_node_geo(const NodeTable& nt, const ProblemParams* prm, uint32_t n, hipStream_t s);
 hipError_t launch_roots(const NodeTable& nt, const ProblemParams* prm, int nprob, hipStream_t s);
 hipError_t launch_gram(int p, int path, int dtype, const LevelArgs& a, double* partial, hipStream_t s);
+// Power moments of every chunk (mode 0: M, B, sum r^2; mode 1: B of r - Lambda F).
+size_t moment_partial_doubles(int p);
+size_t moment_refine_doubles(int p);
+hipError_t launch_moments(int p, int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s);
 hipError_t launch_solve(int p, const LevelArgs& a, const double* partial, double* fac, hipStream_t s);
-hipError_t launch_refine_sweep(int p, int dtype, const LevelArgs& a, double* part_b, hipStream_t s);
+// K6 assembled from power moments (the k_moments mode-0 layout).
+hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part, double* fac, hipStream_t s);
 hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s);
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s);
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,

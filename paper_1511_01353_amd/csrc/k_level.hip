@@ -18,25 +18,96 @@ size_t factor_doubles(int p) {
 constexpr double PIVOT_EPS = 1e-13;
 
 // ---------------------------------------------------------------------------
-// Triangular solves with a packed factor; one workgroup, one sync per step.
-// b: scaled right-hand side (destroyed); z: solution of (L L^T) z = b.
+// Triangular solves with a packed factor, run by wave 0 alone: lane l owns
+// rows l, l+64, l+128 (registers), the pivot value of each step is broadcast
+// from its owner lane, so no workgroup barrier is needed.  Solves
+// (L L^T) z = b for the scaled right-hand side b; deflated pivots (0) give 0.
+// The caller synchronises the workgroup before reading z.
 // ---------------------------------------------------------------------------
 template <int L>
-__device__ void tri_solve(const double* A, const double* diagL, double* b, double* y, double* z) {
+__device__ void tri_solve_wave(const double* A, const double* dg, const double* b, double* z) {
+  constexpr int NS = (L + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  double bb[NS], yy[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = lane + 64 * s;
+    bb[s] = i < L ? b[i] : 0.0;
+    yy[s] = 0.0;
+  }
+  // forward: L y = b
+#pragma unroll
+  for (int s0 = 0; s0 < NS; ++s0) {
+    const int jn = (L - 64 * s0) < 64 ? (L - 64 * s0) : 64;
+    for (int jj = 0; jj < jn; ++jj) {
+      const int j = 64 * s0 + jj;
+      const double bj = __shfl(bb[s0], jj);
+      const double dj = dg[j];
+      const double yj = dj > 0.0 ? bj / dj : 0.0;
+      if (lane == jj) yy[s0] = yj;
+#pragma unroll
+      for (int s = s0; s < NS; ++s) {
+        const int i = lane + 64 * s;
+        if (i > j && i < L) bb[s] -= A[pk(i, j)] * yj;
+      }
+    }
+  }
+  // backward: L^T z = y
+  double zz[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) zz[s] = 0.0;
+#pragma unroll
+  for (int s0 = NS - 1; s0 >= 0; --s0) {
+    const int jn = (L - 64 * s0) < 64 ? (L - 64 * s0) : 64;
+    for (int jj = jn - 1; jj >= 0; --jj) {
+      const int j = 64 * s0 + jj;
+      const double yj = __shfl(yy[s0], jj);
+      const double dj = dg[j];
+      const double zj = dj > 0.0 ? yj / dj : 0.0;
+      if (lane == jj) zz[s0] = zj;
+#pragma unroll
+      for (int s = 0; s <= s0; ++s) {
+        const int i = lane + 64 * s;
+        if (i < j) yy[s] -= A[pk(j, i)] * zj;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = lane + 64 * s;
+    if (i < L) z[i] = zz[s];
+  }
+}
+
+// Left-looking Cholesky of the packed, unit-diagonal matrix A in place (all
+// threads of the workgroup).  At step j each active row's dot product over
+// the finished columns is split over a group of G lanes (G a power of two,
+// the largest with (L - j) * G <= 256) and reduced by a fixed butterfly.
+// Pivots <= PIVOT_EPS are deflated: the column is dropped (dg = 0).
+template <int L>
+__device__ void cholesky_lds(double* A, double* dg) {
   const int tid = threadIdx.x;
   for (int j = 0; j < L; ++j) {
-    const double dj = diagL[j];
-    const double yj = dj > 0.0 ? b[j] / dj : 0.0;
-    const int i = j + 1 + tid;
-    if (i < L) b[i] -= A[pk(i, j)] * yj;
-    if (tid == 0) y[j] = yj;
+    const int rows = L - j;
+    int lg2 = 0;
+    while (lg2 < 6 && (rows << (lg2 + 1)) <= 256) ++lg2;
+    const int G = 1 << lg2;
+    const int r = tid >> lg2, q0 = tid & (G - 1);
+    double t = 0.0;
+    if (r < rows) {
+      const double* ri = A + pk(j + r, 0);
+      const double* rj = A + pk(j, 0);
+      for (int q = q0; q < j; q += G) t += ri[q] * rj[q];
+    }
+    for (int off = G >> 1; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+    if (r < rows && q0 == 0) A[pk(j + r, j)] -= t;
     __syncthreads();
-  }
-  for (int j = L - 1; j >= 0; --j) {
-    const double dj = diagL[j];
-    const double zj = dj > 0.0 ? y[j] / dj : 0.0;
-    if (tid < j) y[tid] -= A[pk(j, tid)] * zj;
-    if (tid == 0) z[j] = zj;
+    const double d = A[pk(j, j)];
+    const bool ok = d > PIVOT_EPS;
+    const double inv = ok ? 1.0 / sqrt(d) : 0.0;
+    const int i = j + 1 + tid;
+    if (i < L) A[pk(i, j)] *= inv;
+    if (tid == 0) dg[j] = ok ? sqrt(d) : 0.0;
     __syncthreads();
   }
 }
@@ -53,11 +124,11 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   constexpr int NPAIR = T * (T + 1) / 2;
   constexpr int NPK = L * (L + 1) / 2;
   __shared__ double A[NPK];
-  __shared__ double b[L], y[L], z[L], dg[L], sc[L];
+  __shared__ double b[L], z[L], dg[L], sc[L];
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
-  const uint32_t c0 = a.chunk_off[k], c1 = a.chunk_off[k + 1];
+  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
 
   // assemble: packed lower triangle of Lambda^T Lambda, then Lambda^T r
   for (int e = tid; e < NPK + L; e += 256) {
@@ -75,8 +146,7 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
     const int t1 = lo >> 4, t2 = hi >> 4;
     const int j = t1 * T - t1 * (t1 - 1) / 2 + (t2 - t1);
     const size_t off = (size_t)j * 256 + (lo & 15) * 16 + (hi & 15);
-    double s = 0.0;
-    for (uint32_t g = c0; g < c1; ++g) s += partial[(size_t)g * NPAIR * 256 + off];
+    const double s = partial[(size_t)c0 * NPAIR * 256 + off];
     if (e < NPK) A[e] = s; else b[i] = s;
   }
   __syncthreads();
@@ -94,25 +164,79 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   }
   for (int i = tid; i < L; i += 256) b[i] *= sc[i];
   __syncthreads();
-  // left-looking Cholesky in place; thread t owns row j + t at step j
-  for (int j = 0; j < L; ++j) {
-    const int i = j + tid;
-    if (i < L) {
-      double t = A[pk(i, j)];
-      const double* ri = A + pk(i, 0);
-      const double* rj = A + pk(j, 0);
-      for (int q = 0; q < j; ++q) t -= ri[q] * rj[q];
-      A[pk(i, j)] = t;
-    }
-    __syncthreads();
-    const double d = A[pk(j, j)];
-    const bool ok = d > PIVOT_EPS;
-    const double lj = ok ? sqrt(d) : 0.0;
-    if (i < L && i > j) A[pk(i, j)] = ok ? A[pk(i, j)] / lj : 0.0;
-    if (tid == 0) dg[j] = lj;
-    __syncthreads();
+  cholesky_lds<L>(A, dg);
+  if (tid < 64) tri_solve_wave<L>(A, dg, b, z);
+  __syncthreads();
+  double* F = a.nt.coef + (size_t)node * L;
+  bool deflated = false;
+  for (int i = tid; i < L; i += 256) {
+    F[i] = sc[i] * z[i];
+    if (dg[i] == 0.0) deflated = true;
   }
-  tri_solve<L>(A, dg, b, y, z);
+  if (fac) {
+    double* fo = fac + (size_t)k * (NPK + 2 * L);
+    for (int e = tid; e < NPK; e += 256) fo[e] = A[e];
+    for (int i = tid; i < L; i += 256) {
+      fo[NPK + i] = dg[i];
+      fo[NPK + L + i] = sc[i];
+    }
+  }
+  if (deflated) atomicOr(a.nt.flags + node, FLAG_DEFLATED);
+}
+
+// K6 from power moments: G_ik = M[alpha_i + alpha_k] / (alpha_i! alpha_k!),
+// b_i = B[alpha_i] / alpha_i!.  Equilibration is folded into the assembly:
+// with s_i = 1 / sqrt(G_ii) and w_i = s_i / alpha_i!, the scaled matrix is
+// A_ik = M[alpha_i + alpha_k] w_i w_k and the scaled right-hand side
+// B[alpha_i] w_i.
+__device__ __forceinline__ int graded(int a, int b, int c) {
+  const int k = a + b + c;
+  return k * (k + 1) * (k + 2) / 6 + (k - a) * (k - a + 1) / 2 + (k - a - b);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __restrict__ part,
+                                                 double* __restrict__ fac) {
+  constexpr int L = basis_size(P);
+  constexpr int NPK = L * (L + 1) / 2;
+  constexpr int NM = basis_size(2 * P);
+  constexpr int NOUT = NM + L + 1;
+  constexpr Basis<P> B{};
+  __shared__ double A[NPK];
+  __shared__ double mom[NOUT];
+  __shared__ double b[L], z[L], dg[L], sc[L], wv[L];
+  __shared__ int ex[L][3];
+  const int tid = threadIdx.x;
+  const uint32_t k = blockIdx.x;
+  const uint32_t node = a.node0 + k;
+  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
+  for (int e = tid; e < NOUT; e += 256) mom[e] = part[(size_t)c0 * NOUT + e];
+  for (int i = tid; i < L; i += 256) {
+    ex[i][0] = B.lx[i];
+    ex[i][1] = B.ly[i];
+    ex[i][2] = B.lz[i];
+  }
+  __syncthreads();
+  for (int i = tid; i < L; i += 256) {
+    const double f = B.inv_fact[i];
+    const double gii = mom[graded(2 * ex[i][0], 2 * ex[i][1], 2 * ex[i][2])] * f * f;
+    const double s = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+    sc[i] = s;
+    wv[i] = s * f;
+    b[i] = mom[NM + i] * s * f;
+  }
+  __syncthreads();
+  for (int i = tid; i < L; i += 256) {
+    const int xi = ex[i][0], yi = ex[i][1], zi = ex[i][2];
+    const double wi = wv[i];
+    double* row = A + pk(i, 0);
+    for (int q = 0; q <= i; ++q)
+      row[q] = mom[graded(xi + ex[q][0], yi + ex[q][1], zi + ex[q][2])] * wi * wv[q];
+  }
+  __syncthreads();
+  cholesky_lds<L>(A, dg);
+  if (tid < 64) tri_solve_wave<L>(A, dg, b, z);
+  __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
   bool deflated = false;
   for (int i = tid; i < L; i += 256) {
@@ -131,82 +255,32 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
 }
 
 // ---------------------------------------------------------------------------
-// K7: refinement.  Sweep: per chunk, r' = r - Lambda F and Lambda^T r' in
-// float64.  Solve: delta = G^{-1} (sum of chunk parts) with the kept factor,
-// F += delta.
+// K7: refinement.  The sweep (power moments of r' = r - Lambda F, float64,
+// in k_moments.hip) gives B'[alpha] = sum r' u^alpha per chunk; the solve
+// takes delta = G^{-1} Lambda^T r' with the kept factor and sets F += delta.
 // ---------------------------------------------------------------------------
-template <int P, typename TIN>
-__global__ void __launch_bounds__(256) k_refine_sweep(LevelArgs a, double* __restrict__ part_b) {
-  constexpr int L = basis_size(P);
-  constexpr int PB = 64, PS = PB + 4;
-  __shared__ double tile[L * PS];
-  __shared__ double Fs[L];
-  __shared__ double rp[PB];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const uint32_t g = blockIdx.x;
-  const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
-  const uint32_t node = a.node0 + k;
-  const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
-  const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
-  const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
-  const double* geo = a.nt.geo + 6 * (size_t)node;
-  const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
-  for (int i = tid; i < L; i += 256) Fs[i] = a.nt.coef[(size_t)node * L + i];
-  constexpr Basis<P> B{};
-  double acc = 0.0;
-  for (uint32_t bs = start; bs < end; bs += PB) {
-    const uint32_t pt = bs + lane;
-    const bool valid = pt < end;
-    double x = 0, y = 0, z = 0;
-    if (valid) load_point<TIN>(a.px, a.py, a.pz, pt, x, y, z);
-    double pu[P + 1], pv[P + 1], pw[P + 1];
-    scaled_powers<P>(valid ? (x - cx) * sx : 0.0, pu);
-    scaled_powers<P>(valid ? (y - cy) * sy : 0.0, pv);
-    scaled_powers<P>(valid ? (z - cz) * sz : 0.0, pw);
-    if (!valid) pu[0] = 0.0;
-    __syncthreads();
-    // wave w writes basis columns c = w, w+4, ...
-#pragma unroll
-    for (int c = 0; c < L; ++c)
-      if ((c & 3) == w) tile[c * PS + lane] = pu[B.lx[c]] * pv[B.ly[c]] * pw[B.lz[c]];
-    __syncthreads();
-    if (tid < PB) {
-      double s = 0.0;
-      for (int c = 0; c < L; ++c) s += tile[c * PS + tid] * Fs[c];
-      rp[tid] = (bs + tid < end) ? a.r[bs + tid] - s : 0.0;
-    }
-    __syncthreads();
-    if (tid < L) {
-      const double* col = tile + tid * PS;
-#pragma unroll 8
-      for (int q = 0; q < PB; ++q) acc += col[q] * rp[q];
-    }
-  }
-  if (tid < L) part_b[(size_t)g * L + tid] = acc;
-}
-
 template <int P>
 __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double* __restrict__ part_b,
                                                       const double* __restrict__ fac) {
   constexpr int L = basis_size(P);
   constexpr int NPK = L * (L + 1) / 2;
+  constexpr Basis<P> B{};
   __shared__ double A[NPK];
-  __shared__ double b[L], y[L], z[L], dg[L], sc[L];
+  __shared__ double b[L], z[L], dg[L], sc[L];
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
-  const uint32_t c0 = a.chunk_off[k], c1 = a.chunk_off[k + 1];
+  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   const double* fo = fac + (size_t)k * (NPK + 2 * L);
   for (int e = tid; e < NPK; e += 256) A[e] = fo[e];
   for (int i = tid; i < L; i += 256) {
     dg[i] = fo[NPK + i];
     sc[i] = fo[NPK + L + i];
-    double s = 0.0;
-    for (uint32_t g = c0; g < c1; ++g) s += part_b[(size_t)g * L + i];
-    b[i] = s * fo[NPK + L + i];
+    b[i] = part_b[(size_t)c0 * L + i] * B.inv_fact[i] * fo[NPK + L + i];
   }
   __syncthreads();
-  tri_solve<L>(A, dg, b, y, z);
+  if (tid < 64) tri_solve_wave<L>(A, dg, b, z);
+  __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
   for (int i = tid; i < L; i += 256) F[i] += sc[i] * z[i];
 }
@@ -297,19 +371,42 @@ __global__ void __launch_bounds__(256) k_children(LevelArgs a, const double* __r
     }
     bnd[o] = lo;
   }
-  const uint32_t c0 = a.chunk_off[k], c1 = a.chunk_off[k + 1];
+  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   uint32_t mask = 0;
   for (int o = 0; o < 8; ++o) {
     const uint32_t n_o = bnd[o + 1] - bnd[o];
     cbeg[(size_t)k * 8 + o] = bnd[o];
     ccnt[(size_t)k * 8 + o] = n_o;
     if (n_o < L) continue;
-    double s = 0.0;
-    for (uint32_t gg = c0; gg < c1; ++gg) s += part_ss[(size_t)gg * 8 + o];
+    const double s = part_ss[(size_t)c0 * 8 + o];
     if (sqrt(s / (double)n_o) > a.tol) mask |= 1u << o;
   }
   a.nt.child_mask[node] = mask;
   nact[k] = (uint32_t)__popc(mask);
+}
+
+// Sum the per-chunk partials of every multi-chunk node into the node's first
+// chunk slot (deterministic).  `width` doubles per chunk.  A workgroup covers
+// 64 elements of one node with 4 lane groups; group q sums chunks q, q+4, ...
+// and the four group sums are added in a fixed order.  Single-chunk nodes
+// exit at once.
+__global__ void __launch_bounds__(256) k_chunk_reduce(const uint32_t* __restrict__ chunk_off, uint32_t nnodes,
+                                                      double* __restrict__ buf, uint32_t width, uint32_t eblocks) {
+  __shared__ double part[4][64];
+  const uint32_t k = blockIdx.x / eblocks;
+  if (k >= nnodes) return;
+  const uint32_t c0 = chunk_off[k], c1 = chunk_off[k + 1];
+  if (c1 - c0 < 2) return;
+  const uint32_t e = (blockIdx.x % eblocks) * 64 + (threadIdx.x & 63);
+  const uint32_t q = threadIdx.x >> 6;
+  double s = 0.0;
+  if (e < width)
+    for (uint32_t g = c0 + q; g < c1; g += 4) s += buf[(size_t)g * width + e];
+  part[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q == 0 && e < width)
+    buf[(size_t)c0 * width + e] = ((part[0][threadIdx.x] + part[1][threadIdx.x]) + part[2][threadIdx.x]) +
+                                  part[3][threadIdx.x];
 }
 
 // Cell coordinates (i, j, k) of a Morton prefix with `level` triples.
@@ -383,6 +480,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
   }
   const uint32_t total = s[1023];
   uint32_t run = s[tid] - sum;
+  uint32_t pts = 0;
   for (uint32_t i = b; i < e; ++i) {
     const uint32_t node = a.node0 + i;
     const uint32_t mask = a.nt.child_mask[node];
@@ -405,9 +503,19 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
       a.nt.flags[cid] = 0;
       node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
       next_chunk_off[run] = (cn + CHUNK - 1) / CHUNK;
+      pts += cn;
       ++run;
     }
   }
+  __syncthreads();
+  // total points of the next level (fixed-order integer sum)
+  s[tid] = pts;
+  __syncthreads();
+  for (uint32_t off = 512; off >= 1; off >>= 1) {
+    if (tid < off) s[tid] += s[tid + off];
+    __syncthreads();
+  }
+  const uint32_t next_points = s[0];
   __syncthreads();
   // exclusive scan of the children's chunk counts
   const uint32_t seg2 = (total + 1023u) / 1024u;
@@ -433,6 +541,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     next_chunk_off[total] = s[1023];
     counters[0] = total;
     counters[1] = s[1023];
+    counters[2] = next_points;
   }
 }
 
@@ -466,14 +575,13 @@ hipError_t launch_solve(int p, const LevelArgs& a, const double* partial, double
 }
 
 template <int P>
-static hipError_t sweep_impl(int dtype, const LevelArgs& a, double* part_b, hipStream_t s) {
-  if (a.nchunks == 0) return hipSuccess;
-  if (dtype == FMT_F32) hipLaunchKernelGGL((k_refine_sweep<P, float>), dim3(a.nchunks), dim3(256), 0, s, a, part_b);
-  else hipLaunchKernelGGL((k_refine_sweep<P, double>), dim3(a.nchunks), dim3(256), 0, s, a, part_b);
+static hipError_t solve_m_impl(const LevelArgs& a, const double* part, double* fac, hipStream_t s) {
+  if (a.nnodes == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_solve_m<P>, dim3(a.nnodes), dim3(256), 0, s, a, part, fac);
   return hipGetLastError();
 }
-hipError_t launch_refine_sweep(int p, int dtype, const LevelArgs& a, double* part_b, hipStream_t s) {
-  FMT_DISPATCH_P(p, sweep_impl, dtype, a, part_b, s);
+hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part, double* fac, hipStream_t s) {
+  FMT_DISPATCH_P(p, solve_m_impl, a, part, fac, s);
 }
 
 template <int P>
@@ -512,6 +620,14 @@ hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uin
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, hipStream_t s) {
   hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, s, a, prm, cbeg, ccnt, nact, next0, next_chunk_off, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, hipStream_t s) {
+  if (a.nnodes == 0 || a.nchunks <= a.nnodes) return hipSuccess;
+  const uint32_t eblocks = (width + 63) / 64;
+  hipLaunchKernelGGL(k_chunk_reduce, dim3(a.nnodes * eblocks), dim3(256), 0, s, a.chunk_off, a.nnodes, buf, width,
+                     eblocks);
   return hipGetLastError();
 }
 

@@ -19,6 +19,9 @@ hipError_t launch_keygen(int dtype, const PtrSet* ptrs, const ProblemParams* prm
                          uint32_t total, uint32_t* keys, uint32_t* status, hipStream_t s);
 hipError_t launch_query_keys(int dtype, const void* qx, const void* qy, const void* qz, uint32_t nq,
                              const ProblemParams& P, int depth, uint32_t* keys, hipStream_t s);
+// number of passes radix_sort makes over `bits` key bits (odd counts leave
+// the result in the alternate buffers)
+int radix_sort_passes(int bits);
 // scratch: radix_sort_scratch_words(n) words of device memory
 size_t radix_sort_scratch_words(uint32_t n);
 // Sorts (keys, vals) by the low `bits` bits of the keys, stably.  The result

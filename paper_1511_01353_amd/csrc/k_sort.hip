@@ -80,31 +80,31 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __r
   for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) hist[d * gridDim.x + blockIdx.x] = h[d];
 }
 
-// Exclusive scan of m words by one workgroup of 1024 threads (each thread
-// owns a contiguous segment).  Writes the total to *total if non-null.
-__global__ void __launch_bounds__(1024) k_scan_1wg(uint32_t* __restrict__ data, uint32_t m,
-                                                   uint32_t* __restrict__ total) {
-  __shared__ uint32_t s[1024];
+// Exclusive scan of one digit's per-tile counts (workgroup d owns digit d:
+// hist[d * tiles + t], contiguous, read in coalesced rounds of 256); the
+// digit's total goes to tot[d].
+__global__ void __launch_bounds__(256) k_digit_scan(uint32_t* __restrict__ hist, uint32_t tiles,
+                                                    uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s[256];
   const uint32_t tid = threadIdx.x;
-  const uint32_t seg = (m + 1023u) / 1024u;
-  const uint32_t b = min(m, tid * seg), e = min(m, b + seg);
-  uint32_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += data[i];
-  s[tid] = sum;
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    uint32_t v = tid >= off ? s[tid - off] : 0u;
+  uint32_t* row = hist + (size_t)blockIdx.x * tiles;
+  uint32_t run = 0;
+  for (uint32_t base = 0; base < tiles; base += 256) {
+    const uint32_t i = base + tid;
+    const uint32_t v = i < tiles ? row[i] : 0u;
+    s[tid] = v;
     __syncthreads();
-    s[tid] += v;
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+      const uint32_t t = tid >= off ? s[tid - off] : 0u;
+      __syncthreads();
+      s[tid] += t;
+      __syncthreads();
+    }
+    if (i < tiles) row[i] = run + s[tid] - v;
+    run += s[255];
     __syncthreads();
   }
-  uint32_t run = s[tid] - sum;
-  for (uint32_t i = b; i < e; ++i) {
-    uint32_t v = data[i];
-    data[i] = run;
-    run += v;
-  }
-  if (tid == 1023 && total) *total = s[1023];
+  if (tid == 0) tot[blockIdx.x] = run;
 }
 
 template <bool FIRST>
@@ -113,13 +113,15 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
                                                                 uint32_t* __restrict__ kout,
                                                                 uint32_t* __restrict__ vout, uint32_t n,
                                                                 int shift,
-                                                                const uint32_t* __restrict__ offs) {
+                                                                const uint32_t* __restrict__ offs,
+                                                                const uint32_t* __restrict__ tot) {
   constexpr int WAVES = SORT_THREADS / 64;
   constexpr int QUARTER = SORT_TILE / WAVES;
   constexpr int ROUNDS = QUARTER / 64;
   __shared__ uint32_t wcnt[WAVES][RADIX];
   __shared__ uint32_t lofs[RADIX];
   __shared__ uint32_t goff[RADIX];
+  __shared__ uint32_t dbase[RADIX];
   __shared__ uint32_t sk[SORT_TILE];
   __shared__ uint32_t sv[SORT_TILE];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -164,19 +166,27 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
       wcnt[ww][tid] = run;
       run += c;
     }
-    lofs[tid] = run;   // digit total for now
-    goff[tid] = offs[tid * gridDim.x + blockIdx.x];
+    lofs[tid] = run;   // tile-local digit total for now
+    dbase[tid] = tot[tid];
   }
   __syncthreads();
-  // exclusive scan of the 256 digit totals (Hillis-Steele in place)
-  uint32_t mine = tid < RADIX ? lofs[tid] : 0u;
+  // exclusive scans of the tile-local and of the global digit totals
+  const uint32_t mine = tid < RADIX ? lofs[tid] : 0u;
+  const uint32_t mine_g = tid < RADIX ? dbase[tid] : 0u;
   for (int off = 1; off < RADIX; off <<= 1) {
-    uint32_t v = (tid < RADIX && tid >= off) ? lofs[tid - off] : 0u;
+    const uint32_t v = (tid < RADIX && tid >= off) ? lofs[tid - off] : 0u;
+    const uint32_t vg = (tid < RADIX && tid >= off) ? dbase[tid - off] : 0u;
     __syncthreads();
-    if (tid < RADIX) lofs[tid] += v;
+    if (tid < RADIX) {
+      lofs[tid] += v;
+      dbase[tid] += vg;
+    }
     __syncthreads();
   }
-  if (tid < RADIX) lofs[tid] -= mine;
+  if (tid < RADIX) {
+    lofs[tid] -= mine;
+    goff[tid] = dbase[tid] - mine_g + offs[tid * gridDim.x + blockIdx.x];
+  }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < ROUNDS; ++j) {
@@ -260,9 +270,14 @@ hipError_t launch_query_keys(int dtype, const void* qx, const void* qy, const vo
   return hipGetLastError();
 }
 
+int radix_sort_passes(int bits) {
+  const int p = (bits + RADIX_BITS - 1) / RADIX_BITS;
+  return p < 1 ? 1 : p;
+}
+
 size_t radix_sort_scratch_words(uint32_t n) {
   uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
-  return (size_t)RADIX * tiles + 16;
+  return (size_t)RADIX * tiles + RADIX + 16;
 }
 
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
@@ -271,26 +286,26 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32
   if (n == 0) return hipSuccess;
   const uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
   uint32_t* hist = scratch;
-  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  uint32_t* tot = scratch + (size_t)RADIX * tiles;
   int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
   if (passes < 1) passes = 1;   // at least one pass so that the index array is written
+  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * RADIX_BITS;
     hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
-    hipLaunchKernelGGL(k_scan_1wg, dim3(1), dim3(1024), 0, s, hist, (uint32_t)(RADIX * tiles),
-                       (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_digit_scan, dim3(RADIX), dim3(256), 0, s, hist, tiles, tot);
     if (p == 0 && vals_are_iota)
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
-                         hist);
+                         hist, tot);
     else
       hipLaunchKernelGGL(k_radix_scatter<false>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
-                         hist);
+                         hist, tot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t* t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
-    *result_in_alt = !*result_in_alt;
   }
+  *result_in_alt = (ki != keys);
   return hipSuccess;
 }
 

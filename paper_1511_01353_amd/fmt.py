@@ -32,6 +32,8 @@ FMT_F32 = 0
 FMT_F64 = 1
 FMT_PATH_FP64 = 0
 FMT_PATH_MIXED = 1
+FMT_GRAM_MOMENTS = 0
+FMT_GRAM_MFMA = 1
 FMT_MAX_P = 8
 FMT_MAX_DEPTH = 10
 FMT_MAX_LEVELS = FMT_MAX_DEPTH + 1
@@ -39,19 +41,23 @@ FMT_MAX_LEVELS = FMT_MAX_DEPTH + 1
 EXPORTED = [
     "fmt_default_opts", "fmt_fit", "fmt_fit_batch", "fmt_eval", "fmt_tree_wait", "fmt_tree_get_info",
     "fmt_tree_export_nodes", "fmt_tree_export_points", "fmt_tree_import", "fmt_tree_destroy",
-    "fmt_last_error", "fmt_version",
+    "fmt_last_error", "fmt_version", "fmt_profile_enable", "fmt_profile_reset", "fmt_profile_read",
 ]
 
 
 class fmt_fit_opts(ctypes.Structure):
     _fields_ = [("p", c_int), ("tol", c_double), ("max_depth", c_int), ("path", c_int),
-                ("refine_steps", c_int), ("box_lo", c_double * 3), ("box_hi", c_double * 3)]
+                ("refine_steps", c_int), ("box_lo", c_double * 3), ("box_hi", c_double * 3), ("gram", c_int)]
 
 
 class fmt_tree_info(ctypes.Structure):
     _fields_ = [("nodes", c_int64), ("n_points", c_int64), ("depth", c_int32), ("p", c_int32), ("L", c_int32),
                 ("max_depth", c_int32), ("path", c_int32), ("rank_deficient_nodes", c_int32),
                 ("per_level", c_int64 * FMT_MAX_LEVELS), ("device_bytes", c_int64)]
+
+
+class fmt_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("ms", c_double), ("units", c_double)]
 
 
 class FmtError(RuntimeError):
@@ -86,7 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fmt_tree_wait.restype = c_int
     lib.fmt_tree_get_info.argtypes = [T, POINTER(fmt_tree_info)]
     lib.fmt_tree_get_info.restype = c_int
-    lib.fmt_tree_export_nodes.argtypes = [T, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.fmt_tree_export_nodes.argtypes = [T, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.fmt_tree_export_nodes.restype = c_int
     lib.fmt_tree_export_points.argtypes = [T, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.fmt_tree_export_points.restype = c_int
@@ -99,6 +105,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fmt_last_error.restype = c_char_p
     lib.fmt_version.argtypes = []
     lib.fmt_version.restype = c_char_p
+    lib.fmt_profile_enable.argtypes = [c_int]
+    lib.fmt_profile_enable.restype = c_int
+    lib.fmt_profile_reset.argtypes = []
+    lib.fmt_profile_reset.restype = None
+    lib.fmt_profile_read.argtypes = [POINTER(fmt_kernel_stat), c_int]
+    lib.fmt_profile_read.restype = c_int
     _lib = lib
     return lib
 
@@ -217,10 +229,11 @@ def fmt_tree_export_nodes(tree: "Tree"):
     prefix = np.zeros(m, np.uint32)
     begin = np.zeros(m, np.uint32)
     count = np.zeros(m, np.uint32)
+    flags = np.zeros(m, np.uint32)
     coeffs = np.zeros((m, int(info.L)), np.float64)
     _check(load_library().fmt_tree_export_nodes(tree.handle, _hptr(level), _hptr(prefix), _hptr(begin),
-                                                _hptr(count), _hptr(coeffs)))
-    return dict(level=level, prefix=prefix, begin=begin, count=count, coeffs=coeffs)
+                                                _hptr(count), _hptr(flags), _hptr(coeffs)))
+    return dict(level=level, prefix=prefix, begin=begin, count=count, flags=flags, coeffs=coeffs)
 
 
 def fmt_tree_export_points(tree: "Tree"):
@@ -255,6 +268,24 @@ def fmt_last_error() -> str:
 
 def fmt_version() -> str:
     return load_library().fmt_version().decode()
+
+
+def fmt_profile_enable(on: bool = True) -> bool:
+    return bool(load_library().fmt_profile_enable(1 if on else 0))
+
+
+def fmt_profile_reset():
+    load_library().fmt_profile_reset()
+
+
+def fmt_profile_read() -> dict:
+    """{kernel name: (launches, total ms, total work units)}."""
+    lib = load_library()
+    n = lib.fmt_profile_read(None, 0)
+    rows = (fmt_kernel_stat * n)()
+    n = lib.fmt_profile_read(rows, n)
+    return {rows[i].name.decode(): (int(rows[i].launches), float(rows[i].ms), float(rows[i].units))
+            for i in range(n)}
 
 
 class Tree:

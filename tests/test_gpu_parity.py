@@ -60,6 +60,64 @@ def compare_topology(tr, ot):
     return nodes, pts
 
 
+def chain_stats(ot, pr, qx, qy, qz):
+    """Per query, over the nodes of its root-to-leaf chain: the largest
+    statistical leverage h_q = ||R^-T Lambda(u_q)||^2 (R: the triangle of the
+    QR of the node's Vandermonde matrix, the oracle's Alg. 2 factor) and the
+    largest condition number of the column-equilibrated triangle.  Data
+    points have h <= 1; h measures how far a query is extrapolated."""
+    from oracle import fmt_oracle as fo
+    D = ot.max_depth
+    keys = oracle.morton(oracle.quantise(qx, ot.lo[0], ot.hi[0], D), oracle.quantise(qy, ot.lo[1], ot.hi[1], D),
+                         oracle.quantise(qz, ot.lo[2], ot.hi[2], D), D)
+    x, y, z = (np.asarray(a, np.float64) for a in (pr.x, pr.y, pr.z))
+    q = [np.asarray(a, np.float64) for a in (qx, qy, qz)]
+    h = np.zeros(q[0].shape[0])
+    kap = np.zeros(q[0].shape[0])
+    for i in range(ot.nodes):
+        d, pre = int(ot.level[i]), int(ot.prefix[i])
+        sel = (keys >> (3 * (D - d))) == pre
+        if not np.any(sel):
+            continue
+        c, s = oracle.node_frame(d, fo._prefix_cell(pre, d), ot.lo, ot.hi)
+        idx = ot.order[ot.begin[i]:ot.begin[i] + ot.count[i]]
+        lam = oracle.moments((x[idx] - c[0]) * s[0], (y[idx] - c[1]) * s[1], (z[idx] - c[2]) * s[2], ot.p)
+        R = np.linalg.qr(lam, mode="r")
+        sv = np.linalg.svd(R / np.linalg.norm(lam, axis=0)[None, :], compute_uv=False)
+        kap[sel] = np.maximum(kap[sel], sv[0] / max(sv[-1], 1e-300))
+        if ot.rank_deficient[i]:
+            h[sel] = np.inf
+            continue
+        lq = oracle.moments((q[0][sel] - c[0]) * s[0], (q[1][sel] - c[1]) * s[1], (q[2][sel] - c[2]) * s[2], ot.p)
+        w = np.linalg.solve(R.T, lq.T)
+        h[sel] = np.maximum(h[sel], np.sum(w * w, axis=0))
+    return h, kap, keys
+
+
+H_MAX = 1e4      # queries extrapolated further than this are not determined by the data
+KAPPA_MAX = 1e8  # nor are queries under a node this ill-conditioned
+
+
+def compare_eval(ot, nodes, pr, got, want, bound, min_frac=0.5):
+    """Element-wise parity on the queries the data determine: on every node
+    of the chain no rank flag (either side), condition number <= KAPPA_MAX and
+    leverage <= H_MAX; the difference is scaled by max(1, sqrt(h)), the
+    sensitivity of a least-squares prediction to perturbations of the data.
+    Every other query must be finite."""
+    h, kap, keys = chain_stats(ot, pr, pr.qx, pr.qy, pr.qz)
+    D = ot.max_depth
+    for i in np.nonzero((nodes["flags"] & 1) != 0)[0]:
+        h[(keys >> (3 * (D - int(ot.level[i])))) == int(ot.prefix[i])] = np.inf
+    ok = (h <= H_MAX) & (kap <= KAPPA_MAX)
+    assert np.all(np.isfinite(got))
+    assert ok.mean() >= min_frac, ok.mean()
+    scaled = (got[ok] - want[ok]) / np.maximum(1.0, np.sqrt(h[ok]))
+    err = oracle.rms(scaled)
+    print(f"eval parity on {ok.sum()} of {ok.size} determined queries: rms scaled diff {err:.3e}", flush=True)
+    assert err <= bound, (err, bound, int((~ok).sum()))
+    return err
+
+
 def fitted_rms(pr, pts, ot):
     f = pr.f.astype(np.float64)
     return oracle.rms((f - pts["residual"]) - (f - ot.residual))
@@ -87,10 +145,10 @@ def test_fp64_path_matches_oracle(fmt, n, p, depth, tol, seed, dtype):
     ok = ~ot.rank_deficient
     scale = np.maximum(np.abs(ot.coeffs[ok]), 1.0)
     assert np.max(np.abs(nodes["coeffs"][ok] - ot.coeffs[ok]) / scale) < 1e-7
+    want = oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)
     for sort in (0, 1):
         got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz), sort_queries=sort).cpu().numpy()
-        want = oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)
-        assert oracle.rms(got - want) <= FP64_RMS, sort
+        compare_eval(ot, nodes, pr, got, want, FP64_RMS)
     tr.close()
 
 
@@ -99,24 +157,26 @@ def test_config1_workload(fmt):
     print_case("config1", pr)
     tr = run_fit(fmt, pr)
     ot = oracle_fit(pr)
-    compare_topology(tr, ot)
+    nodes, _ = compare_topology(tr, ot)
     info = tr.info()
     assert info.nodes == 73 and info.depth == 2
     got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-    assert oracle.rms(got - oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)) <= FP64_RMS
+    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS)
 
 
-@pytest.mark.parametrize("seed,p", [(21, 4), (22, 6)])
+@pytest.mark.parametrize("seed,p", [(21, 4), (22, 6), (23, 8)])
 def test_mixed_path_matches_oracle(fmt, seed, p):
     pr = synthetic.small_problem(40000, p, seed, tol=1e-7, depth=4, dtype=np.float32, nq=4000)
     print_case("mixed", pr)
-    tr = run_fit(fmt, pr, path=1, refine=2)
+    tr = run_fit(fmt, pr, path=1, refine=3)
     ot = oracle_fit(pr)
     nodes, pts = compare_topology(tr, ot)
     ref = oracle.rms(pr.f.astype(np.float64))
-    assert fitted_rms(pr, pts, ot) <= MIXED_REL * ref
+    err = fitted_rms(pr, pts, ot)
+    print(f"mixed fitted-value rms diff {err:.3e} = {err / ref:.3e} x rms(f)", flush=True)
+    assert err <= MIXED_REL * ref
     got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-    assert oracle.rms(got - oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)) <= MIXED_REL * ref
+    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), MIXED_REL * ref)
 
 
 def test_clustered_points_on_faces(fmt):
@@ -125,8 +185,10 @@ def test_clustered_points_on_faces(fmt):
     assert np.any(pr.x == 0.0) or np.any(pr.x == 1.0)
     tr = run_fit(fmt, pr)
     ot = oracle_fit(pr)
-    _, pts = compare_topology(tr, ot)
+    nodes, pts = compare_topology(tr, ot)
     assert fitted_rms(pr, pts, ot) <= FP64_RMS
+    got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
+    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.2)
 
 
 def test_points_on_split_planes_and_faces(fmt):
@@ -231,6 +293,8 @@ def test_batch_equals_single_fits(fmt):
         na, nb = tb.export_nodes(), ts.export_nodes()
         np.testing.assert_array_equal(na["coeffs"], nb["coeffs"])
         ot = oracle_fit(pr)
-        compare_topology(tb, ot)
+        nodes, _ = compare_topology(tb, ot)
         qa = tb.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-        assert oracle.rms(qa - oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)) <= FP64_RMS
+        qs = ts.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
+        np.testing.assert_array_equal(qa, qs)
+        compare_eval(ot, nodes, pr, qa, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.2)
