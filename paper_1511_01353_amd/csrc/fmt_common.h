@@ -53,31 +53,37 @@ __device__ __forceinline__ T monomial(const T (&pu)[P + 1], const T (&pv)[P + 1]
 }
 
 // sum_i F[i] Lambda_i(u) with compile-time indices; F read through a pointer
-// (LDS or global).  Grouped as sum_{l,m} (u^l/l! v^m/m!) * sum_n F * w^n/n!.
+// (LDS or global).  Nested Horner form, w innermost:
+//   sum_l u^l/l! sum_m v^m/m! sum_n F_lmn w^n/n!,
+// each level evaluated as c_0 + (t/1)(c_1 + (t/2)(c_2 + ...)), so every
+// coefficient costs one fused multiply-add and few values stay live.
 template <int P, typename T, typename FPtr>
 __device__ __forceinline__ T poly_eval(const FPtr F, T u, T v, T w) {
-  T pu[P + 1], pv[P + 1], pw[P + 1];
-  scaled_powers<P>(u, pu);
-  scaled_powers<P>(v, pv);
-  scaled_powers<P>(w, pw);
-  T acc = T(0);
-  // graded index of (l, m, n): rank stride of degree k plus the offset inside
-  // the degree block, (k-l)(k-l+1)/2 + (k-l-m)
+  T ud[P + 1], vd[P + 1], wd[P + 1];
 #pragma unroll
-  for (int l = 0; l <= P; ++l) {
+  for (int k = 0; k <= P; ++k) {
+    ud[k] = u * (T(1) / T(k + 1));
+    vd[k] = v * (T(1) / T(k + 1));
+    wd[k] = w * (T(1) / T(k + 1));
+  }
+  T f = T(0);
 #pragma unroll
-    for (int m = 0; m + l <= P; ++m) {
-      T s = T(0);
+  for (int l = P; l >= 0; --l) {
+    T g = T(0);
 #pragma unroll
-      for (int n = 0; n + m + l <= P; ++n) {
+    for (int m = P - l; m >= 0; --m) {
+      T h = T(0);
+#pragma unroll
+      for (int n = P - l - m; n >= 0; --n) {
         const int k = l + m + n;
         const int idx = k * (k + 1) * (k + 2) / 6 + (k - l) * (k - l + 1) / 2 + (k - l - m);
-        s += T(F[idx]) * pw[n];
+        h = T(F[idx]) + h * wd[n];
       }
-      acc += pu[l] * pv[m] * s;
+      g = h + g * vd[m];
     }
+    f = g + f * ud[l];
   }
-  return acc;
+  return f;
 }
 
 // ---------------------------------------------------------------------------

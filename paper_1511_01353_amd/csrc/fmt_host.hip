@@ -148,10 +148,25 @@ struct Workspace {
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status, params, ptrs;
   uint32_t* host_counters = nullptr;
+  char* stage = nullptr;        // pinned staging for small host-to-device copies
+  size_t stage_bytes = 0;
   std::mutex mu;
   Workspace() { hip_check(hipHostMalloc((void**)&host_counters, 64, hipHostMallocDefault), "hipHostMalloc"); }
   ~Workspace() {
     if (host_counters) (void)hipHostFree(host_counters);
+    if (stage) (void)hipHostFree(stage);
+  }
+  // Pinned buffer of at least n bytes; callers reuse it only after the
+  // stream has passed the copies that read it.
+  char* staging(size_t n) {
+    if (n > stage_bytes) {
+      if (stage) (void)hipHostFree(stage);
+      stage = nullptr;
+      stage_bytes = 0;
+      hip_check(hipHostMalloc((void**)&stage, std::max<size_t>(n, 4096), hipHostMallocDefault), "hipHostMalloc");
+      stage_bytes = std::max<size_t>(n, 4096);
+    }
+    return stage;
   }
 };
 
@@ -345,8 +360,14 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   W.ptrs.reserve(sizeof(PtrSet) * K);
   W.status.reserve(64);
   W.counters.reserve(64);
-  HIPCHK(hipMemcpyAsync(W.params.p, prm.data(), sizeof(ProblemParams) * K, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(W.ptrs.p, ptrs.data(), sizeof(PtrSet) * K, hipMemcpyHostToDevice, s));
+  // small per-fit tables go through pinned staging: parameters, pointers,
+  // then the level-0 chunk offsets
+  const size_t prm_b = sizeof(ProblemParams) * K, ptr_b = sizeof(PtrSet) * K, off_b = 4ull * (K + 1);
+  char* stg = W.staging(prm_b + ptr_b + off_b);
+  std::memcpy(stg, prm.data(), prm_b);
+  std::memcpy(stg + prm_b, ptrs.data(), ptr_b);
+  HIPCHK(hipMemcpyAsync(W.params.p, stg, prm_b, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(W.ptrs.p, stg + prm_b, ptr_b, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
   const ProblemParams* d_prm = W.params.as<ProblemParams>();
 
@@ -391,7 +412,8 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   std::vector<uint32_t> off0(K + 1, 0);
   for (int k = 0; k < K; ++k) off0[k + 1] = off0[k] + (uint32_t)((in[k].n + CHUNK - 1) / CHUNK);
   W.chunk_a.reserve(4ull * (K + 1));
-  HIPCHK(hipMemcpyAsync(W.chunk_a.p, off0.data(), 4ull * (K + 1), hipMemcpyHostToDevice, s));
+  std::memcpy(stg + prm_b + ptr_b, off0.data(), off_b);
+  HIPCHK(hipMemcpyAsync(W.chunk_a.p, stg + prm_b + ptr_b, off_b, hipMemcpyHostToDevice, s));
 
   uint32_t nnodes = (uint32_t)K, nchunks = off0[K], node0 = 0;
   uint32_t level_points = N;

@@ -5,27 +5,168 @@
 
 namespace fmt {
 
-// packed lower triangle: element (i, k), k <= i
-__device__ __forceinline__ int pk(int i, int k) { return i * (i + 1) / 2 + k; }
-
-size_t factor_doubles(int p) {
-  const size_t L = (size_t)basis_size(p);
-  return L * (L + 1) / 2 + 2 * L;
-}
+typedef double solve_d4 __attribute__((ext_vector_type(4)));
 
 // Pivots of the equilibrated Gram (unit diagonal) at or below this are
 // treated as linear dependence: the column is dropped from the factor.
 constexpr double PIVOT_EPS = 1e-13;
 
 // ---------------------------------------------------------------------------
-// Triangular solves with a packed factor, run by wave 0 alone: lane l owns
-// rows l, l+64, l+128 (registers), the pivot value of each step is broadcast
-// from its owner lane, so no workgroup barrier is needed.  Solves
-// (L L^T) z = b for the scaled right-hand side b; deflated pivots (0) give 0.
-// The caller synchronises the workgroup before reading z.
+// Blocked lower-triangular storage of an n x n symmetric matrix in LDS,
+// n padded to T blocks of 16: block (I, J), I >= J, holds 16 x 16 doubles;
+// element (r, c) of a block sits at 16 r + (c ^ (r >> 1)) so that the MFMA
+// operand pattern (16 rows, one column each) spreads over the LDS banks.
 // ---------------------------------------------------------------------------
 template <int L>
-__device__ void tri_solve_wave(const double* A, const double* dg, const double* b, double* z) {
+struct BlockShape {
+  static constexpr int T = (L + 15) / 16;
+  static constexpr int LP = 16 * T;
+  static constexpr int NBLK = T * (T + 1) / 2;
+  static constexpr int WORDS = NBLK * 256;
+};
+
+__device__ __forceinline__ int bidx(int I, int J) { return (I * (I + 1) / 2 + J) * 256; }
+__device__ __forceinline__ int bel(int r, int c) { return r * 16 + (c ^ (r >> 1)); }
+// element (i, j), i and j in the lower block triangle (i >> 4 >= j >> 4)
+__device__ __forceinline__ int belem(int i, int j) { return bidx(i >> 4, j >> 4) + bel(i & 15, j & 15); }
+
+size_t factor_doubles(int p) {
+  const int L = basis_size(p);
+  const int T = (L + 15) / 16;
+  return (size_t)T * (T + 1) / 2 * 256 + 3 * (size_t)L;
+}
+
+// ---------------------------------------------------------------------------
+// Right-looking blocked Cholesky of the unit-diagonal matrix A (blocked
+// storage, padding rows/columns set to the identity), in place, by all 256
+// threads.  Per block column J:
+//   (a) wave 0 factors the diagonal block in registers (lane = column
+//       c = lane % 16, rows lane / 16 + 4m), broadcasting pivots and column
+//       values with lane shuffles;
+//   (b) one thread per row below solves the panel row against L_JJ^T;
+//   (c) the trailing blocks take A_IK -= L_IJ L_KJ^T on float64 MFMA.
+// Deflated pivots (<= PIVOT_EPS) give a zero column; dg holds the diagonal
+// of the factor and rdg its reciprocal (0 where deflated); both hold
+// BlockShape<L>::LP entries (the padding pivots included).
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ void cholesky_blocked(double* A, double* dg, double* rdg) {
+  using S = BlockShape<L>;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int J = 0; J < S::T; ++J) {
+    // (a) diagonal block
+    if (w == 0) {
+      const int c = lane & 15, rg = lane >> 4;
+      double* blk = A + bidx(J, J);
+      double v[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int r = rg + 4 * m;
+        v[m] = r >= c ? blk[bel(r, c)] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double d = __shfl(v[k >> 2], 16 * (k & 3) + k);
+        const bool ok = d > PIVOT_EPS;
+        const double ld = ok ? sqrt(d) : 0.0;
+        const double rl = ok ? 1.0 / ld : 0.0;
+        if (c == k) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int r = rg + 4 * m;
+            if (r > k) v[m] *= rl;
+            else if (r == k) v[m] = ld;
+          }
+        }
+        // L[r][k] for this lane's rows, and L[c][k] for its column
+        double lrk[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) lrk[m] = __shfl(v[m], 16 * rg + k);
+        const double t0 = __shfl(v[0], 16 * (c & 3) + k);
+        const double t1 = __shfl(v[1], 16 * (c & 3) + k);
+        const double t2 = __shfl(v[2], 16 * (c & 3) + k);
+        const double t3 = __shfl(v[3], 16 * (c & 3) + k);
+        const int cm = c >> 2;
+        const double lck = cm == 0 ? t0 : (cm == 1 ? t1 : (cm == 2 ? t2 : t3));
+        if (c > k) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int r = rg + 4 * m;
+            if (r >= c) v[m] -= lrk[m] * lck;
+          }
+        }
+        if (lane == k) {
+          dg[16 * J + k] = ld;
+          rdg[16 * J + k] = rl;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int r = rg + 4 * m;
+        if (r >= c) blk[bel(r, c)] = v[m];
+      }
+    }
+    __syncthreads();
+    if (J + 1 == S::T) break;
+    // (b) panel: rows i of blocks I > J, x = a L_JJ^{-T}
+    {
+      const int i = 16 * (J + 1) + tid;
+      if (i < S::LP) {
+        const double* ljj = A + bidx(J, J);
+        double* row = A + bidx(i >> 4, J) + (i & 15) * 16;
+        const int sw = (i & 15) >> 1;
+        double x[16];
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) x[cc] = row[cc ^ sw];
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+          double t = x[cc];
+#pragma unroll
+          for (int m = 0; m < cc; ++m) t -= x[m] * ljj[bel(cc, m)];
+          x[cc] = t * rdg[16 * J + cc];
+        }
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) row[cc ^ sw] = x[cc];
+      }
+    }
+    __syncthreads();
+    // (c) trailing update A_IK -= L_IJ L_KJ^T for J < K <= I, on MFMA
+    {
+      const int nb = S::T - J - 1;
+      const int npair = nb * (nb + 1) / 2;
+      for (int pidx = w; pidx < npair; pidx += 4) {
+        int rem = pidx, I = J + 1;
+        while (rem > I - J - 1) { rem -= I - J; ++I; }
+        const int K = J + 1 + rem;
+        double* out = A + bidx(I, K);
+        const double* li = A + bidx(I, J);
+        const double* lk = A + bidx(K, J);
+        solve_d4 acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = out[bel((lane >> 4) + 4 * q, lane & 15)];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int kk = 4 * s4 + (lane >> 4);
+          const double av = -li[bel(lane & 15, kk)];
+          const double bv = lk[bel(lane & 15, kk)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[bel((lane >> 4) + 4 * q, lane & 15)] = acc[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (L L^T) z = b with the blocked factor, run by wave 0 alone: lane l owns rows
+// l, l+64, l+128 in registers; each step's value is broadcast from its owner
+// lane; reciprocal pivots replace divisions.  Deflated pivots give 0.  The
+// caller synchronises the workgroup before reading z.
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ void tri_solve_wave(const double* A, const double* rdg, const double* b, double* z) {
   constexpr int NS = (L + 63) / 64;
   const int lane = threadIdx.x & 63;
   double bb[NS], yy[NS];
@@ -41,14 +182,12 @@ __device__ void tri_solve_wave(const double* A, const double* dg, const double* 
     const int jn = (L - 64 * s0) < 64 ? (L - 64 * s0) : 64;
     for (int jj = 0; jj < jn; ++jj) {
       const int j = 64 * s0 + jj;
-      const double bj = __shfl(bb[s0], jj);
-      const double dj = dg[j];
-      const double yj = dj > 0.0 ? bj / dj : 0.0;
+      const double yj = __shfl(bb[s0], jj) * rdg[j];
       if (lane == jj) yy[s0] = yj;
 #pragma unroll
       for (int s = s0; s < NS; ++s) {
         const int i = lane + 64 * s;
-        if (i > j && i < L) bb[s] -= A[pk(i, j)] * yj;
+        if (i > j && i < L) bb[s] -= A[belem(i, j)] * yj;
       }
     }
   }
@@ -61,14 +200,12 @@ __device__ void tri_solve_wave(const double* A, const double* dg, const double* 
     const int jn = (L - 64 * s0) < 64 ? (L - 64 * s0) : 64;
     for (int jj = jn - 1; jj >= 0; --jj) {
       const int j = 64 * s0 + jj;
-      const double yj = __shfl(yy[s0], jj);
-      const double dj = dg[j];
-      const double zj = dj > 0.0 ? yj / dj : 0.0;
+      const double zj = __shfl(yy[s0], jj) * rdg[j];
       if (lane == jj) zz[s0] = zj;
 #pragma unroll
       for (int s = 0; s <= s0; ++s) {
         const int i = lane + 64 * s;
-        if (i < j) yy[s] -= A[pk(j, i)] * zj;
+        if (i < j) yy[s] -= A[belem(j, i)] * zj;
       }
     }
   }
@@ -79,93 +216,17 @@ __device__ void tri_solve_wave(const double* A, const double* dg, const double* 
   }
 }
 
-// Left-looking Cholesky of the packed, unit-diagonal matrix A in place (all
-// threads of the workgroup).  At step j each active row's dot product over
-// the finished columns is split over a group of G lanes (G a power of two,
-// the largest with (L - j) * G <= 256) and reduced by a fixed butterfly.
-// Pivots <= PIVOT_EPS are deflated: the column is dropped (dg = 0).
+// Factor, solve, write F and (optionally) the factor; shared tail of both
+// K6 variants.  A holds the equilibrated matrix (blocked, padding = identity),
+// b the scaled right-hand side, sc the equilibration scales.
 template <int L>
-__device__ void cholesky_lds(double* A, double* dg) {
+__device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dg, double* rdg,
+                                                   const double* sc, const LevelArgs& a, uint32_t k, uint32_t node,
+                                                   double* fac) {
+  using S = BlockShape<L>;
   const int tid = threadIdx.x;
-  for (int j = 0; j < L; ++j) {
-    const int rows = L - j;
-    int lg2 = 0;
-    while (lg2 < 6 && (rows << (lg2 + 1)) <= 256) ++lg2;
-    const int G = 1 << lg2;
-    const int r = tid >> lg2, q0 = tid & (G - 1);
-    double t = 0.0;
-    if (r < rows) {
-      const double* ri = A + pk(j + r, 0);
-      const double* rj = A + pk(j, 0);
-      for (int q = q0; q < j; q += G) t += ri[q] * rj[q];
-    }
-    for (int off = G >> 1; off >= 1; off >>= 1) t += __shfl_xor(t, off);
-    if (r < rows && q0 == 0) A[pk(j + r, j)] -= t;
-    __syncthreads();
-    const double d = A[pk(j, j)];
-    const bool ok = d > PIVOT_EPS;
-    const double inv = ok ? 1.0 / sqrt(d) : 0.0;
-    const int i = j + 1 + tid;
-    if (i < L) A[pk(i, j)] *= inv;
-    if (tid == 0) dg[j] = ok ? sqrt(d) : 0.0;
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// K6: sum a node's chunk partials, equilibrate, Cholesky, solve for F.
-// One workgroup per node.  The factor is kept for the refinement sweeps.
-// ---------------------------------------------------------------------------
-template <int P>
-__global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __restrict__ partial,
-                                               double* __restrict__ fac) {
-  constexpr int L = basis_size(P);
-  constexpr int T = pad16(L + 1) / 16;
-  constexpr int NPAIR = T * (T + 1) / 2;
-  constexpr int NPK = L * (L + 1) / 2;
-  __shared__ double A[NPK];
-  __shared__ double b[L], z[L], dg[L], sc[L];
-  const int tid = threadIdx.x;
-  const uint32_t k = blockIdx.x;
-  const uint32_t node = a.node0 + k;
-  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
-
-  // assemble: packed lower triangle of Lambda^T Lambda, then Lambda^T r
-  for (int e = tid; e < NPK + L; e += 256) {
-    int i, kk;
-    if (e < NPK) {
-      i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while (pk(i + 1, 0) <= e) ++i;
-      while (pk(i, 0) > e) --i;
-      kk = e - pk(i, 0);
-    } else {
-      i = e - NPK;
-      kk = L;
-    }
-    const int lo = i < kk ? i : kk, hi = i < kk ? kk : i;
-    const int t1 = lo >> 4, t2 = hi >> 4;
-    const int j = t1 * T - t1 * (t1 - 1) / 2 + (t2 - t1);
-    const size_t off = (size_t)j * 256 + (lo & 15) * 16 + (hi & 15);
-    const double s = partial[(size_t)c0 * NPAIR * 256 + off];
-    if (e < NPK) A[e] = s; else b[i] = s;
-  }
-  __syncthreads();
-  // equilibrate to a unit diagonal
-  for (int i = tid; i < L; i += 256) {
-    const double d = A[pk(i, i)];
-    sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < NPK; e += 256) {
-    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while (pk(i + 1, 0) <= e) ++i;
-    while (pk(i, 0) > e) --i;
-    A[e] *= sc[i] * sc[e - pk(i, 0)];
-  }
-  for (int i = tid; i < L; i += 256) b[i] *= sc[i];
-  __syncthreads();
-  cholesky_lds<L>(A, dg);
-  if (tid < 64) tri_solve_wave<L>(A, dg, b, z);
+  cholesky_blocked<L>(A, dg, rdg);
+  if (tid < 64) tri_solve_wave<L>(A, rdg, b, z);
   __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
   bool deflated = false;
@@ -174,21 +235,71 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
     if (dg[i] == 0.0) deflated = true;
   }
   if (fac) {
-    double* fo = fac + (size_t)k * (NPK + 2 * L);
-    for (int e = tid; e < NPK; e += 256) fo[e] = A[e];
+    double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
+    for (int e = tid; e < S::WORDS; e += 256) fo[e] = A[e];
     for (int i = tid; i < L; i += 256) {
-      fo[NPK + i] = dg[i];
-      fo[NPK + L + i] = sc[i];
+      fo[S::WORDS + i] = dg[i];
+      fo[S::WORDS + L + i] = rdg[i];
+      fo[S::WORDS + 2 * L + i] = sc[i];
     }
   }
   if (deflated) atomicOr(a.nt.flags + node, FLAG_DEFLATED);
 }
 
+// Identity on the padding rows and columns [L, LP) of the blocked matrix.
+template <int L>
+__device__ __forceinline__ void pad_identity(double* A) {
+  using S = BlockShape<L>;
+  for (int i = L + threadIdx.x; i < S::LP; i += 256)
+    for (int q = 0; q <= i; ++q) A[belem(i, q)] = q == i ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// K6 from Gram partials (the MFMA Gram layout: 16x16 blocks of the upper
+// triangle of [Lambda | r]^T [Lambda | r]).  One workgroup per node.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __restrict__ partial,
+                                               double* __restrict__ fac) {
+  constexpr int L = basis_size(P);
+  constexpr int TG = pad16(L + 1) / 16;
+  constexpr int NPAIR = TG * (TG + 1) / 2;
+  using S = BlockShape<L>;
+  __shared__ double A[S::WORDS];
+  __shared__ double b[L], z[L], dg[S::LP], rdg[S::LP], sc[L];   // pivots cover the padding too
+  const int tid = threadIdx.x;
+  const uint32_t k = blockIdx.x;
+  const uint32_t node = a.node0 + k;
+  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
+  const double* G = partial + (size_t)c0 * NPAIR * 256;
+  // Gram element (i, j) of the augmented matrix, i <= j
+  auto gram = [&](int i, int j) {
+    const int t1 = i >> 4, t2 = j >> 4;
+    const int pj = t1 * TG - t1 * (t1 - 1) / 2 + (t2 - t1);
+    return G[(size_t)pj * 256 + (i & 15) * 16 + (j & 15)];
+  };
+  for (int i = tid; i < L; i += 256) {
+    const double d = gram(i, i);
+    sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < L; i += 256) {
+    const double si = sc[i];
+    for (int q = 0; q <= i; ++q) A[belem(i, q)] = gram(q, i) * si * sc[q];
+    b[i] = gram(i, L) * si;
+  }
+  pad_identity<L>(A);
+  __syncthreads();
+  factor_solve_store<L>(A, b, z, dg, rdg, sc, a, k, node, fac);
+}
+
+// ---------------------------------------------------------------------------
 // K6 from power moments: G_ik = M[alpha_i + alpha_k] / (alpha_i! alpha_k!),
 // b_i = B[alpha_i] / alpha_i!.  Equilibration is folded into the assembly:
 // with s_i = 1 / sqrt(G_ii) and w_i = s_i / alpha_i!, the scaled matrix is
 // A_ik = M[alpha_i + alpha_k] w_i w_k and the scaled right-hand side
 // B[alpha_i] w_i.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ int graded(int a, int b, int c) {
   const int k = a + b + c;
   return k * (k + 1) * (k + 2) / 6 + (k - a) * (k - a + 1) / 2 + (k - a - b);
@@ -198,13 +309,13 @@ template <int P>
 __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __restrict__ part,
                                                  double* __restrict__ fac) {
   constexpr int L = basis_size(P);
-  constexpr int NPK = L * (L + 1) / 2;
   constexpr int NM = basis_size(2 * P);
   constexpr int NOUT = NM + L + 1;
   constexpr Basis<P> B{};
-  __shared__ double A[NPK];
+  using S = BlockShape<L>;
+  __shared__ double A[S::WORDS];
   __shared__ double mom[NOUT];
-  __shared__ double b[L], z[L], dg[L], sc[L], wv[L];
+  __shared__ double b[L], z[L], dg[S::LP], rdg[S::LP], sc[L], wv[L];   // pivots cover the padding too
   __shared__ int ex[L][3];
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
@@ -229,29 +340,12 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   for (int i = tid; i < L; i += 256) {
     const int xi = ex[i][0], yi = ex[i][1], zi = ex[i][2];
     const double wi = wv[i];
-    double* row = A + pk(i, 0);
     for (int q = 0; q <= i; ++q)
-      row[q] = mom[graded(xi + ex[q][0], yi + ex[q][1], zi + ex[q][2])] * wi * wv[q];
+      A[belem(i, q)] = mom[graded(xi + ex[q][0], yi + ex[q][1], zi + ex[q][2])] * wi * wv[q];
   }
+  pad_identity<L>(A);
   __syncthreads();
-  cholesky_lds<L>(A, dg);
-  if (tid < 64) tri_solve_wave<L>(A, dg, b, z);
-  __syncthreads();
-  double* F = a.nt.coef + (size_t)node * L;
-  bool deflated = false;
-  for (int i = tid; i < L; i += 256) {
-    F[i] = sc[i] * z[i];
-    if (dg[i] == 0.0) deflated = true;
-  }
-  if (fac) {
-    double* fo = fac + (size_t)k * (NPK + 2 * L);
-    for (int e = tid; e < NPK; e += 256) fo[e] = A[e];
-    for (int i = tid; i < L; i += 256) {
-      fo[NPK + i] = dg[i];
-      fo[NPK + L + i] = sc[i];
-    }
-  }
-  if (deflated) atomicOr(a.nt.flags + node, FLAG_DEFLATED);
+  factor_solve_store<L>(A, b, z, dg, rdg, sc, a, k, node, fac);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,23 +357,23 @@ template <int P>
 __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double* __restrict__ part_b,
                                                       const double* __restrict__ fac) {
   constexpr int L = basis_size(P);
-  constexpr int NPK = L * (L + 1) / 2;
   constexpr Basis<P> B{};
-  __shared__ double A[NPK];
-  __shared__ double b[L], z[L], dg[L], sc[L];
+  using S = BlockShape<L>;
+  __shared__ double A[S::WORDS];
+  __shared__ double b[L], z[L], rdg[L], sc[L];
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
-  const double* fo = fac + (size_t)k * (NPK + 2 * L);
-  for (int e = tid; e < NPK; e += 256) A[e] = fo[e];
+  const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
+  for (int e = tid; e < S::WORDS; e += 256) A[e] = fo[e];
   for (int i = tid; i < L; i += 256) {
-    dg[i] = fo[NPK + i];
-    sc[i] = fo[NPK + L + i];
-    b[i] = part_b[(size_t)c0 * L + i] * B.inv_fact[i] * fo[NPK + L + i];
+    rdg[i] = fo[S::WORDS + L + i];
+    sc[i] = fo[S::WORDS + 2 * L + i];
+    b[i] = part_b[(size_t)c0 * L + i] * B.inv_fact[i] * fo[S::WORDS + 2 * L + i];
   }
   __syncthreads();
-  if (tid < 64) tri_solve_wave<L>(A, dg, b, z);
+  if (tid < 64) tri_solve_wave<L>(A, rdg, b, z);
   __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
   for (int i = tid; i < L; i += 256) F[i] += sc[i] * z[i];

@@ -134,7 +134,7 @@ __device__ __forceinline__ void accumulate(std::index_sequence<T...>, const doub
 // red: 16 x 65 doubles of LDS owned by this wave.
 template <int P, int MODE, int G, typename TIN>
 __device__ __forceinline__ void moments_group(const LevelArgs& a, uint32_t start, uint32_t end, const double* geo,
-                                              const double* Fs, double* red, double* out) {
+                                              const double* rp, double* red, double* out) {
   constexpr const MomentPlan<P, MODE>& M = Plan<P, MODE>::v;
   constexpr int NA = M.load[G] > 0 ? M.load[G] : 1;
   static_assert(NA <= MomentPlan<P, MODE>::OUTW, "a moment group exceeds the output map");
@@ -148,8 +148,7 @@ __device__ __forceinline__ void moments_group(const LevelArgs& a, uint32_t start
     double x, y, z;
     load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
     const double u = (x - cx) * sx, v = (y - cy) * sy, w = (z - cz) * sz;
-    double wt = a.r[i];
-    if constexpr (MODE == 1) wt -= poly_eval<P, double>(Fs, u, v, w);
+    const double wt = MODE == 1 ? rp[i - start] : a.r[i];
     double pu[P2 + 1], pv[P2 + 1], pw[P2 + 1];
     pu[0] = pv[0] = pw[0] = 1.0;
 #pragma unroll
@@ -188,10 +187,10 @@ __device__ __forceinline__ void moments_group(const LevelArgs& a, uint32_t start
 
 template <int P, int MODE, typename TIN, int G = 0>
 __device__ __forceinline__ void dispatch_group(int g, const LevelArgs& a, uint32_t start, uint32_t end,
-                                               const double* geo, const double* Fs, double* red, double* out) {
+                                               const double* geo, const double* rp, double* red, double* out) {
   if constexpr (G < MomentPlan<P, MODE>::NG) {
-    if (g == G) moments_group<P, MODE, G, TIN>(a, start, end, geo, Fs, red, out);
-    else dispatch_group<P, MODE, TIN, G + 1>(g, a, start, end, geo, Fs, red, out);
+    if (g == G) moments_group<P, MODE, G, TIN>(a, start, end, geo, rp, red, out);
+    else dispatch_group<P, MODE, TIN, G + 1>(g, a, start, end, geo, rp, red, out);
   }
 }
 
@@ -200,6 +199,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NW * 64)) k_moments(Leve
   using MP = MomentPlan<P, MODE>;
   constexpr int L = basis_size(P);
   __shared__ double Fs[MODE == 1 ? L : 1];
+  __shared__ double rp[MODE == 1 ? CHUNK : 1];   // r' = r - Lambda F of the chunk's points
   __shared__ double red[MP::NW][16 * 65];
   const uint32_t g = blockIdx.x;
   const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
@@ -211,11 +211,21 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NW * 64)) k_moments(Leve
   if constexpr (MODE == 1) {
     for (int i = threadIdx.x; i < L; i += MP::NW * 64) Fs[i] = a.nt.coef[(size_t)node * L + i];
     __syncthreads();
+    // r' once per point; coefficients read through a volatile view so that
+    // they stay in LDS instead of occupying registers
+    const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
+    const volatile double* Fv = Fs;
+    for (uint32_t i = start + threadIdx.x; i < end; i += MP::NW * 64) {
+      double x, y, z;
+      load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
+      rp[i - start] = a.r[i] - poly_eval<P, double>(Fv, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
+    }
+    __syncthreads();
   }
   double* out = part + (size_t)g * MP::NOUT;
   const int w = threadIdx.x >> 6;
   for (int pass = 0; pass < MP::NPASS; ++pass)
-    dispatch_group<P, MODE, TIN>(pass * MP::NW + w, a, start, end, geo, Fs, red[w], out);
+    dispatch_group<P, MODE, TIN>(pass * MP::NW + w, a, start, end, geo, rp, red[w], out);
 }
 
 template <int P>
