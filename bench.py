@@ -57,11 +57,13 @@ def solve_flops_per_node(L: int) -> float:
     return L ** 3 / 3.0 + 2.0 * L * L
 
 
-def eval_flops_per_query_node(L: int) -> float:
-    return 2 * L + L
+def eval_flops_per_query(L: int) -> float:
+    # one multiply-add per coefficient of the node's composite polynomial
+    return 2.0 * L
 
 
-def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, steps: int, key_passes: int):
+def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, steps: int, key_passes: int,
+                     eval_key_passes: int):
     """Achieved rate of each kernel class over the timed steps: algorithmic work
     (flops or bytes per unit times the units the launches covered) divided by
     the summed launch durations measured with HIP events."""
@@ -88,8 +90,24 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
     add("residual", "hbm", 3 * coord_bytes + 8 + 8 + 4, "GB/s", PEAK_HBM_GBS)
     # sort: per pass read and write key and index
     add("sort", "hbm", 16.0 * key_passes, "GB/s", PEAK_HBM_GBS)
-    add("eval_sort", "hbm", 16.0 * key_passes, "GB/s", PEAK_HBM_GBS)
+    add("eval_sort", "hbm", 16.0 * eval_key_passes, "GB/s", PEAK_HBM_GBS)
     add("gather", "hbm", 4 + 3 * coord_bytes + coord_bytes + 3 * coord_bytes + 8, "GB/s", PEAK_HBM_GBS)
+    # query keys: coordinates in, key out
+    add("eval_keys", "hbm", 3 * coord_bytes + 4, "GB/s", PEAK_HBM_GBS)
+    # evaluation: the bound is whichever of its flops (2L per query) and its
+    # bytes (coordinates in, value out) takes longer at peak
+    t_flop = eval_flops_per_query(L) / (PEAK_TFLOPS["fp64"] * 1e12)
+    t_byte = (3 * coord_bytes + 8) / (PEAK_HBM_GBS * 1e9)
+    if t_flop >= t_byte:
+        add("eval", "alu", eval_flops_per_query(L), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    else:
+        add("eval", "hbm", 3 * coord_bytes + 8, "GB/s", PEAK_HBM_GBS)
+    # chunk reduction: units are partial doubles read (the result writes are
+    # one chunk's worth per node)
+    add("gram_reduce", "hbm", 8.0, "GB/s", PEAK_HBM_GBS)
+    # child activation: 16 partial doubles in, 8 begins + 8 counts + mask +
+    # active count out, begin read, per node
+    add("children", "hbm", 16 * 8 + 16 * 4 + 12, "GB/s", PEAK_HBM_GBS)
     return out
 
 
@@ -107,6 +125,9 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="time only the headline path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 17)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, copy this many MiB device to device (a plain copy kernel of known size "
+                         "against which hardware byte counters are scaled)")
     return ap.parse_args()
 
 
@@ -191,11 +212,13 @@ def main():
 
     h = results[args.path]
     key_passes = max(1, (3 * pr.max_depth + 7) // 8)
-    roofs = kernel_rooflines(h["kernels"], pr.p, L, args.path, pr.x.dtype.itemsize, args.steps, key_passes)
-    # the dominant kernel of the headline path's step
-    dom = max(h["kernels"].items(), key=lambda kv: kv[1]["ms_per_step"])[0]
-    roof = dict(kernel=dom, **roofs[dom]) if dom in roofs else dict(kernel=dom, bound=None, achieved=None,
-                                                                    peak=None, unit=None, frac=None)
+    eval_key_passes = max(1, (3 * (len(h["per_level"]) - 1) + 7) // 8)
+    roofs = kernel_rooflines(h["kernels"], pr.p, L, args.path, pr.x.dtype.itemsize, args.steps, key_passes,
+                             eval_key_passes)
+    # the dominant kernel of the headline path's step (by time) among those
+    # with a roofline definition
+    dom = max((kv for kv in h["kernels"].items() if kv[0] in roofs), key=lambda kv: kv[1]["ms_per_step"])[0]
+    roof = dict(kernel=dom, **roofs[dom])
     roof["traffic"] = None
     gram_roof = roofs.get("gram")
 
@@ -235,6 +258,14 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb}), file=sys.stderr)
 
 
 def cpu_baseline(pr, sample: int):

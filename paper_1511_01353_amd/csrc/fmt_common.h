@@ -37,6 +37,12 @@ struct Basis {
   }
 };
 
+// Position of the monomial u^a v^b w^c in the graded order.
+__host__ __device__ __forceinline__ int graded(int a, int b, int c) {
+  const int k = a + b + c;
+  return k * (k + 1) * (k + 2) / 6 + (k - a) * (k - a + 1) / 2 + (k - a - b);
+}
+
 // Scaled powers t^k / k! for k = 0..P, built by repeated multiplication.
 template <int P, typename T>
 __device__ __forceinline__ void scaled_powers(T t, T (&pw)[P + 1]) {
@@ -84,6 +90,81 @@ __device__ __forceinline__ T poly_eval(const FPtr F, T u, T v, T w) {
     f = g + f * ud[l];
   }
   return f;
+}
+
+// poly_eval for NPT points at once: every coefficient is read once and feeds
+// NPT independent Horner chains.
+template <int P, int NPT, typename FPtr>
+__device__ __forceinline__ void poly_eval_multi(const FPtr F, const double (&u)[NPT], const double (&v)[NPT],
+                                                const double (&w)[NPT], double (&out)[NPT]) {
+  double f[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) f[q] = 0.0;
+#pragma unroll
+  for (int l = P; l >= 0; --l) {
+    double g[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) g[q] = 0.0;
+#pragma unroll
+    for (int m = P - l; m >= 0; --m) {
+      double h[NPT];
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) h[q] = 0.0;
+#pragma unroll
+      for (int n = P - l - m; n >= 0; --n) {
+        const int k = l + m + n;
+        const int idx = k * (k + 1) * (k + 2) / 6 + (k - l) * (k - l + 1) / 2 + (k - l - m);
+        const double c = F[idx];
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) h[q] = c + h[q] * (w[q] * (1.0 / (double)(n + 1)));
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) g[q] = h[q] + g[q] * (v[q] * (1.0 / (double)(m + 1)));
+    }
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) f[q] = g[q] + f[q] * (u[q] * (1.0 / (double)(l + 1)));
+  }
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) out[q] = f[q];
+}
+
+// sum_i C[i] u^a v^b w^c for NPT points at once, with C the coefficients
+// already divided by a! b! c! (plain monomials, so a point needs only u, v,
+// w).  Every coefficient is read once and feeds NPT independent Horner
+// chains, so the reads may come from LDS through a volatile view without
+// serialising each chain on its loads.
+template <int P, int NPT, typename FPtr>
+__device__ __forceinline__ void poly_eval_plain_multi(const FPtr C, const double (&u)[NPT], const double (&v)[NPT],
+                                                      const double (&w)[NPT], double (&out)[NPT]) {
+  double f[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) f[q] = 0.0;
+#pragma unroll
+  for (int l = P; l >= 0; --l) {
+    double g[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) g[q] = 0.0;
+#pragma unroll
+    for (int m = P - l; m >= 0; --m) {
+      double h[NPT];
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) h[q] = 0.0;
+#pragma unroll
+      for (int n = P - l - m; n >= 0; --n) {
+        const int k = l + m + n;
+        const int idx = k * (k + 1) * (k + 2) / 6 + (k - l) * (k - l + 1) / 2 + (k - l - m);
+        const double c = C[idx];
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) h[q] = fma(h[q], w[q], c);
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) g[q] = fma(g[q], v[q], h[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) f[q] = fma(f[q], u[q], g[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) out[q] = f[q];
 }
 
 // ---------------------------------------------------------------------------

@@ -55,9 +55,9 @@ struct ProfRecord {
   double units;   // points (or queries) the launch covered
 };
 const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce", "solve", "refine_sweep",
-                              "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval"};
+                              "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval", "compose"};
 enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
-       KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COUNT };
+       KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_COUNT };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof_pending;
@@ -212,6 +212,16 @@ struct Forest {
   bool host_ready = false;
   std::vector<uint32_t> h_begin, h_count, h_prefix, h_level, h_problem, h_flags;
   std::vector<double> h_coef;
+  // deepest level holding a node
+  int depth_present = 0;
+  // composite coefficients (each node's chain of polynomials in its own
+  // frame), built on the first evaluation; `composed` marks their completion
+  std::mutex compose_mu;
+  DevBuf nb_ccoef;
+  hipEvent_t composed = nullptr;
+  ~Forest() {
+    if (composed) (void)hipEventDestroy(composed);
+  }
 
   NodeTable table() const {
     NodeTable t;
@@ -231,7 +241,7 @@ struct Forest {
   size_t device_bytes() const {
     return nb_begin.bytes + nb_count.bytes + nb_prefix.bytes + nb_level.bytes + nb_problem.bytes + nb_parent.bytes +
            nb_first_child.bytes + nb_child_mask.bytes + nb_flags.bytes + nb_geo.bytes + nb_coef.bytes + skey.bytes +
-           order.bytes + resid.bytes;
+           order.bytes + resid.bytes + nb_ccoef.bytes;
   }
   void alloc_nodes(uint32_t cap) {
     const size_t u = sizeof(uint32_t) * (size_t)cap;
@@ -433,7 +443,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       W.fac.reserve(8ull * fd * nnodes);
       W.part_b.reserve(8ull * rbd * nchunks);
     }
-    W.part_ss.reserve(8ull * 8 * nchunks);
+    W.part_ss.reserve(8ull * 16 * nchunks);
     W.cbeg.reserve(4ull * 8 * nnodes);
     W.ccnt.reserve(4ull * 8 * nnodes);
     W.nact.reserve(4ull * nnodes);
@@ -461,7 +471,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       else HIPCHK(launch_gram(F->p, F->path, dtype, a, W.partial.as<double>(), s));
     }
     if (multi) {
-      ProfScope ps(KN_REDUCE, nchunks, s);
+      ProfScope ps(KN_REDUCE, (double)nchunks * (double)gpd, s);
       HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), (uint32_t)gpd, s));
     }
     {
@@ -482,7 +492,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     {
       ProfScope ps(KN_RESID, level_points, s);
       HIPCHK(launch_residual(F->p, dtype, a, W.part_ss.as<double>(), s));
-      if (multi && d < F->D) HIPCHK(launch_chunk_reduce(a, W.part_ss.as<double>(), 8, s));
+      if (multi && d < F->D) HIPCHK(launch_chunk_reduce(a, W.part_ss.as<double>(), 16, s));
     }
     F->level_points.push_back(level_points);
     if (d == F->D) {
@@ -509,6 +519,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     std::swap(cur_off, next_off);
   }
   F->nodes = node0;
+  F->depth_present = (int)F->level_start.size() - 1;
   HIPCHK(launch_check_coef(F->p, nt, F->nodes, W.status.as<uint32_t>(), s));
 
   // hand the node table to the forest; copy it down to its exact size only
@@ -666,6 +677,24 @@ fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const v
   });
 }
 
+// Composite coefficients of a forest, built once on the first evaluation;
+// every evaluating stream waits for their completion.
+static void ensure_composed(Forest& F, hipStream_t s) {
+  std::lock_guard<std::mutex> g(F.compose_mu);
+  if (!F.composed) {
+    F.nb_ccoef.alloc(sizeof(double) * (size_t)F.L * std::max<uint32_t>(F.nodes, 1));
+    {
+      ProfScope ps(KN_COMPOSE, F.nodes, s);
+      HIPCHK(launch_compose(F.p, F.table(), F.nodes, F.nb_ccoef.as<double>(), s));
+    }
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, s));
+    F.composed = ev;
+  }
+  HIPCHK(hipStreamWaitEvent(s, F.composed, 0));
+}
+
 fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const void* qz, int64_t nq, int dtype,
                     double* out, int sort_queries, void* stream) {
   return guard([&] {
@@ -675,50 +704,60 @@ fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const 
     if (nq == 0) return;
     if (!qx || !qy || !qz || !out) fail(FMT_E_INVALID_ARG, "NULL query or output pointer");
     hipStream_t s = (hipStream_t)stream;
-    const Forest& F = *tree->forest;
+    Forest& F = *tree->forest;
+    ensure_composed(F, s);
     EvalTree t;
     t.nt = F.table();
     t.root = F.probs[tree->problem].root;
-    t.D = F.D;
+    // query cells at the deepest level present: the same top bits as cells at
+    // max_depth (the scale differs by an exact power of two)
+    t.D = F.depth_present;
     t.prm = F.probs[tree->problem].prm;
+    for (int a = 0; a < 3; ++a) t.prm.qscale[a] = std::ldexp(t.prm.qscale[a], t.D - F.D);
+    const double* cc = F.nb_ccoef.as<double>();
     const uint32_t n = (uint32_t)nq;
-    const bool sort = sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) && F.nodes > 64);
+    const bool sort = t.D > 0 && (sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) && F.nodes > 64));
     if (!sort) {
       ProfScope ps(KN_EVAL, n, s);
-      HIPCHK(launch_eval(F.p, dtype, t, qx, qy, qz, nullptr, nullptr, n, out, s));
+      HIPCHK(launch_eval(F.p, dtype, t, cc, qx, qy, qz, nullptr, nullptr, n, out, s));
       return;
     }
     const size_t esz = dtype == FMT_F32 ? 4 : 8;
     const size_t words = radix_sort_scratch_words(n);
-    const size_t bytes = 16ull * n + 4 * words + 3 * esz * n + 1024;
+    const size_t pbytes = (esz * n + 255) & ~(size_t)255;
+    const size_t bytes = 6 * pbytes + 16ull * n + 4 * words + 256;
     char* base = nullptr;
     HIPCHK(hipMallocAsync((void**)&base, bytes, s));
-    uint32_t* k0 = (uint32_t*)base;
+    void* pay[3];
+    void* pay_alt[3];
+    for (int q = 0; q < 3; ++q) {
+      pay[q] = base + q * pbytes;
+      pay_alt[q] = base + (3 + q) * pbytes;
+    }
+    uint32_t* k0 = (uint32_t*)(base + 6 * pbytes);
     uint32_t* v0 = k0 + n;
     uint32_t* k1 = v0 + n;
     uint32_t* v1 = k1 + n;
     uint32_t* scr = v1 + n;
-    char* cbase = (char*)(scr + words);
-    cbase = (char*)(((uintptr_t)cbase + 255) & ~(uintptr_t)255);
-    void* sx = cbase;
-    void* sy = cbase + esz * n;
-    void* sz = cbase + 2 * esz * n;
+    const void* pin[3] = {qx, qy, qz};
     hipError_t e;
     {
       ProfScope ps(KN_EKEYS, n, s);
-      e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, F.D, k0, s);
+      e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, t.D, k0, s);
     }
     bool in_alt = false;
     {
+      // keys with the query coordinates and positions as payload
       ProfScope ps(KN_ESORT, n, s);
-      if (e == hipSuccess) e = radix_sort(k0, v0, k1, v1, n, 3 * F.D, true, scr, s, &in_alt);
+      if (e == hipSuccess)
+        e = radix_sort_payload3(dtype, k0, v0, k1, v1, pin, pay, pay_alt, n, 3 * t.D, scr, s, &in_alt);
     }
     uint32_t* ks = in_alt ? k1 : k0;
     uint32_t* vs = in_alt ? v1 : v0;
+    void* const* sq = in_alt ? pay_alt : pay;
     {
       ProfScope ps(KN_EVAL, n, s);
-      if (e == hipSuccess) e = launch_permute3(dtype, qx, qy, qz, vs, n, sx, sy, sz, s);
-      if (e == hipSuccess) e = launch_eval(F.p, dtype, t, sx, sy, sz, vs, ks, n, out, s);
+      if (e == hipSuccess) e = launch_eval(F.p, dtype, t, cc, sq[0], sq[1], sq[2], vs, ks, n, out, s);
     }
     hipError_t e2 = hipFreeAsync(base, s);
     hip_check(e, "eval");
@@ -888,6 +927,7 @@ fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_
     F->probs[0].root = 0;
     F->probs[0].n = 0;
     F->level_start.assign(1, 0);
+    F->depth_present = (int)*std::max_element(hl.begin(), hl.end());
     fmt_tree* t = new fmt_tree();
     t->forest = F;
     t->problem = 0;

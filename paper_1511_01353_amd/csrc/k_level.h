@@ -27,8 +27,8 @@ struct LevelArgs {
 struct EvalTree {
   NodeTable nt;
   uint32_t root;
-  int D;
-  ProblemParams prm;
+  int D;               // deepest level holding a node (query keys use this depth)
+  ProblemParams prm;   // qscale = 2^D / (hi - lo) for that D
 };
 
 // Doubles of one chunk's partial Gram (upper-triangular 16x16 blocks of the
@@ -58,8 +58,12 @@ hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uin
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, hipStream_t s);
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
-hipError_t launch_eval(int p, int dtype, const EvalTree& t, const void* qx, const void* qy, const void* qz,
-                       const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out, hipStream_t s);
+// Composite coefficients of every node (its chain's polynomials in its frame).
+hipError_t launch_compose(int p, const NodeTable& nt, uint32_t nodes, double* cc, hipStream_t s);
+// perm/skeys: sorted mode (query order and sorted keys), else both null.
+hipError_t launch_eval(int p, int dtype, const EvalTree& t, const double* cc, const void* qx, const void* qy,
+                       const void* qz, const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out,
+                       hipStream_t s);
 
 // Device helpers shared by the level kernels ---------------------------------
 

@@ -36,79 +36,81 @@ size_t factor_doubles(int p) {
   return (size_t)T * (T + 1) / 2 * 256 + 3 * (size_t)L;
 }
 
+// Value of a double held by lane `l` (a wave-uniform index), in scalar
+// registers: two v_readlane_b32, no LDS round trip.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 1 / d for a pivot of the equilibrated matrix (0 < d <= ~1): the hardware
+// reciprocal estimate refined by two Newton steps (error well under 1 ulp
+// of the estimate's square), instead of the full IEEE division sequence.
+__device__ __forceinline__ double pivot_recip(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-d, x, 1.0);
+  return fma(x, e, x);
+}
+
 // ---------------------------------------------------------------------------
-// Right-looking blocked Cholesky of the unit-diagonal matrix A (blocked
-// storage, padding rows/columns set to the identity), in place, by all 256
-// threads.  Per block column J:
-//   (a) wave 0 factors the diagonal block in registers (lane = column
-//       c = lane % 16, rows lane / 16 + 4m), broadcasting pivots and column
-//       values with lane shuffles;
-//   (b) one thread per row below solves the panel row against L_JJ^T;
-//   (c) the trailing blocks take A_IK -= L_IJ L_KJ^T on float64 MFMA.
-// Deflated pivots (<= PIVOT_EPS) give a zero column; dg holds the diagonal
-// of the factor and rdg its reciprocal (0 where deflated); both hold
-// BlockShape<L>::LP entries (the padding pivots included).
+// Right-looking blocked LDL^T factorisation of the unit-diagonal matrix A
+// (blocked storage, padding rows/columns set to the identity), in place, by
+// all 256 threads.  Afterwards the strictly lower part of A holds the unit
+// lower factor L; the diagonal and the strict upper part of every diagonal
+// block hold 0, and D lives in dv (with iv = D^-1, 0 where deflated).  The
+// zeros let the triangular solves run without per-step masks.  The 16 words
+// after the blocked storage, A[WORDS .. WORDS + 15], are a zero row (the
+// caller zeroes them).  Per block column J:
+//   (a) wave 0 factors the diagonal block with lane r holding row r in
+//       registers; pivots and column entries reach the other lanes through
+//       v_readlane (scalar registers).  Entries above the diagonal of a lane's
+//       row collect values that are never read, so the updates need no mask;
+//   (b) one thread per row below solves u L_JJ^T = a in axpy order and keeps
+//       L = u D^-1;
+//   (c) the trailing blocks take A_IK -= (L_IJ D_J) L_KJ^T on float64 MFMA.
+// Pivots at or below PIVOT_EPS are deflated: their inverse is 0, so their
+// column of L is 0 and the solve gives that unknown 0.
 // ---------------------------------------------------------------------------
 template <int L>
-__device__ void cholesky_blocked(double* A, double* dg, double* rdg) {
+__device__ __forceinline__ void ldl_blocked(double* A, double* dv, double* iv) {
   using S = BlockShape<L>;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   for (int J = 0; J < S::T; ++J) {
     // (a) diagonal block
     if (w == 0) {
-      const int c = lane & 15, rg = lane >> 4;
       double* blk = A + bidx(J, J);
-      double v[4];
+      const int r = lane;
+      double a[16];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int r = rg + 4 * m;
-        v[m] = r >= c ? blk[bel(r, c)] : 0.0;
-      }
+      for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? blk[bel(r & 15, c)] : 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const double d = __shfl(v[k >> 2], 16 * (k & 3) + k);
-        const bool ok = d > PIVOT_EPS;
-        const double ld = ok ? sqrt(d) : 0.0;
-        const double rl = ok ? 1.0 / ld : 0.0;
-        if (c == k) {
+        const double d = lane_value(a[k], k);
+        const double inv = d > PIVOT_EPS ? pivot_recip(d) : 0.0;
+        const double lk = a[k] * inv;                  // L[r][k] for r > k
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int r = rg + 4 * m;
-            if (r > k) v[m] *= rl;
-            else if (r == k) v[m] = ld;
-          }
-        }
-        // L[r][k] for this lane's rows, and L[c][k] for its column
-        double lrk[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) lrk[m] = __shfl(v[m], 16 * rg + k);
-        const double t0 = __shfl(v[0], 16 * (c & 3) + k);
-        const double t1 = __shfl(v[1], 16 * (c & 3) + k);
-        const double t2 = __shfl(v[2], 16 * (c & 3) + k);
-        const double t3 = __shfl(v[3], 16 * (c & 3) + k);
-        const int cm = c >> 2;
-        const double lck = cm == 0 ? t0 : (cm == 1 ? t1 : (cm == 2 ? t2 : t3));
-        if (c > k) {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int r = rg + 4 * m;
-            if (r >= c) v[m] -= lrk[m] * lck;
-          }
-        }
-        if (lane == k) {
-          dg[16 * J + k] = ld;
-          rdg[16 * J + k] = rl;
-        }
+        for (int c = k + 1; c < 16; ++c) a[c] = fma(-lk, lane_value(a[k], c), a[c]);
+        a[k] = r > k ? lk : a[k];                      // lane k keeps its pivot
       }
+      if (r < 16) {
+        // lane r's diagonal entry is its pivot; the inverse is recomputed
+        // from it exactly as in the step
+        double dr = a[0];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int r = rg + 4 * m;
-        if (r >= c) blk[bel(r, c)] = v[m];
+        for (int c = 1; c < 16; ++c) dr = c == r ? a[c] : dr;
+        dv[16 * J + r] = dr;
+        iv[16 * J + r] = dr > PIVOT_EPS ? pivot_recip(dr) : 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) blk[bel(r, c)] = c < r ? a[c] : 0.0;
       }
     }
     __syncthreads();
     if (J + 1 == S::T) break;
-    // (b) panel: rows i of blocks I > J, x = a L_JJ^{-T}
+    // (b) panel: rows i of blocks I > J
     {
       const int i = 16 * (J + 1) + tid;
       if (i < S::LP) {
@@ -118,19 +120,18 @@ __device__ void cholesky_blocked(double* A, double* dg, double* rdg) {
         double x[16];
 #pragma unroll
         for (int cc = 0; cc < 16; ++cc) x[cc] = row[cc ^ sw];
+        // x <- x L_JJ^-T (unit lower L_JJ), one column at a time
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) {
-          double t = x[cc];
+        for (int m = 0; m < 16; ++m) {
 #pragma unroll
-          for (int m = 0; m < cc; ++m) t -= x[m] * ljj[bel(cc, m)];
-          x[cc] = t * rdg[16 * J + cc];
+          for (int cc = m + 1; cc < 16; ++cc) x[cc] = fma(-x[m], ljj[bel(cc, m)], x[cc]);
         }
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) row[cc ^ sw] = x[cc];
+        for (int cc = 0; cc < 16; ++cc) row[cc ^ sw] = x[cc] * iv[16 * J + cc];
       }
     }
     __syncthreads();
-    // (c) trailing update A_IK -= L_IJ L_KJ^T for J < K <= I, on MFMA
+    // (c) trailing update A_IK -= (L_IJ D_J) L_KJ^T for J < K <= I, on MFMA
     {
       const int nb = S::T - J - 1;
       const int npair = nb * (nb + 1) / 2;
@@ -147,7 +148,7 @@ __device__ void cholesky_blocked(double* A, double* dg, double* rdg) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           const int kk = 4 * s4 + (lane >> 4);
-          const double av = -li[bel(lane & 15, kk)];
+          const double av = -li[bel(lane & 15, kk)] * dv[16 * J + kk];
           const double bv = lk[bel(lane & 15, kk)];
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
@@ -160,98 +161,136 @@ __device__ void cholesky_blocked(double* A, double* dg, double* rdg) {
 }
 
 // ---------------------------------------------------------------------------
-// (L L^T) z = b with the blocked factor, run by wave 0 alone: lane l owns rows
-// l, l+64, l+128 in registers; each step's value is broadcast from its owner
-// lane; reciprocal pivots replace divisions.  Deflated pivots give 0.  The
-// caller synchronises the workgroup before reading z.
+// L D L^T z = b with the blocked factor of ldl_blocked, run by wave 0 alone:
+// lane l owns rows l, l+64, l+128 in registers; the value of each step is
+// read from its owner lane with v_readlane, so a step is one FMA deep.  The
+// zero diagonal and upper parts of the diagonal blocks, and the zero row for
+// blocks that do not exist, make every update unconditional: a row that is
+// already final, or a padding row, only ever adds 0 * y.  Deflated unknowns
+// (iv = 0) come out 0.  The caller synchronises the workgroup before reading
+// z.
 // ---------------------------------------------------------------------------
 template <int L>
-__device__ void tri_solve_wave(const double* A, const double* rdg, const double* b, double* z) {
+__device__ __forceinline__ void tri_solve_wave(const double* A, const double* iv, const double* b, double* z) {
+  using S = BlockShape<L>;
   constexpr int NS = (L + 63) / 64;
+  constexpr int ZROW = S::WORDS;
   const int lane = threadIdx.x & 63;
-  double bb[NS], yy[NS];
+  int rI[NS], rlo[NS], rsw[NS];
+  double bb[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int i = lane + 64 * s;
+    const int ic = i < S::LP ? i : S::LP - 1;   // rows past the padding read in bounds
+    rI[s] = ic >> 4;
+    rlo[s] = ic & 15;
+    rsw[s] = (ic & 15) >> 1;
     bb[s] = i < L ? b[i] : 0.0;
-    yy[s] = 0.0;
   }
-  // forward: L y = b
+  // forward: L y = b.  Row j is final once step j starts, so bb ends holding y.
 #pragma unroll
   for (int s0 = 0; s0 < NS; ++s0) {
-    const int jn = (L - 64 * s0) < 64 ? (L - 64 * s0) : 64;
-    for (int jj = 0; jj < jn; ++jj) {
-      const int j = 64 * s0 + jj;
-      const double yj = __shfl(bb[s0], jj) * rdg[j];
-      if (lane == jj) yy[s0] = yj;
 #pragma unroll
-      for (int s = s0; s < NS; ++s) {
-        const int i = lane + 64 * s;
-        if (i > j && i < L) bb[s] -= A[belem(i, j)] * yj;
+    for (int jj = 0; jj < 64; ++jj) {
+      const int j = 64 * s0 + jj;
+      if (j < L) {
+        const int J = j >> 4;
+        const double yj = lane_value(bb[s0], jj);
+#pragma unroll
+        for (int s = s0; s < NS; ++s) {
+          // element (i, j): block (I, J) if I >= J, else the zero row
+          const int rowbase = s > s0 ? (rI[s] * (rI[s] + 1) / 2 + J) * 256 + 16 * rlo[s]
+                                     : (rI[s] >= J ? (rI[s] * (rI[s] + 1) / 2 + J) * 256 + 16 * rlo[s] : ZROW);
+          bb[s] = fma(-A[rowbase + ((j & 15) ^ rsw[s])], yj, bb[s]);
+        }
       }
     }
   }
-  // backward: L^T z = y
-  double zz[NS];
+  // diagonal: w = D^-1 y
 #pragma unroll
-  for (int s = 0; s < NS; ++s) zz[s] = 0.0;
+  for (int s = 0; s < NS; ++s) {
+    const int i = lane + 64 * s;
+    bb[s] *= iv[i < L ? i : 0];
+  }
+  // backward: L^T z = w; element (j, i) of L for i < j lies in block row
+  // J = j >> 4; bb ends holding z.
 #pragma unroll
   for (int s0 = NS - 1; s0 >= 0; --s0) {
-    const int jn = (L - 64 * s0) < 64 ? (L - 64 * s0) : 64;
-    for (int jj = jn - 1; jj >= 0; --jj) {
-      const int j = 64 * s0 + jj;
-      const double zj = __shfl(yy[s0], jj) * rdg[j];
-      if (lane == jj) zz[s0] = zj;
 #pragma unroll
-      for (int s = 0; s <= s0; ++s) {
-        const int i = lane + 64 * s;
-        if (i < j) yy[s] -= A[belem(j, i)] * zj;
+    for (int jj = 63; jj >= 0; --jj) {
+      const int j = 64 * s0 + jj;
+      if (j < L) {
+        const int J = j >> 4;
+        const int jsw = (j & 15) >> 1;
+        const double zj = lane_value(bb[s0], jj);
+#pragma unroll
+        for (int s = 0; s <= s0; ++s) {
+          const int base = s < s0 ? (J * (J + 1) / 2 + rI[s]) * 256 + 16 * (j & 15)
+                                  : (rI[s] <= J ? (J * (J + 1) / 2 + rI[s]) * 256 + 16 * (j & 15) : ZROW);
+          bb[s] = fma(-A[base + (rlo[s] ^ jsw)], zj, bb[s]);
+        }
       }
     }
   }
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int i = lane + 64 * s;
-    if (i < L) z[i] = zz[s];
+    if (i < L) z[i] = bb[s];
   }
 }
 
 // Factor, solve, write F and (optionally) the factor; shared tail of both
 // K6 variants.  A holds the equilibrated matrix (blocked, padding = identity),
-// b the scaled right-hand side, sc the equilibration scales.
+// b the scaled right-hand side, sc the equilibration scales.  The kept factor
+// is [blocked L and D | D | D^-1 | sc].
 template <int L>
-__device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dg, double* rdg,
+__device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dv, double* iv,
                                                    const double* sc, const LevelArgs& a, uint32_t k, uint32_t node,
                                                    double* fac) {
   using S = BlockShape<L>;
   const int tid = threadIdx.x;
-  cholesky_blocked<L>(A, dg, rdg);
-  if (tid < 64) tri_solve_wave<L>(A, rdg, b, z);
+  ldl_blocked<L>(A, dv, iv);
+  if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
   __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
   bool deflated = false;
   for (int i = tid; i < L; i += 256) {
     F[i] = sc[i] * z[i];
-    if (dg[i] == 0.0) deflated = true;
+    if (iv[i] == 0.0) deflated = true;
   }
   if (fac) {
     double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
     for (int e = tid; e < S::WORDS; e += 256) fo[e] = A[e];
     for (int i = tid; i < L; i += 256) {
-      fo[S::WORDS + i] = dg[i];
-      fo[S::WORDS + L + i] = rdg[i];
+      fo[S::WORDS + i] = dv[i];
+      fo[S::WORDS + L + i] = iv[i];
       fo[S::WORDS + 2 * L + i] = sc[i];
     }
   }
   if (deflated) atomicOr(a.nt.flags + node, FLAG_DEFLATED);
 }
 
-// Identity on the padding rows and columns [L, LP) of the blocked matrix.
-template <int L>
-__device__ __forceinline__ void pad_identity(double* A) {
+// Fill the blocked matrix in storage order: thread t writes word t of every
+// block, i.e. element (r, c) with r = t >> 4 and c = (t & 15) ^ (r >> 1), so
+// the LDS writes are contiguous and the block indices are compile-time.
+// value(i, q) gives the entry for i, q < L; the padding is the identity.
+// Diagonal blocks get both triangles (the factor reads only the lower one).
+// The zero row after the blocks is cleared too.
+template <int L, typename V>
+__device__ __forceinline__ void assemble_blocked(double* A, V value) {
   using S = BlockShape<L>;
-  for (int i = L + threadIdx.x; i < S::LP; i += 256)
-    for (int q = 0; q <= i; ++q) A[belem(i, q)] = q == i ? 1.0 : 0.0;
+  const int tid = threadIdx.x;
+  const int r = tid >> 4, c = (tid & 15) ^ (r >> 1);
+#pragma unroll
+  for (int I = 0; I < S::T; ++I) {
+    const int i = 16 * I + r;
+#pragma unroll
+    for (int J = 0; J <= I; ++J) {
+      const int q = 16 * J + c;
+      A[bidx(I, J) + tid] = (i < L && q < L) ? value(i, q) : (i == q ? 1.0 : 0.0);
+    }
+  }
+  if (tid < 16) A[S::WORDS + tid] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -265,8 +304,8 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   constexpr int TG = pad16(L + 1) / 16;
   constexpr int NPAIR = TG * (TG + 1) / 2;
   using S = BlockShape<L>;
-  __shared__ double A[S::WORDS];
-  __shared__ double b[L], z[L], dg[S::LP], rdg[S::LP], sc[L];   // pivots cover the padding too
+  __shared__ double A[S::WORDS + 16];   // + the zero row
+  __shared__ double b[L], z[L], dv[S::LP], iv[S::LP], sc[L];   // pivots cover the padding too
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
@@ -280,17 +319,14 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   };
   for (int i = tid; i < L; i += 256) {
     const double d = gram(i, i);
-    sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    const double s = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    sc[i] = s;
+    b[i] = gram(i, L) * s;
   }
   __syncthreads();
-  for (int i = tid; i < L; i += 256) {
-    const double si = sc[i];
-    for (int q = 0; q <= i; ++q) A[belem(i, q)] = gram(q, i) * si * sc[q];
-    b[i] = gram(i, L) * si;
-  }
-  pad_identity<L>(A);
+  assemble_blocked<L>(A, [&](int i, int q) { return (i <= q ? gram(i, q) : gram(q, i)) * sc[i] * sc[q]; });
   __syncthreads();
-  factor_solve_store<L>(A, b, z, dg, rdg, sc, a, k, node, fac);
+  factor_solve_store<L>(A, b, z, dv, iv, sc, a, k, node, fac);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,11 +336,6 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
 // A_ik = M[alpha_i + alpha_k] w_i w_k and the scaled right-hand side
 // B[alpha_i] w_i.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int graded(int a, int b, int c) {
-  const int k = a + b + c;
-  return k * (k + 1) * (k + 2) / 6 + (k - a) * (k - a + 1) / 2 + (k - a - b);
-}
-
 template <int P>
 __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __restrict__ part,
                                                  double* __restrict__ fac) {
@@ -313,9 +344,9 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   constexpr int NOUT = NM + L + 1;
   constexpr Basis<P> B{};
   using S = BlockShape<L>;
-  __shared__ double A[S::WORDS];
+  __shared__ double A[S::WORDS + 16];   // + the zero row
   __shared__ double mom[NOUT];
-  __shared__ double b[L], z[L], dg[S::LP], rdg[S::LP], sc[L], wv[L];   // pivots cover the padding too
+  __shared__ double b[L], z[L], dv[S::LP], iv[S::LP], sc[L], wv[L];   // pivots cover the padding too
   __shared__ int ex[L][3];
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
@@ -337,15 +368,11 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
     b[i] = mom[NM + i] * s * f;
   }
   __syncthreads();
-  for (int i = tid; i < L; i += 256) {
-    const int xi = ex[i][0], yi = ex[i][1], zi = ex[i][2];
-    const double wi = wv[i];
-    for (int q = 0; q <= i; ++q)
-      A[belem(i, q)] = mom[graded(xi + ex[q][0], yi + ex[q][1], zi + ex[q][2])] * wi * wv[q];
-  }
-  pad_identity<L>(A);
+  assemble_blocked<L>(A, [&](int i, int q) {
+    return mom[graded(ex[i][0] + ex[q][0], ex[i][1] + ex[q][1], ex[i][2] + ex[q][2])] * wv[i] * wv[q];
+  });
   __syncthreads();
-  factor_solve_store<L>(A, b, z, dg, rdg, sc, a, k, node, fac);
+  factor_solve_store<L>(A, b, z, dv, iv, sc, a, k, node, fac);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,36 +386,39 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   constexpr int L = basis_size(P);
   constexpr Basis<P> B{};
   using S = BlockShape<L>;
-  __shared__ double A[S::WORDS];
-  __shared__ double b[L], z[L], rdg[L], sc[L];
+  __shared__ double A[S::WORDS + 16];   // + the zero row
+  __shared__ double b[L], z[L], iv[L], sc[L];
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
   for (int e = tid; e < S::WORDS; e += 256) A[e] = fo[e];
+  if (tid < 16) A[S::WORDS + tid] = 0.0;
   for (int i = tid; i < L; i += 256) {
-    rdg[i] = fo[S::WORDS + L + i];
+    iv[i] = fo[S::WORDS + L + i];
     sc[i] = fo[S::WORDS + 2 * L + i];
     b[i] = part_b[(size_t)c0 * L + i] * B.inv_fact[i] * fo[S::WORDS + 2 * L + i];
   }
   __syncthreads();
-  if (tid < 64) tri_solve_wave<L>(A, rdg, b, z);
+  if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
   __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
   for (int i = tid; i < L; i += 256) F[i] += sc[i] * z[i];
 }
 
 // ---------------------------------------------------------------------------
-// K8: residual update r <- r - Lambda F (Alg. 2) and, per chunk, the sum of
-// r^2 over each child octant (Alg. 1's E_RMS numerator), reduced in a fixed
-// order so that results do not depend on scheduling.
+// K8: residual update r <- r - Lambda F (Alg. 2) and, per chunk and child
+// octant, the sum of r^2 (Alg. 1's E_RMS numerator) and the point count,
+// reduced in a fixed order so that results do not depend on scheduling.
+// part_ss holds 16 doubles per chunk: 8 sums of r^2, then 8 counts (exact).
 // ---------------------------------------------------------------------------
 template <int P, typename TIN>
 __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restrict__ part_ss) {
   constexpr int L = basis_size(P);
   __shared__ double Fs[L];
   __shared__ double red[4][8];
+  __shared__ uint32_t redc[4][8];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint32_t g = blockIdx.x;
   const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
@@ -403,8 +433,12 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
   const bool stats = a.level < a.D;
   const int shift = stats ? 3 * (a.D - a.level - 1) : 0;
   double ss[8];
+  uint32_t cn[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) ss[q] = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    ss[q] = 0.0;
+    cn[q] = 0u;
+  }
   for (uint32_t i = start + tid; i < end; i += 256) {
     double x, y, z;
     load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
@@ -414,28 +448,41 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
     const uint32_t o = (a.skey[i] >> shift) & 7u;
     const double r2 = rn * rn;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) ss[q] += (o == (uint32_t)q) ? r2 : 0.0;
+    for (int q = 0; q < 8; ++q) {
+      ss[q] += (o == (uint32_t)q) ? r2 : 0.0;
+      cn[q] += (o == (uint32_t)q) ? 1u : 0u;
+    }
   }
   if (!stats) return;
   // fixed-order reduction: butterfly inside the wave, then waves in order
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) ss[q] += __shfl_xor(ss[q], off);
+    for (int off = 32; off >= 1; off >>= 1) {
+      ss[q] += __shfl_xor(ss[q], off);
+      cn[q] += __shfl_xor(cn[q], off);
+    }
   }
   if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) red[w][q] = ss[q];
+    for (int q = 0; q < 8; ++q) {
+      red[w][q] = ss[q];
+      redc[w][q] = cn[q];
+    }
   }
   __syncthreads();
-  if (tid < 8) part_ss[(size_t)g * 8 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+  if (tid < 8) part_ss[(size_t)g * 16 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+  else if (tid < 16)
+    part_ss[(size_t)g * 16 + tid] =
+        (double)(redc[0][tid - 8] + redc[1][tid - 8] + redc[2][tid - 8] + redc[3][tid - 8]);
 }
 
 // ---------------------------------------------------------------------------
 // Child activation (Alg. 1): octant o of a node at depth d becomes a node iff
 // d + 1 <= D, n_o >= calL (tested first) and sqrt(sum r^2 / n_o) > tol.
-// One thread per node.  Octant ranges come from binary searches of the sorted
-// keys, so counts are exact integers.
+// One thread per node.  The octant counts come from the residual pass (exact
+// integers); points are sorted by key, so octant o's points follow those of
+// octants 0..o-1 inside the node.
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ void __launch_bounds__(256) k_children(LevelArgs a, const double* __restrict__ part_ss,
@@ -450,30 +497,16 @@ __global__ void __launch_bounds__(256) k_children(LevelArgs a, const double* __r
     nact[k] = 0;
     return;
   }
-  const uint32_t nb = a.nt.begin[node], ne = nb + a.nt.count[node];
-  const uint64_t full = ((uint64_t)a.nt.problem[node] << (3 * a.level)) | a.nt.prefix[node];
-  const int shift = 3 * (a.D - a.level - 1);
-  uint32_t bnd[9];
-  bnd[0] = nb;
-  bnd[8] = ne;
-  for (int o = 1; o < 8; ++o) {
-    const uint64_t target = ((full << 3) | (uint64_t)o) << shift;
-    uint32_t lo = bnd[o - 1], hi = ne;   // first position with key >= target
-    while (lo < hi) {
-      uint32_t mid = lo + ((hi - lo) >> 1);
-      if ((uint64_t)a.skey[mid] < target) lo = mid + 1; else hi = mid;
-    }
-    bnd[o] = lo;
-  }
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
-  uint32_t mask = 0;
+  const double* st = part_ss + (size_t)c0 * 16;
+  uint32_t pos = a.nt.begin[node], mask = 0;
   for (int o = 0; o < 8; ++o) {
-    const uint32_t n_o = bnd[o + 1] - bnd[o];
-    cbeg[(size_t)k * 8 + o] = bnd[o];
+    const uint32_t n_o = (uint32_t)st[8 + o];
+    cbeg[(size_t)k * 8 + o] = pos;
     ccnt[(size_t)k * 8 + o] = n_o;
+    pos += n_o;
     if (n_o < L) continue;
-    const double s = part_ss[(size_t)c0 * 8 + o];
-    if (sqrt(s / (double)n_o) > a.tol) mask |= 1u << o;
+    if (sqrt(st[o] / (double)n_o) > a.tol) mask |= 1u << o;
   }
   a.nt.child_mask[node] = mask;
   nact[k] = (uint32_t)__popc(mask);
@@ -481,26 +514,38 @@ __global__ void __launch_bounds__(256) k_children(LevelArgs a, const double* __r
 
 // Sum the per-chunk partials of every multi-chunk node into the node's first
 // chunk slot (deterministic).  `width` doubles per chunk.  A workgroup covers
-// 64 elements of one node with 4 lane groups; group q sums chunks q, q+4, ...
-// and the four group sums are added in a fixed order.  Single-chunk nodes
-// exit at once.
-__global__ void __launch_bounds__(256) k_chunk_reduce(const uint32_t* __restrict__ chunk_off, uint32_t nnodes,
-                                                      double* __restrict__ buf, uint32_t width, uint32_t eblocks) {
-  __shared__ double part[4][64];
+// 64 elements of one node with 16 lane groups; group q sums chunks
+// q, q+16, ... into eight interleaved accumulators (eight loads in flight per
+// thread), and the sixteen group sums are added in a fixed tree.
+// Single-chunk nodes exit at once.
+__global__ void __launch_bounds__(1024) k_chunk_reduce(const uint32_t* __restrict__ chunk_off, uint32_t nnodes,
+                                                       double* __restrict__ buf, uint32_t width, uint32_t eblocks) {
+  __shared__ double part[16][64];
   const uint32_t k = blockIdx.x / eblocks;
   if (k >= nnodes) return;
   const uint32_t c0 = chunk_off[k], c1 = chunk_off[k + 1];
   if (c1 - c0 < 2) return;
-  const uint32_t e = (blockIdx.x % eblocks) * 64 + (threadIdx.x & 63);
-  const uint32_t q = threadIdx.x >> 6;
-  double s = 0.0;
-  if (e < width)
-    for (uint32_t g = c0 + q; g < c1; g += 4) s += buf[(size_t)g * width + e];
-  part[q][threadIdx.x & 63] = s;
+  const uint32_t lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const uint32_t e = (blockIdx.x % eblocks) * 64 + lane;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  if (e < width) {
+    uint32_t g = c0 + q;
+    for (; g + 16 * 7 < c1; g += 16 * 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += buf[(size_t)(g + 16 * u) * width + e];
+    }
+    for (; g < c1; g += 16) acc[0] += buf[(size_t)g * width + e];
+  }
+  part[q][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
-  if (q == 0 && e < width)
-    buf[(size_t)c0 * width + e] = ((part[0][threadIdx.x] + part[1][threadIdx.x]) + part[2][threadIdx.x]) +
-                                  part[3][threadIdx.x];
+  if (q == 0 && e < width) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = part[2 * u][lane] + part[2 * u + 1][lane];
+    buf[(size_t)c0 * width + e] = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+  }
 }
 
 // Cell coordinates (i, j, k) of a Morton prefix with `level` triples.
@@ -720,7 +765,7 @@ hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint3
 hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, hipStream_t s) {
   if (a.nnodes == 0 || a.nchunks <= a.nnodes) return hipSuccess;
   const uint32_t eblocks = (width + 63) / 64;
-  hipLaunchKernelGGL(k_chunk_reduce, dim3(a.nnodes * eblocks), dim3(256), 0, s, a.chunk_off, a.nnodes, buf, width,
+  hipLaunchKernelGGL(k_chunk_reduce, dim3(a.nnodes * eblocks), dim3(1024), 0, s, a.chunk_off, a.nnodes, buf, width,
                      eblocks);
   return hipGetLastError();
 }

@@ -144,6 +144,7 @@ __device__ __forceinline__ void moments_group(const LevelArgs& a, uint32_t start
   double acc[NA];
 #pragma unroll
   for (int s = 0; s < NA; ++s) acc[s] = 0.0;
+#pragma unroll 1
   for (uint32_t i = start + lane; i < end; i += 64) {
     double x, y, z;
     load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
@@ -198,7 +199,6 @@ template <int P, int MODE, typename TIN>
 __global__ void __launch_bounds__((MomentPlan<P, MODE>::NW * 64)) k_moments(LevelArgs a, double* __restrict__ part) {
   using MP = MomentPlan<P, MODE>;
   constexpr int L = basis_size(P);
-  __shared__ double Fs[MODE == 1 ? L : 1];
   __shared__ double rp[MODE == 1 ? CHUNK : 1];   // r' = r - Lambda F of the chunk's points
   __shared__ double red[MP::NW][16 * 65];
   const uint32_t g = blockIdx.x;
@@ -209,16 +209,30 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NW * 64)) k_moments(Leve
   const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
   const double* geo = a.nt.geo + 6 * (size_t)node;
   if constexpr (MODE == 1) {
-    for (int i = threadIdx.x; i < L; i += MP::NW * 64) Fs[i] = a.nt.coef[(size_t)node * L + i];
-    __syncthreads();
-    // r' once per point; coefficients read through a volatile view so that
-    // they stay in LDS instead of occupying registers
+    // r' once per point, four points per thread at a time; the node's
+    // coefficients are wave-uniform and read with scalar loads (read-only
+    // constant address space), so they take no vector registers
+    typedef const double __attribute__((address_space(4))) cdouble;
+    const cdouble* F = (const cdouble*)(a.nt.coef + (size_t)node * L);
     const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
-    const volatile double* Fv = Fs;
-    for (uint32_t i = start + threadIdx.x; i < end; i += MP::NW * 64) {
-      double x, y, z;
-      load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
-      rp[i - start] = a.r[i] - poly_eval<P, double>(Fv, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
+    constexpr int NT = MP::NW * 64, NPT = 4;
+    for (uint32_t i0 = start + threadIdx.x; i0 < end; i0 += NPT * NT) {
+      double u[NPT], v[NPT], w[NPT], val[NPT];
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const uint32_t i = min(i0 + q * NT, end - 1);   // tail lanes repeat a point and do not store
+        double x, y, z;
+        load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
+        u[q] = (x - cx) * sx;
+        v[q] = (y - cy) * sy;
+        w[q] = (z - cz) * sz;
+      }
+      poly_eval_multi<P, NPT>(F, u, v, w, val);
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const uint32_t i = i0 + q * NT;
+        if (i < end) rp[i - start] = a.r[i] - val[q];
+      }
     }
     __syncthreads();
   }

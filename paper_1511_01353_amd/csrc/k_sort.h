@@ -12,6 +12,12 @@ struct PtrSet {
   const void* f;
 };
 
+// NP payload arrays moved by a sort pass (passed by value to the kernel).
+template <typename PT, int NP>
+struct PayloadSet {
+  PT* a[NP];
+};
+
 constexpr uint32_t STATUS_DOMAIN = 1u;
 constexpr uint32_t STATUS_NONFINITE = 2u;
 
@@ -29,6 +35,14 @@ size_t radix_sort_scratch_words(uint32_t n);
 // With vals_are_iota the input values are not read (value = position).
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n, int bits,
                       bool vals_are_iota, uint32_t* scratch, hipStream_t s, bool* result_in_alt);
+// radix_sort that also moves three payload arrays of the given dtype (4 or 8
+// bytes per element): pass 0 reads pin[] and the passes alternate between
+// pay_alt[] and pay[]; the sorted payload ends in pay[] when *result_in_alt
+// is false (an even number of passes), else in pay_alt[].  Values start as
+// source positions (not read).
+hipError_t radix_sort_payload3(int dtype, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                               const void* const* pin, void* const* pay, void* const* pay_alt, uint32_t n, int bits,
+                               uint32_t* scratch, hipStream_t s, bool* result_in_alt);
 hipError_t launch_gather(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, const uint32_t* order,
                          uint32_t total, void* px, void* py, void* pz, double* r, hipStream_t s);
 hipError_t launch_permute3(int dtype, const void* x, const void* y, const void* z, const uint32_t* order,

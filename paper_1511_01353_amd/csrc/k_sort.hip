@@ -210,6 +210,126 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
   }
 }
 
+// The same pass moving NP payload arrays of PT along with (key, value): ranks
+// and destinations as above; each payload array is then staged through LDS
+// one at a time (read coalesced at the element's source position, written
+// coalesced at its destination), so the payload costs no registers during
+// ranking.  FIRST: values are source positions (not read).
+template <bool FIRST, typename PT, int NP>
+__global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t* __restrict__ kin,
+                                                                  const uint32_t* __restrict__ vin,
+                                                                  PayloadSet<PT, NP> pin,
+                                                                  uint32_t* __restrict__ kout,
+                                                                  uint32_t* __restrict__ vout,
+                                                                  PayloadSet<PT, NP> pout, uint32_t n, int shift,
+                                                                  const uint32_t* __restrict__ offs,
+                                                                  const uint32_t* __restrict__ tot) {
+  constexpr int WAVES = SORT_THREADS / 64;
+  constexpr int QUARTER = SORT_TILE / WAVES;
+  constexpr int ROUNDS = QUARTER / 64;
+  __shared__ uint32_t wcnt[WAVES][RADIX];
+  __shared__ uint32_t lofs[RADIX];
+  __shared__ uint32_t goff[RADIX];
+  __shared__ uint32_t dbase[RADIX];
+  __shared__ uint32_t sk[SORT_TILE];
+  __shared__ uint32_t sv[SORT_TILE];
+  __shared__ PT sp[SORT_TILE];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < WAVES * RADIX; i += SORT_THREADS) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+
+  const uint64_t below_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t base = blockIdx.x * SORT_TILE + w * QUARTER;
+  uint32_t key[ROUNDS], rank[ROUNDS];
+#pragma unroll
+  for (int j = 0; j < ROUNDS; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t d = (k >> shift) & (RADIX - 1);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RADIX_BITS; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & below_mask);
+    const uint32_t c = wcnt[w][d];
+    rank[j] = c + before;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && before == 0) wcnt[w][d] = c + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    key[j] = k;
+  }
+  __syncthreads();
+  if (tid < RADIX) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) {
+      uint32_t c = wcnt[ww][tid];
+      wcnt[ww][tid] = run;
+      run += c;
+    }
+    lofs[tid] = run;
+    dbase[tid] = tot[tid];
+  }
+  __syncthreads();
+  const uint32_t mine = tid < RADIX ? lofs[tid] : 0u;
+  const uint32_t mine_g = tid < RADIX ? dbase[tid] : 0u;
+  for (int off = 1; off < RADIX; off <<= 1) {
+    const uint32_t v = (tid < RADIX && tid >= off) ? lofs[tid - off] : 0u;
+    const uint32_t vg = (tid < RADIX && tid >= off) ? dbase[tid - off] : 0u;
+    __syncthreads();
+    if (tid < RADIX) {
+      lofs[tid] += v;
+      dbase[tid] += vg;
+    }
+    __syncthreads();
+  }
+  if (tid < RADIX) {
+    lofs[tid] -= mine;
+    goff[tid] = dbase[tid] - mine_g + offs[tid * gridDim.x + blockIdx.x];
+  }
+  __syncthreads();
+  // tile-local destination of each of this lane's elements
+  uint32_t pos[ROUNDS];
+#pragma unroll
+  for (int j = 0; j < ROUNDS; ++j) {
+    const uint32_t i = base + j * 64 + lane;
+    const uint32_t d = (key[j] >> shift) & (RADIX - 1);
+    pos[j] = lofs[d] + wcnt[w][d] + rank[j];
+    if (i < n) {
+      sk[pos[j]] = key[j];
+      sv[pos[j]] = FIRST ? i : vin[i];
+    }
+  }
+  __syncthreads();
+  const uint32_t tile0 = blockIdx.x * SORT_TILE;
+  const uint32_t tn = min((uint32_t)SORT_TILE, n - tile0);
+  for (uint32_t i = tid; i < tn; i += SORT_THREADS) {
+    const uint32_t k = sk[i];
+    const uint32_t d = (k >> shift) & (RADIX - 1);
+    const uint32_t o = goff[d] + (i - lofs[d]);
+    kout[o] = k;
+    vout[o] = sv[i];
+  }
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    __syncthreads();   // sp is free again
+#pragma unroll
+    for (int j = 0; j < ROUNDS; ++j) {
+      const uint32_t i = base + j * 64 + lane;
+      if (i < n) sp[pos[j]] = pin.a[a][i];
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < tn; i += SORT_THREADS) {
+      const uint32_t d = (sk[i] >> shift) & (RADIX - 1);
+      pout.a[a][goff[d] + (i - lofs[d])] = sp[i];
+    }
+  }
+}
+
 // Gather points into key order; the residual starts as the sampled values.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather(const PtrSet* ptrs, const ProblemParams* prm, int nprob,
@@ -307,6 +427,55 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32
   }
   *result_in_alt = (ki != keys);
   return hipSuccess;
+}
+
+template <typename PT>
+static hipError_t radix_sort_payload_t(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                                       const void* const* pin, void* const* pay, void* const* pay_alt, uint32_t n,
+                                       int bits, uint32_t* scratch, hipStream_t s, bool* result_in_alt) {
+  const uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+  uint32_t* hist = scratch;
+  uint32_t* tot = scratch + (size_t)RADIX * tiles;
+  const int passes = radix_sort_passes(bits);
+  uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+  PayloadSet<PT, 3> src, a, b;
+  for (int q = 0; q < 3; ++q) {
+    src.a[q] = (PT*)pin[q];
+    a.a[q] = (PT*)pay[q];
+    b.a[q] = (PT*)pay_alt[q];
+  }
+  // pass 0 reads the caller's payload and writes the alternate set, then the
+  // sets alternate like the keys
+  PayloadSet<PT, 3> pi = src, po = b;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * RADIX_BITS;
+    hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
+    hipLaunchKernelGGL(k_digit_scan, dim3(RADIX), dim3(256), 0, s, hist, tiles, tot);
+    if (p == 0)
+      hipLaunchKernelGGL((k_radix_scatter_p<true, PT, 3>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi, ko,
+                         vo, po, n, shift, hist, tot);
+    else
+      hipLaunchKernelGGL((k_radix_scatter_p<false, PT, 3>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi, ko,
+                         vo, po, n, shift, hist, tot);
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+    pi = po;
+    po = (p % 2 == 0) ? a : b;
+  }
+  *result_in_alt = ki != keys;
+  return hipGetLastError();
+}
+
+hipError_t radix_sort_payload3(int dtype, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                               const void* const* pin, void* const* pay, void* const* pay_alt, uint32_t n, int bits,
+                               uint32_t* scratch, hipStream_t s, bool* result_in_alt) {
+  *result_in_alt = false;
+  if (n == 0) return hipSuccess;
+  if (dtype == FMT_F32)
+    return radix_sort_payload_t<float>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
+                                       result_in_alt);
+  return radix_sort_payload_t<double>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
+                                      result_in_alt);
 }
 
 hipError_t launch_gather(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, const uint32_t* order,

@@ -18,7 +18,7 @@ def test_algorithmic_work_counts():
     import bench
     # p = 6: calL = 84; symmetric Gram 84*85 + rhs 2*84 + basis 84
     assert bench.gram_flops_per_point(84) == 84 * 85 + 3 * 84
-    assert bench.eval_flops_per_query_node(84) == 3 * 84
+    assert bench.eval_flops_per_query(84) == 2 * 84
     # p = 6: 455 power moments + 84 weighted + 1, 91 + 28 runs, 36 powers
     assert bench.moment_flops_per_point(6) == 2 * (455 + 84 + 1) + 119 + 36
     assert bench.solve_flops_per_node(84) == 84 ** 3 / 3 + 2 * 84 * 84
