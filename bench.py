@@ -88,10 +88,12 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
     add("refine_sweep", "alu", refine_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     # residual: coordinates + residual read, residual written, key read
     add("residual", "hbm", 3 * coord_bytes + 8 + 8 + 4, "GB/s", PEAK_HBM_GBS)
-    # sort: per pass read and write key and index
-    add("sort", "hbm", 16.0 * key_passes, "GB/s", PEAK_HBM_GBS)
-    add("eval_sort", "hbm", 16.0 * eval_key_passes, "GB/s", PEAK_HBM_GBS)
-    add("gather", "hbm", 4 + 3 * coord_bytes + coord_bytes + 3 * coord_bytes + 8, "GB/s", PEAK_HBM_GBS)
+    # sort: per pass read and write key and index, and the payload (the fit
+    # moves x, y, z, f; the evaluation x, y, z), plus the histogram's key read
+    add("sort", "hbm", (20.0 + 8 * coord_bytes) * key_passes, "GB/s", PEAK_HBM_GBS)
+    add("eval_sort", "hbm", (20.0 + 6 * coord_bytes) * eval_key_passes, "GB/s", PEAK_HBM_GBS)
+    # residual start: sorted values in, float64 residual out
+    add("gather", "hbm", coord_bytes + 8, "GB/s", PEAK_HBM_GBS)
     # query keys: coordinates in, key out
     add("eval_keys", "hbm", 3 * coord_bytes + 4, "GB/s", PEAK_HBM_GBS)
     # evaluation: the bound is whichever of its flops (2L per query) and its

@@ -145,7 +145,8 @@ struct DevBuf {
 // Reusable scratch of the level loop, one set per stream (fits on one stream
 // are serialised by the stream itself; different streams never share).
 struct Workspace {
-  DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz;
+  // px, py, pz, pf: key-ordered inputs (payload set A); px2 .. pf2: set B
+  DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status, params, ptrs;
   uint32_t* host_counters = nullptr;
   char* stage = nullptr;        // pinned staging for small host-to-device copies
@@ -219,8 +220,15 @@ struct Forest {
   std::mutex compose_mu;
   DevBuf nb_ccoef;
   hipEvent_t composed = nullptr;
+  // per problem: cell table (cell of depth T -> deepest node), its depth and
+  // the event marking its completion; built on the problem's first evaluation
+  std::vector<DevBuf> cell_tab;
+  std::vector<int> cell_T;
+  std::vector<hipEvent_t> cell_ev;
   ~Forest() {
     if (composed) (void)hipEventDestroy(composed);
+    for (hipEvent_t e : cell_ev)
+      if (e) (void)hipEventDestroy(e);
   }
 
   NodeTable table() const {
@@ -241,7 +249,12 @@ struct Forest {
   size_t device_bytes() const {
     return nb_begin.bytes + nb_count.bytes + nb_prefix.bytes + nb_level.bytes + nb_problem.bytes + nb_parent.bytes +
            nb_first_child.bytes + nb_child_mask.bytes + nb_flags.bytes + nb_geo.bytes + nb_coef.bytes + skey.bytes +
-           order.bytes + resid.bytes + nb_ccoef.bytes;
+           order.bytes + resid.bytes + nb_ccoef.bytes + cell_bytes();
+  }
+  size_t cell_bytes() const {
+    size_t b = 0;
+    for (const DevBuf& t : cell_tab) b += t.bytes;
+    return b;
   }
   void alloc_nodes(uint32_t cap) {
     const size_t u = sizeof(uint32_t) * (size_t)cap;
@@ -363,9 +376,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   W.keys_alt.reserve(4ull * N);
   W.vals_alt.reserve(4ull * N);
   W.sort_scratch.reserve(4 * radix_sort_scratch_words(N));
-  W.px.reserve(esz * N);
-  W.py.reserve(esz * N);
-  W.pz.reserve(esz * N);
+  for (DevBuf* b : {&W.px, &W.py, &W.pz, &W.pf, &W.px2, &W.py2, &W.pz2, &W.pf2}) b->reserve(esz * N);
   W.params.reserve(sizeof(ProblemParams) * K);
   W.ptrs.reserve(sizeof(PtrSet) * K);
   W.status.reserve(64);
@@ -381,28 +392,47 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
   const ProblemParams* d_prm = W.params.as<ProblemParams>();
 
-  // K1 keys, K2 sort, K3 gather.  With an odd number of sort passes the keys
-  // start in the alternate buffer so that the sorted result lands in the
-  // forest's arrays.
+  // K1 keys, K2 sort with the inputs as payload (K3: the sort itself leaves
+  // them in key order).  With an odd number of sort passes the keys start in
+  // the alternate buffer so that the sorted result lands in the forest's
+  // arrays.  A batch's inputs are first concatenated (by the key kernel) so
+  // that the first pass reads one array per coordinate.
   const int key_bits = 3 * F->D + F->pbits;
   const bool odd = (radix_sort_passes(key_bits) & 1) != 0;
   uint32_t* k_in = odd ? W.keys_alt.as<uint32_t>() : F->skey.as<uint32_t>();
   uint32_t* v_in = odd ? W.vals_alt.as<uint32_t>() : F->order.as<uint32_t>();
   uint32_t* k_out = odd ? F->skey.as<uint32_t>() : W.keys_alt.as<uint32_t>();
   uint32_t* v_out = odd ? F->order.as<uint32_t>() : W.vals_alt.as<uint32_t>();
+  PtrSet cat{nullptr, nullptr, nullptr, nullptr};
+  if (K > 1) cat = PtrSet{W.px.p, W.py.p, W.pz.p, W.pf.p};
   {
     ProfScope ps(KN_KEYGEN, N, s);
-    HIPCHK(launch_keygen(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->D, N, k_in, W.status.as<uint32_t>(), s));
+    HIPCHK(launch_keygen(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->D, N, k_in, W.status.as<uint32_t>(), cat, s));
   }
   bool in_alt = false;
-  ProfScope* sort_scope = new ProfScope(KN_SORT, N, s);
-  HIPCHK(radix_sort(k_in, v_in, k_out, v_out, N, key_bits, true, W.sort_scratch.as<uint32_t>(), s, &in_alt));
+  {
+    ProfScope ps(KN_SORT, N, s);
+    const void* pin[4];
+    if (K > 1) {
+      pin[0] = W.px.p; pin[1] = W.py.p; pin[2] = W.pz.p; pin[3] = W.pf.p;
+    } else {
+      pin[0] = in[0].x; pin[1] = in[0].y; pin[2] = in[0].z; pin[3] = in[0].f;
+    }
+    void* pay[4] = {W.px.p, W.py.p, W.pz.p, W.pf.p};
+    void* pay_alt[4] = {W.px2.p, W.py2.p, W.pz2.p, W.pf2.p};
+    HIPCHK(radix_sort_payload(dtype, 4, k_in, v_in, k_out, v_out, pin, pay, pay_alt, N, key_bits,
+                              W.sort_scratch.as<uint32_t>(), s, &in_alt));
+  }
   if (in_alt != odd) fail(FMT_E_DEVICE, "internal: sort result in an unexpected buffer");
-  delete sort_scope;
+  if (in_alt) {
+    std::swap(W.px, W.px2);
+    std::swap(W.py, W.py2);
+    std::swap(W.pz, W.pz2);
+    std::swap(W.pf, W.pf2);
+  }
   {
     ProfScope ps(KN_GATHER, N, s);
-    HIPCHK(launch_gather(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->order.as<uint32_t>(), N, W.px.p, W.py.p,
-                         W.pz.p, F->resid.as<double>(), s));
+    HIPCHK(launch_widen(dtype, W.pf.p, N, F->resid.as<double>(), s));
   }
 
   // node capacity: at depth d at most min(K 8^d, N / L) nodes
@@ -679,8 +709,30 @@ fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const v
 
 // Composite coefficients of a forest, built once on the first evaluation;
 // every evaluating stream waits for their completion.
-static void ensure_composed(Forest& F, hipStream_t s) {
+static void ensure_composed(Forest& F, int problem, hipStream_t s) {
   std::lock_guard<std::mutex> g(F.compose_mu);
+  if (F.nodes >= (1u << 28)) fail(FMT_E_INVALID_ARG, "too many nodes for evaluation (2^28 at most)");
+  if (F.cell_tab.size() != F.probs.size()) {
+    F.cell_tab.resize(F.probs.size());
+    F.cell_T.assign(F.probs.size(), -1);
+    F.cell_ev.assign(F.probs.size(), nullptr);
+  }
+  if (!F.cell_ev[problem]) {
+    // 8^T entries: T <= 6 for one tree (1 MiB), <= 4 per tree of a batch
+    const int T = std::min(F.depth_present, F.probs.size() == 1 ? 6 : 4);
+    // [frame table | cells]; the frames use the problem's box, the same
+    // scale as the fit's node frames
+    DevBuf& b = F.cell_tab[problem];
+    b.alloc(1024 + (sizeof(uint32_t) << (3 * T)));
+    HIPCHK(launch_cell_table(F.table(), F.probs[problem].root, T, F.probs[problem].prm, b.as<double>(),
+                             (uint32_t*)(b.as<char>() + 1024), s));
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, s));
+    F.cell_T[problem] = T;
+    F.cell_ev[problem] = ev;
+  }
+  HIPCHK(hipStreamWaitEvent(s, F.cell_ev[problem], 0));
   if (!F.composed) {
     F.nb_ccoef.alloc(sizeof(double) * (size_t)F.L * std::max<uint32_t>(F.nodes, 1));
     {
@@ -705,18 +757,26 @@ fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const 
     if (!qx || !qy || !qz || !out) fail(FMT_E_INVALID_ARG, "NULL query or output pointer");
     hipStream_t s = (hipStream_t)stream;
     Forest& F = *tree->forest;
-    ensure_composed(F, s);
+    ensure_composed(F, tree->problem, s);
     EvalTree t;
     t.nt = F.table();
     t.root = F.probs[tree->problem].root;
     // query cells at the deepest level present: the same top bits as cells at
     // max_depth (the scale differs by an exact power of two)
     t.D = F.depth_present;
+    t.T = F.cell_T[tree->problem];
+    t.lvl = F.cell_tab[tree->problem].as<double>();
+    t.cells = (const uint32_t*)(F.cell_tab[tree->problem].as<char>() + 1024);
     t.prm = F.probs[tree->problem].prm;
     for (int a = 0; a < 3; ++a) t.prm.qscale[a] = std::ldexp(t.prm.qscale[a], t.D - F.D);
     const double* cc = F.nb_ccoef.as<double>();
     const uint32_t n = (uint32_t)nq;
-    const bool sort = t.D > 0 && (sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) && F.nodes > 64));
+    // Sorting makes the coefficient reads of a wave uniform; without it every
+    // lane reads its own node's row.  That is cheaper while the coefficient
+    // table stays cache-resident, so sort by default only for large tables.
+    const size_t coef_bytes = sizeof(double) * (size_t)F.L * F.nodes;
+    const bool sort = t.D > 0 && (sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) &&
+                                                       coef_bytes > (64ull << 20)));
     if (!sort) {
       ProfScope ps(KN_EVAL, n, s);
       HIPCHK(launch_eval(F.p, dtype, t, cc, qx, qy, qz, nullptr, nullptr, n, out, s));
@@ -750,7 +810,7 @@ fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const 
       // keys with the query coordinates and positions as payload
       ProfScope ps(KN_ESORT, n, s);
       if (e == hipSuccess)
-        e = radix_sort_payload3(dtype, k0, v0, k1, v1, pin, pay, pay_alt, n, 3 * t.D, scr, s, &in_alt);
+        e = radix_sort_payload(dtype, 3, k0, v0, k1, v1, pin, pay, pay_alt, n, 3 * t.D, scr, s, &in_alt);
     }
     uint32_t* ks = in_alt ? k1 : k0;
     uint32_t* vs = in_alt ? v1 : v0;

@@ -80,16 +80,57 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t nodes, d
 }
 
 // ---------------------------------------------------------------------------
-// One query per thread: walk down while the child holding the query's cell
-// exists (integer loads only), then evaluate the composite polynomial of the
-// node reached.  In sorted mode the coordinates arrive in key order (moved by
-// the sort), skeys holds their keys and perm their positions in the caller's
-// order, where the result is written.  A wave whose queries all reach one
-// node reads that node's coefficients with wave-uniform (scalar) loads.
+// Cell table: for every cell of depth T, the deepest node (level <= T) whose
+// cell contains it, found by walking down from the root.  One thread per
+// cell.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cell_table(NodeTable nt, uint32_t root, int T, ProblemParams prm,
+                                                   double* __restrict__ lvl, uint32_t* __restrict__ cells) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c <= (uint32_t)FMT_MAX_DEPTH) {
+    // frame of level c: h = (hi - lo) / 2^c, 2 / h (as the fit's node frames)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double h = ldexp(__dsub_rn(prm.hi[a], prm.lo[a]), -(int)c);
+      lvl[6 * c + a] = h;
+      lvl[6 * c + 3 + a] = __ddiv_rn(2.0, h);
+    }
+  }
+  if (c >= (1u << (3 * T))) return;
+  uint32_t node = root;
+  int d = 0;
+  for (; d < T; ++d) {
+    const uint32_t m = nt.child_mask[node];
+    const uint32_t o = (c >> (3 * (T - d - 1))) & 7u;
+    if (!((m >> o) & 1u)) break;
+    node = nt.first_child[node] + (uint32_t)__popc(m & ((1u << o) - 1u));
+  }
+  cells[c] = node | ((uint32_t)d << 28);
+}
+
+// Bits 3b + shift of v gathered into bit b (inverse of spread3).
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x000003FFu;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// One query per thread: the cell table gives the deepest node down to depth
+// T, the walk continues below T while the child holding the query's cell
+// exists (integer loads only), and the composite polynomial of the node
+// reached is evaluated.  The node's frame follows from its level and the
+// query's cell, exactly as the fit computes it, so no geometry is loaded.
+// In sorted mode the coordinates arrive in key order (moved by the sort),
+// skeys holds their keys and perm their positions in the caller's order,
+// where the result is written.  A wave whose queries all reach one node
+// reads that node's coefficients with wave-uniform (scalar) loads.
 // ---------------------------------------------------------------------------
 template <int P, typename TQ>
-__global__ void __launch_bounds__(256) k_eval(EvalTree t, const double* __restrict__ cc,
-                                              const double* __restrict__ geo, const TQ* __restrict__ qx,
+__global__ void __launch_bounds__(256) k_eval(EvalTree t, const double* __restrict__ cc, const TQ* __restrict__ qx,
                                               const TQ* __restrict__ qy, const TQ* __restrict__ qz,
                                               const uint32_t* __restrict__ perm, const uint32_t* __restrict__ skeys,
                                               uint32_t nq, double* __restrict__ out) {
@@ -109,24 +150,32 @@ __global__ void __launch_bounds__(256) k_eval(EvalTree t, const double* __restri
           (spread3(cell_of(y, t.prm.lo[1], t.prm.qscale[1], cmax, &bad)) << 1) |
           spread3(cell_of(z, t.prm.lo[2], t.prm.qscale[2], cmax, &bad));
   }
-  uint32_t node = t.root;
-  for (int d = 0; d < t.D; ++d) {
-    const uint32_t m = t.nt.child_mask[node];
-    const uint32_t o = (key >> (3 * (t.D - d - 1))) & 7u;
-    if (!((m >> o) & 1u)) break;
-    node = t.nt.first_child[node] + (uint32_t)__popc(m & ((1u << o) - 1u));
+  const uint32_t e = t.cells[key >> (3 * (t.D - t.T))];
+  uint32_t node = e & 0x0fffffffu;
+  int d = (int)(e >> 28);
+  if (d == t.T) {
+    for (; d < t.D; ++d) {
+      const uint32_t m = t.nt.child_mask[node];
+      const uint32_t o = (key >> (3 * (t.D - d - 1))) & 7u;
+      if (!((m >> o) & 1u)) break;
+      node = t.nt.first_child[node] + (uint32_t)__popc(m & ((1u << o) - 1u));
+    }
   }
+  // frame of the node reached: its cell is the query's cell at level d
+  const uint32_t cell = d > 0 ? key >> (3 * (t.D - d)) : 0u;
+  const uint32_t ci = compact3(cell >> 2), cj = compact3(cell >> 1), ck = compact3(cell);
+  const double* fr = t.lvl + 6 * d;
+  const double u = (x - __dadd_rn(t.prm.lo[0], __dmul_rn((double)ci + 0.5, fr[0]))) * fr[3];
+  const double v = (y - __dadd_rn(t.prm.lo[1], __dmul_rn((double)cj + 0.5, fr[1]))) * fr[4];
+  const double w = (z - __dadd_rn(t.prm.lo[2], __dmul_rn((double)ck + 0.5, fr[2]))) * fr[5];
   const uint32_t n0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)node);
   double val;
   if (__ballot(node != n0) == 0) {
     // read-only constant address space + a wave-uniform address: scalar loads
     typedef const double __attribute__((address_space(4))) cdouble;
-    const cdouble* g = (const cdouble*)(geo + 6 * (size_t)n0);
-    const cdouble* F = (const cdouble*)(cc + (size_t)n0 * L);
-    val = poly_eval<P, double>(F, (x - g[0]) * g[3], (y - g[1]) * g[4], (z - g[2]) * g[5]);
+    val = poly_eval<P, double>((const cdouble*)(cc + (size_t)n0 * L), u, v, w);
   } else {
-    const double* g = geo + 6 * (size_t)node;
-    val = poly_eval<P, double>(cc + (size_t)node * L, (x - g[0]) * g[3], (y - g[1]) * g[4], (z - g[2]) * g[5]);
+    val = poly_eval<P, double>(cc + (size_t)node * L, u, v, w);
   }
   if (valid) out[src] = val;
 }
@@ -142,6 +191,14 @@ hipError_t launch_compose(int p, const NodeTable& nt, uint32_t nodes, double* cc
   FMT_DISPATCH_P(p, compose_impl, nt, nodes, cc, s);
 }
 
+hipError_t launch_cell_table(const NodeTable& nt, uint32_t root, int T, const ProblemParams& prm, double* lvl,
+                             uint32_t* cells, hipStream_t s) {
+  const uint32_t n = 1u << (3 * T);
+  const uint32_t threads = n > (uint32_t)FMT_MAX_DEPTH + 1 ? n : (uint32_t)FMT_MAX_DEPTH + 1;
+  hipLaunchKernelGGL(k_cell_table, dim3((threads + 255) / 256), dim3(256), 0, s, nt, root, T, prm, lvl, cells);
+  return hipGetLastError();
+}
+
 template <int P>
 static hipError_t eval_impl(int dtype, const EvalTree& t, const double* cc, const void* qx, const void* qy,
                             const void* qz, const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out,
@@ -149,11 +206,11 @@ static hipError_t eval_impl(int dtype, const EvalTree& t, const double* cc, cons
   if (nq == 0) return hipSuccess;
   dim3 grid((nq + 255) / 256), block(256);
   if (dtype == FMT_F32)
-    hipLaunchKernelGGL((k_eval<P, float>), grid, block, 0, s, t, cc, (const double*)t.nt.geo, (const float*)qx,
-                       (const float*)qy, (const float*)qz, perm, skeys, nq, out);
+    hipLaunchKernelGGL((k_eval<P, float>), grid, block, 0, s, t, cc, (const float*)qx, (const float*)qy,
+                       (const float*)qz, perm, skeys, nq, out);
   else
-    hipLaunchKernelGGL((k_eval<P, double>), grid, block, 0, s, t, cc, (const double*)t.nt.geo, (const double*)qx,
-                       (const double*)qy, (const double*)qz, perm, skeys, nq, out);
+    hipLaunchKernelGGL((k_eval<P, double>), grid, block, 0, s, t, cc, (const double*)qx, (const double*)qy,
+                       (const double*)qz, perm, skeys, nq, out);
   return hipGetLastError();
 }
 

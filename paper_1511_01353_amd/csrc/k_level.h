@@ -28,8 +28,18 @@ struct EvalTree {
   NodeTable nt;
   uint32_t root;
   int D;               // deepest level holding a node (query keys use this depth)
+  int T;               // depth of the cell table (T <= D)
   ProblemParams prm;   // qscale = 2^D / (hi - lo) for that D
+  // per level d <= FMT_MAX_DEPTH: cell side h (3) then dilation 2 / h (3),
+  // computed as the fit computes node frames (so the values agree bit for bit)
+  const double* lvl;
+  // cell c of depth T -> deepest node (level <= T) containing it, as
+  // node | level << 28
+  const uint32_t* cells;
 };
+
+// Doubles of the per-level frame table in front of a cell table.
+constexpr int LVL_DOUBLES = 6 * (FMT_MAX_DEPTH + 1);
 
 // Doubles of one chunk's partial Gram (upper-triangular 16x16 blocks of the
 // augmented (L+1) x (L+1) matrix [Lambda | r]^T [Lambda | r]).
@@ -60,6 +70,10 @@ hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint3
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
 // Composite coefficients of every node (its chain's polynomials in its frame).
 hipError_t launch_compose(int p, const NodeTable& nt, uint32_t nodes, double* cc, hipStream_t s);
+// Cell table of one tree: 8^T entries, see EvalTree::cells.
+// Also writes the frame table lvl (LVL_DOUBLES) of the tree's problem.
+hipError_t launch_cell_table(const NodeTable& nt, uint32_t root, int T, const ProblemParams& prm, double* lvl,
+                             uint32_t* cells, hipStream_t s);
 // perm/skeys: sorted mode (query order and sorted keys), else both null.
 hipError_t launch_eval(int p, int dtype, const EvalTree& t, const double* cc, const void* qx, const void* qy,
                        const void* qz, const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out,

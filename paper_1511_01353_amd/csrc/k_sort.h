@@ -21,8 +21,10 @@ struct PayloadSet {
 constexpr uint32_t STATUS_DOMAIN = 1u;
 constexpr uint32_t STATUS_NONFINITE = 2u;
 
+// cat: if cat.x is set, the inputs are also copied there, concatenated in
+// global point order (x, y, z, f).
 hipError_t launch_keygen(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, int depth,
-                         uint32_t total, uint32_t* keys, uint32_t* status, hipStream_t s);
+                         uint32_t total, uint32_t* keys, uint32_t* status, const PtrSet& cat, hipStream_t s);
 hipError_t launch_query_keys(int dtype, const void* qx, const void* qy, const void* qz, uint32_t nq,
                              const ProblemParams& P, int depth, uint32_t* keys, hipStream_t s);
 // number of passes radix_sort makes over `bits` key bits (odd counts leave
@@ -35,17 +37,15 @@ size_t radix_sort_scratch_words(uint32_t n);
 // With vals_are_iota the input values are not read (value = position).
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n, int bits,
                       bool vals_are_iota, uint32_t* scratch, hipStream_t s, bool* result_in_alt);
-// radix_sort that also moves three payload arrays of the given dtype (4 or 8
-// bytes per element): pass 0 reads pin[] and the passes alternate between
-// pay_alt[] and pay[]; the sorted payload ends in pay[] when *result_in_alt
-// is false (an even number of passes), else in pay_alt[].  Values start as
-// source positions (not read).
-hipError_t radix_sort_payload3(int dtype, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
-                               const void* const* pin, void* const* pay, void* const* pay_alt, uint32_t n, int bits,
-                               uint32_t* scratch, hipStream_t s, bool* result_in_alt);
-hipError_t launch_gather(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, const uint32_t* order,
-                         uint32_t total, void* px, void* py, void* pz, double* r, hipStream_t s);
-hipError_t launch_permute3(int dtype, const void* x, const void* y, const void* z, const uint32_t* order,
-                           uint32_t n, void* ox, void* oy, void* oz, hipStream_t s);
+// radix_sort that also moves np (3 or 4) payload arrays of the given dtype
+// (4 or 8 bytes per element): pass 0 reads pin[] and the passes alternate
+// between pay_alt[] and pay[]; the sorted payload ends in pay[] when
+// *result_in_alt is false (an even number of passes), else in pay_alt[].
+// Values start as source positions (not read).
+hipError_t radix_sort_payload(int dtype, int np, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                              uint32_t* vals_alt, const void* const* pin, void* const* pay, void* const* pay_alt,
+                              uint32_t n, int bits, uint32_t* scratch, hipStream_t s, bool* result_in_alt);
+// r[i] = (double)f[i]
+hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, hipStream_t s);
 
 }  // namespace fmt

@@ -20,7 +20,7 @@ __device__ __forceinline__ uint32_t find_problem(const ProblemParams* prm, int n
 template <typename T>
 __global__ void __launch_bounds__(256) k_keygen(const PtrSet* ptrs, const ProblemParams* prm,
                                                 int nprob, int depth, uint32_t total,
-                                                uint32_t* keys, uint32_t* status) {
+                                                uint32_t* keys, uint32_t* status, PtrSet cat) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   uint32_t k = nprob == 1 ? 0u : find_problem(prm, nprob, g);
@@ -42,6 +42,13 @@ __global__ void __launch_bounds__(256) k_keygen(const PtrSet* ptrs, const Proble
   if (nprob > 1) key |= k << (3 * depth);
   keys[g] = key;
   if (bad) atomicOr(status, STATUS_DOMAIN);
+  if (cat.x) {
+    // a batch's inputs, concatenated in global point order (the sort's payload)
+    ((T*)cat.x)[g] = X[i];
+    ((T*)cat.y)[g] = Y[i];
+    ((T*)cat.z)[g] = Z[i];
+    ((T*)cat.f)[g] = ((const T*)ptrs[k].f)[i];
+  }
 }
 
 // Query keys for evaluation of one tree: same cell rule, no domain check
@@ -210,11 +217,12 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
   }
 }
 
-// The same pass moving NP payload arrays of PT along with (key, value): ranks
-// and destinations as above; each payload array is then staged through LDS
-// one at a time (read coalesced at the element's source position, written
-// coalesced at its destination), so the payload costs no registers during
-// ranking.  FIRST: values are source positions (not read).
+// The same pass moving NP payload arrays of PT along with (key, value).
+// Ranks and destinations as above; once keys and values are out, their LDS
+// staging area is reused for the payload, one array at a time (read
+// coalesced at the element's source position, written coalesced at its
+// destination), so the payload costs neither registers during ranking nor
+// extra LDS.  FIRST: values are source positions (not read).
 template <bool FIRST, typename PT, int NP>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ vin,
@@ -227,19 +235,34 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t
   constexpr int WAVES = SORT_THREADS / 64;
   constexpr int QUARTER = SORT_TILE / WAVES;
   constexpr int ROUNDS = QUARTER / 64;
+  constexpr int OUTS = SORT_TILE / SORT_THREADS;
+  static_assert(sizeof(PT) <= 8, "payload elements of at most 8 bytes");
   __shared__ uint32_t wcnt[WAVES][RADIX];
   __shared__ uint32_t lofs[RADIX];
   __shared__ uint32_t goff[RADIX];
   __shared__ uint32_t dbase[RADIX];
-  __shared__ uint32_t sk[SORT_TILE];
-  __shared__ uint32_t sv[SORT_TILE];
-  __shared__ PT sp[SORT_TILE];
+  __shared__ __attribute__((aligned(16))) uint32_t stage[2 * SORT_TILE];
+  uint32_t* sk = stage;
+  uint32_t* sv = stage + SORT_TILE;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   for (int i = tid; i < WAVES * RADIX; i += SORT_THREADS) (&wcnt[0][0])[i] = 0;
   __syncthreads();
 
   const uint64_t below_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint32_t base = blockIdx.x * SORT_TILE + w * QUARTER;
+  // 4-byte payloads are loaded up front so that their latency overlaps the
+  // ranking; wider ones are read again at staging time
+  constexpr bool PRELOAD = sizeof(PT) == 4;
+  PT pre[PRELOAD ? NP : 1][PRELOAD ? ROUNDS : 1];
+  if constexpr (PRELOAD) {
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+      for (int j = 0; j < ROUNDS; ++j) {
+        const uint32_t i = base + j * 64 + lane;
+        pre[a][j] = i < n ? pin.a[a][i] : PT(0);
+      }
+  }
   uint32_t key[ROUNDS], rank[ROUNDS];
 #pragma unroll
   for (int j = 0; j < ROUNDS; ++j) {
@@ -292,7 +315,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t
     goff[tid] = dbase[tid] - mine_g + offs[tid * gridDim.x + blockIdx.x];
   }
   __syncthreads();
-  // tile-local destination of each of this lane's elements
+  // tile-local position of each of this lane's elements
   uint32_t pos[ROUNDS];
 #pragma unroll
   for (int j = 0; j < ROUNDS; ++j) {
@@ -307,58 +330,38 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t
   __syncthreads();
   const uint32_t tile0 = blockIdx.x * SORT_TILE;
   const uint32_t tn = min((uint32_t)SORT_TILE, n - tile0);
-  for (uint32_t i = tid; i < tn; i += SORT_THREADS) {
-    const uint32_t k = sk[i];
-    const uint32_t d = (k >> shift) & (RADIX - 1);
-    const uint32_t o = goff[d] + (i - lofs[d]);
-    kout[o] = k;
-    vout[o] = sv[i];
+  // global destination of the tile positions this thread writes out
+  uint32_t dst[OUTS];
+#pragma unroll
+  for (int m = 0; m < OUTS; ++m) {
+    const uint32_t i = tid + m * SORT_THREADS;
+    if (i < tn) {
+      const uint32_t k = sk[i];
+      const uint32_t d = (k >> shift) & (RADIX - 1);
+      dst[m] = goff[d] + (i - lofs[d]);
+      kout[dst[m]] = k;
+      vout[dst[m]] = sv[i];
+    }
   }
+  PT* sp = (PT*)stage;
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
-    __syncthreads();   // sp is free again
+    __syncthreads();   // the staging area is free again
 #pragma unroll
     for (int j = 0; j < ROUNDS; ++j) {
       const uint32_t i = base + j * 64 + lane;
-      if (i < n) sp[pos[j]] = pin.a[a][i];
+      if (i < n) {
+        if constexpr (PRELOAD) sp[pos[j]] = pre[a][j];
+        else sp[pos[j]] = pin.a[a][i];
+      }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < tn; i += SORT_THREADS) {
-      const uint32_t d = (sk[i] >> shift) & (RADIX - 1);
-      pout.a[a][goff[d] + (i - lofs[d])] = sp[i];
+#pragma unroll
+    for (int m = 0; m < OUTS; ++m) {
+      const uint32_t i = tid + m * SORT_THREADS;
+      if (i < tn) pout.a[a][dst[m]] = sp[i];
     }
   }
-}
-
-// Gather points into key order; the residual starts as the sampled values.
-template <typename T>
-__global__ void __launch_bounds__(256) k_gather(const PtrSet* ptrs, const ProblemParams* prm, int nprob,
-                                                const uint32_t* __restrict__ order, uint32_t total,
-                                                T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
-                                                double* __restrict__ r) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  uint32_t g = order[i];
-  uint32_t k = nprob == 1 ? 0u : find_problem(prm, nprob, g);
-  uint32_t j = g - prm[k].offset;
-  px[i] = ((const T*)ptrs[k].x)[j];
-  py[i] = ((const T*)ptrs[k].y)[j];
-  pz[i] = ((const T*)ptrs[k].z)[j];
-  r[i] = (double)((const T*)ptrs[k].f)[j];
-}
-
-// Permute query coordinates into key order (for coherent evaluation).
-template <typename T>
-__global__ void __launch_bounds__(256) k_permute3(const T* __restrict__ x, const T* __restrict__ y,
-                                                  const T* __restrict__ z, const uint32_t* __restrict__ order,
-                                                  uint32_t n, T* __restrict__ ox, T* __restrict__ oy,
-                                                  T* __restrict__ oz) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t g = order[i];
-  ox[i] = x[g];
-  oy[i] = y[g];
-  oz[i] = z[g];
 }
 
 // ---------------------------------------------------------------------------
@@ -367,14 +370,14 @@ __global__ void __launch_bounds__(256) k_permute3(const T* __restrict__ x, const
 static inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_keygen(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, int depth,
-                         uint32_t total, uint32_t* keys, uint32_t* status, hipStream_t s) {
+                         uint32_t total, uint32_t* keys, uint32_t* status, const PtrSet& cat, hipStream_t s) {
   if (total == 0) return hipSuccess;
   if (dtype == FMT_F32)
     hipLaunchKernelGGL(k_keygen<float>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, depth,
-                       total, keys, status);
+                       total, keys, status, cat);
   else
     hipLaunchKernelGGL(k_keygen<double>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, depth,
-                       total, keys, status);
+                       total, keys, status, cat);
   return hipGetLastError();
 }
 
@@ -429,7 +432,7 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32
   return hipSuccess;
 }
 
-template <typename PT>
+template <typename PT, int NP>
 static hipError_t radix_sort_payload_t(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                        const void* const* pin, void* const* pay, void* const* pay_alt, uint32_t n,
                                        int bits, uint32_t* scratch, hipStream_t s, bool* result_in_alt) {
@@ -438,68 +441,73 @@ static hipError_t radix_sort_payload_t(uint32_t* keys, uint32_t* vals, uint32_t*
   uint32_t* tot = scratch + (size_t)RADIX * tiles;
   const int passes = radix_sort_passes(bits);
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-  PayloadSet<PT, 3> src, a, b;
-  for (int q = 0; q < 3; ++q) {
+  PayloadSet<PT, NP> src, a, b;
+  for (int q = 0; q < NP; ++q) {
     src.a[q] = (PT*)pin[q];
     a.a[q] = (PT*)pay[q];
     b.a[q] = (PT*)pay_alt[q];
   }
   // pass 0 reads the caller's payload and writes the alternate set, then the
   // sets alternate like the keys
-  PayloadSet<PT, 3> pi = src, po = b;
+  PayloadSet<PT, NP> pi = src, po = b;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * RADIX_BITS;
     hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
     hipLaunchKernelGGL(k_digit_scan, dim3(RADIX), dim3(256), 0, s, hist, tiles, tot);
     if (p == 0)
-      hipLaunchKernelGGL((k_radix_scatter_p<true, PT, 3>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi, ko,
+      hipLaunchKernelGGL((k_radix_scatter_p<true, PT, NP>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi, ko,
                          vo, po, n, shift, hist, tot);
     else
-      hipLaunchKernelGGL((k_radix_scatter_p<false, PT, 3>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi, ko,
-                         vo, po, n, shift, hist, tot);
+      hipLaunchKernelGGL((k_radix_scatter_p<false, PT, NP>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi,
+                         ko, vo, po, n, shift, hist, tot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
     pi = po;
     po = (p % 2 == 0) ? a : b;
   }
   *result_in_alt = ki != keys;
-  return hipGetLastError();
+  return hipSuccess;
 }
 
-hipError_t radix_sort_payload3(int dtype, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
-                               const void* const* pin, void* const* pay, void* const* pay_alt, uint32_t n, int bits,
-                               uint32_t* scratch, hipStream_t s, bool* result_in_alt) {
+hipError_t radix_sort_payload(int dtype, int np, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                              uint32_t* vals_alt, const void* const* pin, void* const* pay, void* const* pay_alt,
+                              uint32_t n, int bits, uint32_t* scratch, hipStream_t s, bool* result_in_alt) {
   *result_in_alt = false;
   if (n == 0) return hipSuccess;
-  if (dtype == FMT_F32)
-    return radix_sort_payload_t<float>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
-                                       result_in_alt);
-  return radix_sort_payload_t<double>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
-                                      result_in_alt);
+  if (np == 3) {
+    if (dtype == FMT_F32)
+      return radix_sort_payload_t<float, 3>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
+                                            result_in_alt);
+    return radix_sort_payload_t<double, 3>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
+                                           result_in_alt);
+  }
+  if (np == 4) {
+    if (dtype == FMT_F32)
+      return radix_sort_payload_t<float, 4>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
+                                            result_in_alt);
+    return radix_sort_payload_t<double, 4>(keys, vals, keys_alt, vals_alt, pin, pay, pay_alt, n, bits, scratch, s,
+                                           result_in_alt);
+  }
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_gather(int dtype, const PtrSet* ptrs, const ProblemParams* prm, int nprob, const uint32_t* order,
-                         uint32_t total, void* px, void* py, void* pz, double* r, hipStream_t s) {
-  if (total == 0) return hipSuccess;
-  if (dtype == FMT_F32)
-    hipLaunchKernelGGL(k_gather<float>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, order,
-                       total, (float*)px, (float*)py, (float*)pz, r);
-  else
-    hipLaunchKernelGGL(k_gather<double>, dim3(blocks_for(total, 256)), dim3(256), 0, s, ptrs, prm, nprob, order,
-                       total, (double*)px, (double*)py, (double*)pz, r);
-  return hipGetLastError();
+// residual start: the sorted values, widened to float64
+template <typename T>
+__global__ void __launch_bounds__(256) k_widen(const T* __restrict__ f, uint32_t n, double* __restrict__ r) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r[i] = (double)f[i];
 }
 
-hipError_t launch_permute3(int dtype, const void* x, const void* y, const void* z, const uint32_t* order,
-                           uint32_t n, void* ox, void* oy, void* oz, hipStream_t s) {
+hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (dtype == FMT_F32)
-    hipLaunchKernelGGL(k_permute3<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const float*)x,
-                       (const float*)y, (const float*)z, order, n, (float*)ox, (float*)oy, (float*)oz);
+    hipLaunchKernelGGL(k_widen<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const float*)f, n, r);
   else
-    hipLaunchKernelGGL(k_permute3<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const double*)x,
-                       (const double*)y, (const double*)z, order, n, (double*)ox, (double*)oy, (double*)oz);
+    hipLaunchKernelGGL(k_widen<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const double*)f, n, r);
   return hipGetLastError();
 }
+
 
 }  // namespace fmt
