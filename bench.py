@@ -113,6 +113,35 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
     return out
 
 
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1511_01353_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith(".hip") or f.endswith(".h"):
+            h.update(f.encode())
+            with open(os.path.join(src, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Per-class HBM bytes per launch from the committed rocprofv3 --pmc summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_fit_eval_n2p20_p6.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        text = fh.read()
+    tag = "<!-- traffic-json: "
+    if tag not in text:
+        return None
+    doc = json.loads(text.split(tag, 1)[1].split(" -->", 1)[0])
+    if doc.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return {c: v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"] for c, v in doc["classes"].items()}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,7 +250,10 @@ def main():
     # with a roofline definition
     dom = max((kv for kv in h["kernels"].items() if kv[0] in roofs), key=lambda kv: kv[1]["ms_per_step"])[0]
     roof = dict(kernel=dom, **roofs[dom])
-    roof["traffic"] = None
+    traffic = measured_traffic() if args.path == "fp64" and args.n == 1 << 20 and args.nq == 1 << 22 else None
+    roof["traffic"] = traffic.get(dom) if traffic else None
+    for k, v in roofs.items():
+        v["traffic"] = traffic.get(k) if traffic else None
     gram_roof = roofs.get("gram")
 
     cpu = None
