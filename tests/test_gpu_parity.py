@@ -134,6 +134,7 @@ def print_case(name, pr):
     (9000, 2, 5, 1e-5, 13, np.float32),
     (5000, 0, 3, 0.0, 14, np.float64),
     (3000, 5, 2, 1e-7, 15, np.float64),
+    (40000, 8, 2, 1e-8, 16, np.float32),       # calL = 165: the largest basis
 ])
 def test_fp64_path_matches_oracle(fmt, n, p, depth, tol, seed, dtype):
     pr = synthetic.small_problem(n, p, seed, tol=tol, depth=depth, dtype=dtype, nq=5000)
