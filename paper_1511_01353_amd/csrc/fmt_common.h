@@ -128,6 +128,52 @@ __device__ __forceinline__ void poly_eval_multi(const FPtr F, const double (&u)[
   for (int q = 0; q < NPT; ++q) out[q] = f[q];
 }
 
+// poly_eval for NPT points at once with the per-point step tables t/(k+1)
+// formed first (as poly_eval does): each coefficient read feeds NPT
+// independent Horner chains.  Same operations per point as poly_eval.
+template <int P, int NPT, typename FPtr>
+__device__ __forceinline__ void poly_eval_n(const FPtr F, const double (&u)[NPT], const double (&v)[NPT],
+                                            const double (&w)[NPT], double (&out)[NPT]) {
+  double ud[NPT][P + 1], vd[NPT][P + 1], wd[NPT][P + 1];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q)
+#pragma unroll
+    for (int k = 0; k <= P; ++k) {
+      ud[q][k] = u[q] * (1.0 / (double)(k + 1));
+      vd[q][k] = v[q] * (1.0 / (double)(k + 1));
+      wd[q][k] = w[q] * (1.0 / (double)(k + 1));
+    }
+  double f[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) f[q] = 0.0;
+#pragma unroll
+  for (int l = P; l >= 0; --l) {
+    double g[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) g[q] = 0.0;
+#pragma unroll
+    for (int m = P - l; m >= 0; --m) {
+      double h[NPT];
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) h[q] = 0.0;
+#pragma unroll
+      for (int n = P - l - m; n >= 0; --n) {
+        const int k = l + m + n;
+        const int idx = k * (k + 1) * (k + 2) / 6 + (k - l) * (k - l + 1) / 2 + (k - l - m);
+        const double c = F[idx];
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) h[q] = c + h[q] * wd[q][n];
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) g[q] = h[q] + g[q] * vd[q][m];
+    }
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) f[q] = g[q] + f[q] * ud[q][l];
+  }
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) out[q] = f[q];
+}
+
 // sum_i C[i] u^a v^b w^c for NPT points at once, with C the coefficients
 // already divided by a! b! c! (plain monomials, so a point needs only u, v,
 // w).  Every coefficient is read once and feeds NPT independent Horner

@@ -67,6 +67,24 @@ struct ProfAcc {
 };
 ProfAcc g_prof_acc[KN_COUNT];
 
+// Events are recycled: creating them per launch would put host work
+// between the launches being timed.
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pooled_event() {
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_event_pool.empty()) {
+      hipEvent_t e = g_event_pool.back();
+      g_event_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
 struct ProfScope {
   bool on;
   int kernel;
@@ -79,8 +97,8 @@ struct ProfScope {
       on = g_prof_on;
     }
     if (on) {
-      HIPCHK(hipEventCreate(&a));
-      HIPCHK(hipEventCreate(&b));
+      a = pooled_event();
+      b = pooled_event();
       HIPCHK(hipEventRecord(a, s));
     }
   }
@@ -102,8 +120,8 @@ void prof_resolve() {
       g_prof_acc[r.kernel].ms += ms;
       g_prof_acc[r.kernel].units += r.units;
     }
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    g_event_pool.push_back(r.a);
+    g_event_pool.push_back(r.b);
   }
   g_prof_pending.clear();
 }
