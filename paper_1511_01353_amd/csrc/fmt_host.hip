@@ -167,14 +167,52 @@ struct Workspace {
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status, params, ptrs;
   uint32_t* host_counters = nullptr;
+  // host-visible, fine-grained words the topology kernel writes the next
+  // level's counters and a sequence number into (host view and device view)
+  uint32_t* level_flag = nullptr;
+  uint32_t* level_flag_dev = nullptr;
+  uint32_t level_seq = 0;
   char* stage = nullptr;        // pinned staging for small host-to-device copies
   size_t stage_bytes = 0;
   std::mutex mu;
-  Workspace() { hip_check(hipHostMalloc((void**)&host_counters, 64, hipHostMallocDefault), "hipHostMalloc"); }
+  Workspace() {
+    hip_check(hipHostMalloc((void**)&host_counters, 64, hipHostMallocDefault), "hipHostMalloc");
+    hip_check(hipHostMalloc((void**)&level_flag, 64, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc");
+    std::memset(level_flag, 0, 64);
+    hip_check(hipHostGetDevicePointer((void**)&level_flag_dev, level_flag, 0), "hipHostGetDevicePointer");
+  }
   ~Workspace() {
     if (host_counters) (void)hipHostFree(host_counters);
+    if (level_flag) (void)hipHostFree(level_flag);
     if (stage) (void)hipHostFree(stage);
   }
+  // Wait for the topology kernel's counters of sequence number seq: spin on
+  // the host-visible word; every few thousand spins ask whether the stream
+  // has drained (then the word must be there, else read the device copy).
+  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[3]) {
+    for (uint64_t it = 1;; ++it) {
+      if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) {
+        out[0] = __atomic_load_n(level_flag + 0, __ATOMIC_RELAXED);
+        out[1] = __atomic_load_n(level_flag + 1, __ATOMIC_RELAXED);
+        out[2] = __atomic_load_n(level_flag + 2, __ATOMIC_RELAXED);
+        return;
+      }
+      if ((it & 4095) == 0) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess) {
+          if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) continue;
+          HIPCHK(hipMemcpy(host_counters, counters_dev, 12, hipMemcpyDeviceToHost));
+          out[0] = host_counters[0];
+          out[1] = host_counters[1];
+          out[2] = host_counters[2];
+          return;
+        }
+        if (e != hipErrorNotReady) hip_check(e, "level wait");
+      }
+      __builtin_ia32_pause();
+    }
+  }
+  const void* counters_dev = nullptr;
   // Pinned buffer of at least n bytes; callers reuse it only after the
   // stream has passed the copies that read it.
   char* staging(size_t n) {
@@ -553,17 +591,19 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
                              W.nact.as<uint32_t>(), s));
     }
     const uint32_t next0 = node0 + nnodes;
+    const uint32_t seq = ++W.level_seq;
     {
       ProfScope ps(KN_EMIT, nnodes, s);
       HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
-                         next_off->as<uint32_t>(), W.counters.as<uint32_t>(), s));
+                         next_off->as<uint32_t>(), W.counters.as<uint32_t>(), W.level_flag_dev, seq, s));
     }
-    HIPCHK(hipMemcpyAsync(W.host_counters, W.counters.p, 12, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    uint32_t cnt[3];
+    W.counters_dev = W.counters.p;
+    W.wait_level(seq, s, cnt);
     node0 = next0;
-    nnodes = W.host_counters[0];
-    nchunks = W.host_counters[1];
-    level_points = W.host_counters[2];
+    nnodes = cnt[0];
+    nchunks = cnt[1];
+    level_points = cnt[2];
     std::swap(cur_off, next_off);
   }
   F->nodes = node0;

@@ -65,8 +65,12 @@ hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, 
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s);
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
                            uint32_t* nact, hipStream_t s);
+// counters[0..2] = next level's nodes, chunks, points; with hostc (device view
+// of host-visible memory) they are also written there, followed by seq at
+// hostc[3] (system-scope release).
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
-                       uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, hipStream_t s);
+                       uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
+                       uint32_t seq, hipStream_t s);
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
 // Composite coefficients of every node (its chain's polynomials in its frame).
 hipError_t launch_compose(int p, const NodeTable& nt, uint32_t nodes, double* cc, hipStream_t s);

@@ -601,7 +601,8 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
                                                const uint32_t* __restrict__ cbeg, const uint32_t* __restrict__ ccnt,
                                                uint32_t* __restrict__ nact, uint32_t next0,
                                                uint32_t* __restrict__ next_chunk_off,
-                                               uint32_t* __restrict__ counters) {
+                                               uint32_t* __restrict__ counters, uint32_t* __restrict__ hostc,
+                                               uint32_t seq) {
   __shared__ uint32_t s[1024];
   const uint32_t tid = threadIdx.x;
   const uint32_t m = a.nnodes;
@@ -681,6 +682,14 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     counters[0] = total;
     counters[1] = s[1023];
     counters[2] = next_points;
+    if (hostc) {
+      // the same counters into host-visible (fine-grained) memory, then the
+      // sequence number with a system-scope release: the host waits on it
+      hostc[0] = total;
+      hostc[1] = s[1023];
+      hostc[2] = next_points;
+      __hip_atomic_store(hostc + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -757,8 +766,10 @@ hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uin
 }
 
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
-                       uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, hipStream_t s) {
-  hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, s, a, prm, cbeg, ccnt, nact, next0, next_chunk_off, counters);
+                       uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
+                       uint32_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, s, a, prm, cbeg, ccnt, nact, next0, next_chunk_off, counters,
+                     hostc, seq);
   return hipGetLastError();
 }
 
