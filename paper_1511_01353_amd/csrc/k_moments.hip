@@ -144,12 +144,22 @@ __device__ __forceinline__ void moments_group(const LevelArgs& a, uint32_t start
   double acc[NA];
 #pragma unroll
   for (int s = 0; s < NA; ++s) acc[s] = 0.0;
+  // the next point's data is loaded one iteration ahead (index clamped into
+  // the chunk), so its latency overlaps this point's arithmetic
+  double nx = 0.0, ny = 0.0, nz = 0.0, nw = 0.0;
+  if (start + lane < end) {
+    load_point<TIN>(a.px, a.py, a.pz, start + lane, nx, ny, nz);
+    nw = MODE == 1 ? rp[lane] : a.r[start + lane];
+  }
 #pragma unroll 1
   for (uint32_t i = start + lane; i < end; i += 64) {
-    double x, y, z;
-    load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
+    const double x = nx, y = ny, z = nz, wt = nw;
+    {
+      const uint32_t j = min(i + 64, end - 1);
+      load_point<TIN>(a.px, a.py, a.pz, j, nx, ny, nz);
+      nw = MODE == 1 ? rp[j - start] : a.r[j];
+    }
     const double u = (x - cx) * sx, v = (y - cy) * sy, w = (z - cz) * sz;
-    const double wt = MODE == 1 ? rp[i - start] : a.r[i];
     double pu[P2 + 1], pv[P2 + 1], pw[P2 + 1];
     pu[0] = pv[0] = pw[0] = 1.0;
 #pragma unroll
