@@ -83,7 +83,14 @@ typedef struct {
   double tol;          /* tau: split tolerance on the octant RMS residual, >= 0 */
   int max_depth;       /* D, 0..FMT_MAX_DEPTH; the root is depth 0 */
   int path;            /* fmt_path */
-  int refine_steps;    /* iterative-refinement sweeps per node, 0..8 */
+  int refine_steps;    /* iterative-refinement sweeps, 0..8: a sweep
+                          recomputes the residual from the points and
+                          corrects the coefficients with the kept factor.
+                          The mixed path applies them to every node; the
+                          float64 path only to nodes whose equilibrated
+                          normal equations have an estimated condition
+                          number above 1e6 or a deflated pivot (elsewhere
+                          the float64 solve is already accurate). */
   double box_lo[3];    /* root box; default 0 */
   double box_hi[3];    /* default 1; box_hi > box_lo on every axis */
   int gram;            /* fmt_gram: how the float64 path forms the normal
@@ -173,7 +180,11 @@ fmt_status fmt_tree_get_info(const fmt_tree* tree, fmt_tree_info* info);
  *   flags  : bit 0 set if a Cholesky pivot was deflated (the node's points
  *            do not determine every basis coefficient: the fitted values at
  *            the points are unique, the polynomial away from them is not);
- *            bit 1 set if a coefficient was not finite
+ *            bit 1 set if a coefficient was not finite;
+ *            bit 2 set if the node's coefficients went through the
+ *            refinement sweep (always on the mixed path; on the float64 path
+ *            only for nodes whose normal equations are ill-conditioned or
+ *            deflated, see fmt_fit_opts.refine_steps)
  */
 fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t* prefix,
                                  uint32_t* begin, uint32_t* count, uint32_t* flags, double* coeffs);

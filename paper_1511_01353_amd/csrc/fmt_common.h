@@ -245,6 +245,7 @@ struct NodeTable {
 
 constexpr uint32_t FLAG_DEFLATED = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
+constexpr uint32_t FLAG_REFINE = 4u;   // the refinement sweeps apply to this node
 
 // Per-problem parameters of one batched fit.
 struct ProblemParams {

@@ -549,6 +549,9 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     a.level = d;
     a.D = F->D;
     a.tol = tols[0];
+    // the mixed path's float32 Gram always needs the sweeps; the float64
+    // path applies them where the conditioning estimate asks for them
+    a.refine = F->refine == 0 ? 0 : (F->path == FMT_PATH_MIXED ? 2 : 1);
 
     const bool multi = nchunks > nnodes;   // some node spans several chunks
     {

@@ -22,6 +22,7 @@ struct LevelArgs {
   int level;                 // depth of this level
   int D;                     // maximum depth
   double tol;                // split tolerance
+  int refine;                // 0: no refinement; 1: nodes whose conditioning needs it; 2: every node
 };
 
 struct EvalTree {

@@ -243,20 +243,55 @@ __device__ __forceinline__ void tri_solve_wave(const double* A, const double* iv
 // K6 variants.  A holds the equilibrated matrix (blocked, padding = identity),
 // b the scaled right-hand side, sc the equilibration scales.  The kept factor
 // is [blocked L and D | D | D^-1 | sc].
+// Refinement is needed where the equilibrated normal equations are
+// ill-conditioned: with the estimate below at or under this bound the float64
+// solve's fitted values are accurate to ~1e-13 relative, and one sweep is
+// applied above it.
+constexpr double REFINE_KAPPA = 1e6;
+
+// Entry i of the fixed probe vector `which` (0 or 1): +-1/sqrt(L) with signs
+// from an integer hash, so the estimate is deterministic.
+__device__ __forceinline__ double probe_entry(int i, int which, int L) {
+  uint32_t h = (uint32_t)i * 0x9E3779B1u + (uint32_t)which * 0x85EBCA77u + 0x165667B1u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  return ((h >> 7) & 1u ? 1.0 : -1.0) * rsqrt((double)L);
+}
+
 template <int L>
 __device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dv, double* iv,
-                                                   const double* sc, const LevelArgs& a, uint32_t k, uint32_t node,
-                                                   double* fac) {
+                                                   const double* sc, double (*xv)[L], double (*yv)[L],
+                                                   const LevelArgs& a, uint32_t k, uint32_t node, double* fac) {
   using S = BlockShape<L>;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const bool estimate = a.refine == 1;
+  if (estimate)
+    for (int e = tid; e < 2 * L; e += 256) xv[e / L][e % L] = probe_entry(e % L, e / L, L);
   ldl_blocked<L>(A, dv, iv);
-  if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
+  // wave 0 solves for the coefficients; waves 1 and 2 meanwhile apply the
+  // inverse to the two probe vectors (|G^-1 x| <= 1 / lambda_min, close to
+  // it for all but exceptional x), a condition estimate at no extra latency
+  if (w == 0) tri_solve_wave<L>(A, iv, b, z);
+  else if (estimate && w <= 2) tri_solve_wave<L>(A, iv, xv[w - 1], yv[w - 1]);
   __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
   bool deflated = false;
   for (int i = tid; i < L; i += 256) {
     F[i] = sc[i] * z[i];
     if (iv[i] == 0.0) deflated = true;
+  }
+  if (estimate && (w == 1 || w == 2)) {
+    double ss = 0.0;
+    for (int i = lane; i < L; i += 64) ss += yv[w - 1][i] * yv[w - 1][i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off);
+    if (lane == 0 && (double)L * sqrt(ss) > REFINE_KAPPA) atomicOr(a.nt.flags + node, FLAG_REFINE);
+  }
+  if (a.refine == 2) {
+    if (tid == 0) atomicOr(a.nt.flags + node, FLAG_REFINE);
+  } else if (estimate && deflated) {
+    atomicOr(a.nt.flags + node, FLAG_REFINE);
   }
   if (fac) {
     double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
@@ -306,6 +341,7 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   using S = BlockShape<L>;
   __shared__ double A[S::WORDS + 16];   // + the zero row
   __shared__ double b[L], z[L], dv[S::LP], iv[S::LP], sc[L];   // pivots cover the padding too
+  __shared__ double xv[2][L], yv[2][L];                           // condition-estimate probes
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
@@ -326,7 +362,7 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   __syncthreads();
   assemble_blocked<L>(A, [&](int i, int q) { return (i <= q ? gram(i, q) : gram(q, i)) * sc[i] * sc[q]; });
   __syncthreads();
-  factor_solve_store<L>(A, b, z, dv, iv, sc, a, k, node, fac);
+  factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a, k, node, fac);
 }
 
 // ---------------------------------------------------------------------------
@@ -345,9 +381,12 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   constexpr Basis<P> B{};
   using S = BlockShape<L>;
   __shared__ double A[S::WORDS + 16];   // + the zero row
-  __shared__ double mom[NOUT];
+  __shared__ double mom[NOUT > 4 * L ? NOUT : 4 * L];
   __shared__ double b[L], z[L], dv[S::LP], iv[S::LP], sc[L], wv[L];   // pivots cover the padding too
   __shared__ int ex[L][3];
+  // the condition-estimate probes reuse the moments' space (dead after assembly)
+  double(*xv)[L] = reinterpret_cast<double(*)[L]>(mom);
+  double(*yv)[L] = reinterpret_cast<double(*)[L]>(mom + 2 * L);
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
@@ -372,7 +411,7 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
     return mom[graded(ex[i][0] + ex[q][0], ex[i][1] + ex[q][1], ex[i][2] + ex[q][2])] * wv[i] * wv[q];
   });
   __syncthreads();
-  factor_solve_store<L>(A, b, z, dv, iv, sc, a, k, node, fac);
+  factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a, k, node, fac);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,6 +430,7 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
+  if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
   for (int e = tid; e < S::WORDS; e += 256) A[e] = fo[e];

@@ -219,6 +219,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NW * 64)) k_moments(Leve
   const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
   const double* geo = a.nt.geo + 6 * (size_t)node;
   if constexpr (MODE == 1) {
+    if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
     // r' once per point, four points per thread at a time; the node's
     // coefficients are wave-uniform and read with scalar loads (read-only
     // constant address space), so they take no vector registers

@@ -299,3 +299,27 @@ def test_batch_equals_single_fits(fmt):
         qs = ts.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
         np.testing.assert_array_equal(qa, qs)
         compare_eval(ot, nodes, pr, qa, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.2)
+
+
+def test_refinement_applies_where_conditioning_needs_it(fmt):
+    """Float64 path: the refinement sweep is applied exactly to nodes whose
+    equilibrated normal equations are ill-conditioned (or deflated); the
+    mixed path refines every node.  Either way the fitted values stay at the
+    oracle's."""
+    well = synthetic.small_problem(30001, 6, 12, tol=1e-8, depth=3, dtype=np.float32)
+    ill = synthetic.small_problem(30000, 8, 22, tol=1e-8, depth=3, dtype=np.float32, clustered=True)
+    for pr, expect_some in ((well, False), (ill, True)):
+        print_case("refinement flags", pr)
+        tr = run_fit(fmt, pr)
+        nodes, pts = tr.export_nodes(), tr.export_points()
+        refined = (nodes["flags"] & 4) != 0
+        print(f"refined nodes: {int(refined.sum())} of {refined.size}", flush=True)
+        assert refined.any() == expect_some
+        assert np.all(refined[(nodes["flags"] & 1) != 0])   # deflated nodes are always refined
+        ot = oracle_fit(pr)
+        compare_topology(tr, ot)
+        assert fitted_rms(pr, pts, ot) <= FP64_RMS
+        tr.close()
+    tr = run_fit(fmt, well, path=1, refine=3)
+    assert np.all((tr.export_nodes()["flags"] & 4) != 0)
+    tr.close()
