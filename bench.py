@@ -46,6 +46,18 @@ def moment_flops_per_point(p: int) -> float:
     return 2.0 * (nm + nb + 1) + runs + 3 * 2 * p
 
 
+def bmoment_flops_per_point(p: int) -> float:
+    # r-weighted moments only (|alpha| <= p): one multiply-add each, one
+    # product per run, and the powers up to p
+    return 2.0 * basis_count(p) + (p + 1) * (p + 2) // 2 + 3 * p
+
+
+def base_moment_flops_per_point(p: int) -> float:
+    # power moments only (|gamma| <= 2p), once per point at the pyramid's
+    # finest level
+    return 2.0 * basis_count(2 * p) + (2 * p + 1) * (2 * p + 2) // 2 + 3 * 2 * p
+
+
 def refine_flops_per_point(p: int) -> float:
     # r' = r - Lambda F (about 2L) and the r'-weighted moments (2L + runs + powers)
     L = basis_count(p)
@@ -83,6 +95,8 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
         add("gram", "mfma", gram_flops_per_point(L), "TFLOP/s", PEAK_TFLOPS["fp32"])
     else:
         add("gram", "alu", moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("bmoments", "alu", bmoment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("base_moments", "alu", base_moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("solve", "alu", solve_flops_per_node(L), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("refine_solve", "alu", 2.0 * L * L, "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("refine_sweep", "alu", refine_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])

@@ -72,10 +72,18 @@ typedef enum {
 
 typedef enum {
   /* power moments M_gamma = sum u^gamma (|gamma| <= 2p) accumulated on the
-     float64 vector ALUs; Gram entries are M_{alpha+beta} / (alpha! beta!) */
+     float64 vector ALUs; Gram entries are M_{alpha+beta} / (alpha! beta!).
+     M does not depend on the residual: for the top levels of the tree it is
+     accumulated once over the cells of one level (the deepest whose cells
+     hold calL points on average, at most 5) and carried to the coarser
+     levels by an exact change of frame (the moment pyramid); each of those
+     levels then accumulates only the r-weighted moments B_alpha */
   FMT_GRAM_MOMENTS = 0,
   /* the Gram [Lambda|r]^T [Lambda|r] formed on float64 MFMA */
-  FMT_GRAM_MFMA = 1
+  FMT_GRAM_MFMA = 1,
+  /* power moments as FMT_GRAM_MOMENTS, but M and B accumulated from the
+     points at every level (no pyramid) */
+  FMT_GRAM_MOMENTS_LEVEL = 2
 } fmt_gram;
 
 typedef struct {

@@ -13,7 +13,7 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
-SOURCES = ["k_sort.hip", "k_gram.hip", "k_moments.hip", "k_level.hip", "k_eval.hip", "fmt_host.hip"]
+SOURCES = ["k_sort.hip", "k_gram.hip", "k_moments.hip", "k_pyramid.hip", "k_level.hip", "k_eval.hip", "fmt_host.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -55,9 +55,10 @@ struct ProfRecord {
   double units;   // points (or queries) the launch covered
 };
 const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce", "solve", "refine_sweep",
-                              "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval", "compose"};
+                              "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval", "compose",
+                              "bmoments", "base_moments", "pyramid"};
 enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
-       KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_COUNT };
+       KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_BMOM, KN_BASEM, KN_PYR, KN_COUNT };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof_pending;
@@ -166,6 +167,10 @@ struct Workspace {
   // px, py, pz, pf: key-ordered inputs (payload set A); px2 .. pf2: set B
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status, params, ptrs;
+  // moment pyramid: entries, tables, the finest cells' point ranges,
+  // frames, chunk counts, entries, chunk offsets and chunk partials; the
+  // B-only partials of the levels it covers
+  DevBuf pyr, pyr_tab, pyr_begin, pyr_count, pyr_geo, pyr_nchk, pyr_dst, pyr_off, pyr_part, part_m2;
   uint32_t* host_counters = nullptr;
   // host-visible, fine-grained words the topology kernel writes the next
   // level's counters and a sequence number into (host view and device view)
@@ -361,7 +366,8 @@ void validate_opts(const fmt_fit_opts& o) {
   if (!(o.tol >= 0.0) || std::isinf(o.tol)) fail(FMT_E_INVALID_ARG, "tol must be finite and >= 0");
   if (o.path != FMT_PATH_FP64 && o.path != FMT_PATH_MIXED) fail(FMT_E_INVALID_ARG, "unknown path");
   if (o.refine_steps < 0 || o.refine_steps > kRefineMax) fail(FMT_E_INVALID_ARG, "refine_steps out of range 0..8");
-  if (o.gram != FMT_GRAM_MOMENTS && o.gram != FMT_GRAM_MFMA) fail(FMT_E_INVALID_ARG, "unknown gram method");
+  if (o.gram != FMT_GRAM_MOMENTS && o.gram != FMT_GRAM_MFMA && o.gram != FMT_GRAM_MOMENTS_LEVEL)
+    fail(FMT_E_INVALID_ARG, "unknown gram method");
   for (int a = 0; a < 3; ++a)
     if (!(o.box_hi[a] > o.box_lo[a]) || !std::isfinite(o.box_lo[a]) || !std::isfinite(o.box_hi[a]))
       fail(FMT_E_INVALID_ARG, "box_hi must exceed box_lo on every axis");
@@ -437,14 +443,92 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   W.ptrs.reserve(sizeof(PtrSet) * K);
   W.status.reserve(64);
   W.counters.reserve(64);
+
+  // Moment pyramid of each problem (float64 power-moment path): its depth
+  // kp is the deepest level (at most 5, at most D) whose cells hold calL
+  // points on average, 0 (none) if that is the root.  It depends on the
+  // problem alone, so a problem fitted in a batch gets the bits it gets
+  // fitted alone.  Batches beyond the table limits fit without pyramids.
+  const bool use_moments = F->gram == FMT_GRAM_MOMENTS || F->gram == FMT_GRAM_MOMENTS_LEVEL;
+  const uint32_t NMB = (uint32_t)moment_base_doubles(F->p);
+  std::vector<uint32_t> kp(K, 0);
+  if (F->gram == FMT_GRAM_MOMENTS)
+    for (int k = 0; k < K; ++k) {
+      int d = 0;
+      while (d < std::min(F->D, 5) && (uint64_t)in[k].n >= ((uint64_t)L << (3 * (d + 1)))) ++d;
+      kp[k] = (uint32_t)d;
+    }
+  // device table: (first entry, kp, first flat finest cell, 0) per problem |
+  // first flat finest cell of each pyramid (+ total) | its problem | per
+  // level d, the problems with kp > d
+  std::vector<uint32_t> ptab;
+  uint64_t pyr_cells = 0, base_cells = 0, pyr_chunk_bound = 0;
+  int npyr = 0, kp_max = 0;
+  std::vector<uint32_t> list_off, list_n;
+  for (int pass = 0; pass < 2; ++pass) {
+    ptab.assign((size_t)PYR_TAB_WORDS * K, 0);
+    std::vector<uint32_t> cstart, bq;
+    pyr_cells = base_cells = 0;
+    kp_max = 0;
+    for (int k = 0; k < K; ++k) {
+      ptab[PYR_TAB_WORDS * k] = (uint32_t)pyr_cells;
+      ptab[PYR_TAB_WORDS * k + 1] = kp[k];
+      ptab[PYR_TAB_WORDS * k + 2] = (uint32_t)base_cells;
+      if (kp[k] == 0) continue;
+      cstart.push_back((uint32_t)base_cells);
+      bq.push_back((uint32_t)k);
+      pyr_cells += level_first((int)kp[k] + 1);
+      base_cells += 1ull << (3 * kp[k]);
+      kp_max = std::max(kp_max, (int)kp[k]);
+    }
+    npyr = (int)bq.size();
+    pyr_chunk_bound = N / CHUNK + base_cells;   // >= the finest cells' chunk count
+    if (pass == 0 && npyr > 0 &&
+        (base_cells > (1ull << 18) || 8ull * NMB * (pyr_cells + pyr_chunk_bound) > (2ull << 30))) {
+      std::fill(kp.begin(), kp.end(), 0u);
+      continue;
+    }
+    cstart.push_back((uint32_t)base_cells);
+    ptab.insert(ptab.end(), cstart.begin(), cstart.end());
+    ptab.insert(ptab.end(), bq.begin(), bq.end());
+    list_off.assign(kp_max, 0);
+    list_n.assign(kp_max, 0);
+    for (int d = 0; d < kp_max; ++d) {
+      list_off[d] = (uint32_t)ptab.size();
+      for (int k = 0; k < K; ++k)
+        if ((int)kp[k] > d) ptab.push_back((uint32_t)k);
+      list_n[d] = (uint32_t)ptab.size() - list_off[d];
+    }
+    break;
+  }
+  if (npyr == 0) ptab.clear();
+  const uint32_t* pyr_dev = nullptr;
+  if (npyr > 0) {
+    W.pyr_tab.reserve(4ull * ptab.size());
+    pyr_dev = W.pyr_tab.as<uint32_t>();
+    W.pyr.reserve(8ull * NMB * pyr_cells);
+    W.pyr_begin.reserve(4ull * base_cells);
+    W.pyr_count.reserve(4ull * base_cells);
+    W.pyr_geo.reserve(48ull * base_cells);
+    W.pyr_nchk.reserve(4ull * base_cells);
+    W.pyr_dst.reserve(4ull * base_cells);
+    W.pyr_off.reserve(4ull * (base_cells + 1));
+    W.pyr_part.reserve(8ull * NMB * pyr_chunk_bound);
+  }
+
   // small per-fit tables go through pinned staging: parameters, pointers,
-  // then the level-0 chunk offsets
+  // the pyramid table, then the level-0 chunk offsets
   const size_t prm_b = sizeof(ProblemParams) * K, ptr_b = sizeof(PtrSet) * K, off_b = 4ull * (K + 1);
-  char* stg = W.staging(prm_b + ptr_b + off_b);
+  const size_t tab_b = 4ull * ptab.size();
+  char* stg = W.staging(prm_b + ptr_b + tab_b + off_b);
   std::memcpy(stg, prm.data(), prm_b);
   std::memcpy(stg + prm_b, ptrs.data(), ptr_b);
   HIPCHK(hipMemcpyAsync(W.params.p, stg, prm_b, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(W.ptrs.p, stg + prm_b, ptr_b, hipMemcpyHostToDevice, s));
+  if (tab_b) {
+    std::memcpy(stg + prm_b + ptr_b, ptab.data(), tab_b);
+    HIPCHK(hipMemcpyAsync(W.pyr_tab.p, stg + prm_b + ptr_b, tab_b, hipMemcpyHostToDevice, s));
+  }
   HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
   const ProblemParams* d_prm = W.params.as<ProblemParams>();
 
@@ -491,6 +575,50 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     HIPCHK(launch_widen(dtype, W.pf.p, N, F->resid.as<double>(), s));
   }
 
+  if (npyr > 0) {
+    // finest cells of every pyramid: ranges, frames, chunks; their power
+    // moments M; then each pyramid's coarser levels from the finer ones
+    const uint32_t nbc = (uint32_t)base_cells;
+    const uint32_t* cst = pyr_dev + (size_t)PYR_TAB_WORDS * K;
+    PyrTab pt{pyr_dev, cst, cst + npyr + 1, (uint32_t)npyr};
+    {
+      ProfScope ps(KN_PYR, nbc, s);
+      HIPCHK(hipMemsetAsync(W.pyr_begin.p, 0, 4ull * nbc, s));
+      HIPCHK(hipMemsetAsync(W.pyr_count.p, 0, 4ull * nbc, s));
+      HIPCHK(launch_pyr_cells(F->skey.as<uint32_t>(), N, F->D, K, d_prm, pt, nbc, W.pyr_begin.as<uint32_t>(),
+                              W.pyr_count.as<uint32_t>(), W.pyr_geo.as<double>(), W.pyr_nchk.as<uint32_t>(),
+                              W.pyr_dst.as<uint32_t>(), s));
+      HIPCHK(launch_pyr_scan(W.pyr_nchk.as<uint32_t>(), nbc, W.pyr_off.as<uint32_t>(), s));
+    }
+    {
+      // the finest cells as a level of nodes (range, frame, chunks)
+      ProfScope ps(KN_BASEM, N, s);
+      LevelArgs c{};
+      c.nt.begin = W.pyr_begin.as<uint32_t>();
+      c.nt.count = W.pyr_count.as<uint32_t>();
+      c.nt.geo = W.pyr_geo.as<double>();
+      c.node0 = 0;
+      c.nnodes = nbc;
+      c.chunk_off = W.pyr_off.as<uint32_t>();
+      c.nchunks = (uint32_t)pyr_chunk_bound;
+      c.px = W.px.p;
+      c.py = W.py.p;
+      c.pz = W.pz.p;
+      c.r = F->resid.as<double>();
+      c.skey = F->skey.as<uint32_t>();
+      c.D = F->D;
+      c.tol = tols[0];
+      HIPCHK(launch_moments(F->p, 3, dtype, c, W.pyr_part.as<double>(), s));
+    }
+    {
+      ProfScope ps(KN_PYR, (double)pyr_cells, s);
+      HIPCHK(launch_pyr_base(W.pyr_off.as<uint32_t>(), nbc, W.pyr_part.as<double>(), NMB, W.pyr_dst.as<uint32_t>(),
+                             W.pyr.as<double>(), s));
+      for (int d = kp_max - 1; d >= 0; --d)
+        HIPCHK(launch_pyr_up(F->p, W.pyr.as<double>(), pyr_dev, pyr_dev + list_off[d], list_n[d], d, s));
+    }
+  }
+
   // node capacity: at depth d at most min(K 8^d, N / L) nodes
   uint64_t cap = 0;
   for (int d = 0; d <= F->D; ++d) {
@@ -508,8 +636,8 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   std::vector<uint32_t> off0(K + 1, 0);
   for (int k = 0; k < K; ++k) off0[k + 1] = off0[k] + (uint32_t)((in[k].n + CHUNK - 1) / CHUNK);
   W.chunk_a.reserve(4ull * (K + 1));
-  std::memcpy(stg + prm_b + ptr_b, off0.data(), off_b);
-  HIPCHK(hipMemcpyAsync(W.chunk_a.p, stg + prm_b + ptr_b, off_b, hipMemcpyHostToDevice, s));
+  std::memcpy(stg + prm_b + ptr_b + tab_b, off0.data(), off_b);
+  HIPCHK(hipMemcpyAsync(W.chunk_a.p, stg + prm_b + ptr_b + tab_b, off_b, hipMemcpyHostToDevice, s));
 
   uint32_t nnodes = (uint32_t)K, nchunks = off0[K], node0 = 0;
   uint32_t level_points = N;
@@ -517,14 +645,20 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   F->level_count.clear();
   DevBuf* cur_off = &W.chunk_a;
   DevBuf* next_off = &W.chunk_b;
-  const bool use_moments = F->gram == FMT_GRAM_MOMENTS;
   const size_t gpd = use_moments ? moment_partial_doubles(F->p) : gram_partial_doubles(F->p);
   const size_t fd = factor_doubles(F->p);
   const size_t rbd = moment_refine_doubles(F->p);
   for (int d = 0; d <= F->D && nnodes > 0; ++d) {
     F->level_start.push_back(node0);
     F->level_count.push_back(nnodes);
-    W.partial.reserve(8ull * gpd * nchunks);
+    // nodes of this level whose M the pyramid holds (mode 2) and the others (mode 0)
+    bool lvl_pyr = false, lvl_pts = !use_moments;
+    for (int k = 0; k < K; ++k) {
+      if (pyramid_covers(kp[k], d)) lvl_pyr = true;
+      else lvl_pts = true;
+    }
+    if (lvl_pts) W.partial.reserve(8ull * gpd * nchunks);
+    if (lvl_pyr) W.part_m2.reserve(8ull * rbd * nchunks);
     if (F->refine > 0) {
       W.fac.reserve(8ull * fd * nnodes);
       W.part_b.reserve(8ull * rbd * nchunks);
@@ -552,21 +686,29 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     // the mixed path's float32 Gram always needs the sweeps; the float64
     // path applies them where the conditioning estimate asks for them
     a.refine = F->refine == 0 ? 0 : (F->path == FMT_PATH_MIXED ? 2 : 1);
+    a.pyr_tab = npyr > 0 ? pyr_dev : nullptr;
 
     const bool multi = nchunks > nnodes;   // some node spans several chunks
-    {
+    if (lvl_pyr) {
+      ProfScope ps(KN_BMOM, level_points, s);
+      HIPCHK(launch_moments(F->p, 2, dtype, a, W.part_m2.as<double>(), s));
+    }
+    if (lvl_pts) {
       ProfScope ps(KN_GRAM, level_points, s);
       if (use_moments) HIPCHK(launch_moments(F->p, 0, dtype, a, W.partial.as<double>(), s));
       else HIPCHK(launch_gram(F->p, F->path, dtype, a, W.partial.as<double>(), s));
     }
     if (multi) {
-      ProfScope ps(KN_REDUCE, (double)nchunks * (double)gpd, s);
-      HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), (uint32_t)gpd, s));
+      ProfScope ps(KN_REDUCE, (double)nchunks * (double)((lvl_pts ? gpd : 0) + (lvl_pyr ? rbd : 0)), s);
+      if (lvl_pts) HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), (uint32_t)gpd, s));
+      if (lvl_pyr) HIPCHK(launch_chunk_reduce(a, W.part_m2.as<double>(), (uint32_t)rbd, s));
     }
     {
       ProfScope ps(KN_SOLVE, nnodes, s);
       double* fac = F->refine > 0 ? W.fac.as<double>() : nullptr;
-      if (use_moments) HIPCHK(launch_solve_moments(F->p, a, W.partial.as<double>(), fac, s));
+      if (use_moments)
+        HIPCHK(launch_solve_moments(F->p, a, W.partial.as<double>(), W.part_m2.as<double>(), W.pyr.as<double>(),
+                                    fac, s));
       else HIPCHK(launch_solve(F->p, a, W.partial.as<double>(), fac, s));
     }
     for (int it = 0; it < F->refine; ++it) {

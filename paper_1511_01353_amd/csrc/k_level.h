@@ -23,7 +23,29 @@ struct LevelArgs {
   int D;                     // maximum depth
   double tol;                // split tolerance
   int refine;                // 0: no refinement; 1: nodes whose conditioning needs it; 2: every node
+  // moment pyramid table (PyrTab::tab: PYR_TAB_WORDS per problem), null
+  // when no problem has one.  Nodes at levels d <= kp take M from the
+  // pyramid (pyramid_covers)
+  const uint32_t* pyr_tab;
 };
+
+// Moment pyramid tables (k_pyramid.hip).  The per-problem words: first
+// pyramid entry, depth kp (0: none), first flat finest cell, unused.
+constexpr int PYR_TAB_WORDS = 4;
+struct PyrTab {
+  const uint32_t* tab;      // PYR_TAB_WORDS per problem
+  const uint32_t* cstart;   // nbase + 1: first flat finest cell of each pyramid
+  const uint32_t* bq;       // nbase: problem of each pyramid
+  uint32_t nbase;           // problems with a pyramid
+};
+
+// Entries of levels 0 .. d-1 of one pyramid: (8^d - 1) / 7.
+__host__ __device__ __forceinline__ uint32_t level_first(int d) { return ((1u << (3 * d)) - 1u) / 7u; }
+
+// Whether level `level` of a problem with pyramid depth kp reads M from it.
+__host__ __device__ __forceinline__ bool pyramid_covers(uint32_t kp, int level) {
+  return kp > 0 && (uint32_t)level <= kp;
+}
 
 struct EvalTree {
   NodeTable nt;
@@ -55,13 +77,38 @@ hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, 
 hipError_t launch_node_geo(const NodeTable& nt, const ProblemParams* prm, uint32_t n, hipStream_t s);
 hipError_t launch_roots(const NodeTable& nt, const ProblemParams* prm, int nprob, hipStream_t s);
 hipError_t launch_gram(int p, int path, int dtype, const LevelArgs& a, double* partial, hipStream_t s);
-// Power moments of every chunk (mode 0: M, B, sum r^2; mode 1: B of r - Lambda F).
-size_t moment_partial_doubles(int p);
-size_t moment_refine_doubles(int p);
+// Power moments of every chunk (mode 0: M, B, sum r^2; mode 1: B of
+// r - Lambda F; mode 2: B; mode 3: M).  The grid is a.nchunks workgroups,
+// which may exceed chunk_off[nnodes] (the extra ones exit).  With
+// a.pyr_tab, mode 2 skips the nodes the pyramid does not cover and mode 0
+// those it covers.
+size_t moment_partial_doubles(int p);   // mode 0
+size_t moment_refine_doubles(int p);    // modes 1 and 2
+size_t moment_base_doubles(int p);      // mode 3
 hipError_t launch_moments(int p, int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s);
 hipError_t launch_solve(int p, const LevelArgs& a, const double* partial, double* fac, hipStream_t s);
-// K6 assembled from power moments (the k_moments mode-0 layout).
-hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part, double* fac, hipStream_t s);
+// K6 assembled from power moments: M and B from the mode-0 partials part_m,
+// or, for nodes the pyramid covers (a.pyr_tab), M from the pyramid and B from
+// the mode-2 partials part_b.
+hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part_m, const double* part_b,
+                                const double* pyr, double* fac, hipStream_t s);
+// Moment pyramid (k_pyramid.hip): moment_base_doubles(p) doubles per entry.
+// The finest cells of all pyramids (flat numbering): point range, frame (6
+// doubles), chunk count and pyramid entry.  begin and count must hold zeros
+// on entry (empty cells are never written by the boundary pass).
+hipError_t launch_pyr_cells(const uint32_t* skey, uint32_t n, int D, int nprob, const ProblemParams* prm,
+                            const PyrTab& pt, uint32_t ncell, uint32_t* begin, uint32_t* count, double* geo,
+                            uint32_t* nchk, uint32_t* dst, hipStream_t s);
+// off[0..ncell] = exclusive scan of nchk (one workgroup).
+hipError_t launch_pyr_scan(const uint32_t* nchk, uint32_t ncell, uint32_t* off, hipStream_t s);
+// Sum each flat cell's chunk partials (width doubles each) into pyramid
+// entry dst[cell] (zeros if it has none).
+hipError_t launch_pyr_base(const uint32_t* off, uint32_t ncell, const double* part, uint32_t width,
+                           const uint32_t* dst, double* pyr, hipStream_t s);
+// Level d of the nlist pyramids list[0..nlist) (problems with kp > d) from
+// level d+1.
+hipError_t launch_pyr_up(int p, double* pyr, const uint32_t* tab, const uint32_t* list, uint32_t nlist, int d,
+                         hipStream_t s);
 hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s);
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s);
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
@@ -86,14 +133,48 @@ hipError_t launch_eval(int p, int dtype, const EvalTree& t, const double* cc, co
 
 // Device helpers shared by the level kernels ---------------------------------
 
-// Node k of a level owning chunk g: chunk_off[k] <= g < chunk_off[k+1].
+// Node k of a level owning chunk g: the last k with chunk_off[k] <= g, so
+// chunk_off[k] <= g < chunk_off[k+1] (nodes without chunks are skipped).
+// The whole wave searches together (g must be wave-uniform and every lane
+// active): each round its 64 lanes probe evenly spaced offsets of the
+// remaining range and a ballot narrows the range 64-fold, so 4096 nodes take
+// two rounds of loads instead of twelve.
 __device__ __forceinline__ uint32_t chunk_node(const uint32_t* chunk_off, uint32_t nnodes, uint32_t g) {
-  uint32_t lo = 0, hi = nnodes - 1;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi + 1) >> 1;
-    if (chunk_off[mid] <= g) lo = mid; else hi = mid - 1;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t lo = 0, hi = nnodes;   // the answer lies in [lo, hi); chunk_off[lo] <= g
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t idx = lo + lane * step;
+    // probes at or below g form a prefix of the lanes (offsets ascend)
+    const uint32_t c = (uint32_t)__popcll(__ballot(idx < hi && chunk_off[idx] <= g));
+    lo += (c - 1) * step;
+    hi = min(hi, lo + step);
   }
   return lo;
+}
+
+// Cell coordinates (i, j, k) of a Morton prefix with `level` triples.
+__device__ __forceinline__ void decode_cell(uint32_t prefix, int level, uint32_t& ci, uint32_t& cj, uint32_t& ck) {
+  ci = cj = ck = 0;
+  for (int b = level - 1; b >= 0; --b) {
+    const uint32_t t = (prefix >> (3 * b)) & 7u;
+    ci = (ci << 1) | ((t >> 2) & 1u);
+    cj = (cj << 1) | ((t >> 1) & 1u);
+    ck = (ck << 1) | (t & 1u);
+  }
+}
+
+// Centre and dilation of a node: h = (hi - lo) / 2^level, c = lo + (i + 1/2) h,
+// u = (x - c) * (2 / h).  Separate roundings, no fused multiply-add.
+__device__ __forceinline__ void node_geo(const ProblemParams& P, int level, uint32_t prefix, double* geo) {
+  uint32_t c[3];
+  decode_cell(prefix, level, c[0], c[1], c[2]);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const double h = ldexp(__dsub_rn(P.hi[ax], P.lo[ax]), -level);
+    geo[ax] = __dadd_rn(P.lo[ax], __dmul_rn((double)c[ax] + 0.5, h));
+    geo[3 + ax] = __ddiv_rn(2.0, h);
+  }
 }
 
 template <typename T>

@@ -65,13 +65,15 @@ __device__ __forceinline__ double pivot_recip(double d) {
 // zeros let the triangular solves run without per-step masks.  The 16 words
 // after the blocked storage, A[WORDS .. WORDS + 15], are a zero row (the
 // caller zeroes them).  Per block column J:
-//   (a) wave 0 factors the diagonal block with lane r holding row r in
-//       registers; pivots and column entries reach the other lanes through
-//       v_readlane (scalar registers).  Entries above the diagonal of a lane's
-//       row collect values that are never read, so the updates need no mask;
-//   (b) one thread per row below solves u L_JJ^T = a in axpy order and keeps
-//       L = u D^-1;
-//   (c) the trailing blocks take A_IK -= (L_IJ D_J) L_KJ^T on float64 MFMA.
+//   (a) the diagonal block and the panel below it in one right-looking pass:
+//       each wave that holds panel rows (up to 48, in lanes 16..63) also
+//       holds the block's 16 rows in lanes 0..15 and factors the block
+//       alongside (redundantly; wave 0 stores it).  At step k the pivot and the column entries A(c, k),
+//       c > k, reach all lanes through v_readlane (scalar registers); each
+//       lane scales its entry k by 1/d_k (its L(row, k)) and updates its
+//       entries c > k.  Entries above the diagonal of a block row collect
+//       values that are never read, so the updates need no mask;
+//   (b) the trailing blocks take A_IK -= (L_IJ D_J) L_KJ^T on float64 MFMA.
 // Pivots at or below PIVOT_EPS are deflated: their inverse is 0, so their
 // column of L is 0 and the solve gives that unknown 0.
 // ---------------------------------------------------------------------------
@@ -79,59 +81,54 @@ template <int L>
 __device__ __forceinline__ void ldl_blocked(double* A, double* dv, double* iv) {
   using S = BlockShape<L>;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  static_assert(S::LP - 16 <= 4 * 48, "the panel rows exceed the lanes of four waves");
   for (int J = 0; J < S::T; ++J) {
-    // (a) diagonal block
-    if (w == 0) {
-      double* blk = A + bidx(J, J);
+    // (a) diagonal block (lanes 0..15 of every wave) and panel rows
+    // 16 (J + 1) + 48 w + lane - 16 (lanes 16..63 of wave w)
+    {
       const int r = lane;
+      const int i0 = lane < 16 ? 16 * J + lane : 16 * (J + 1) + 48 * w + (lane - 16);
+      const bool live = i0 < S::LP;
+      const int i = live ? i0 : 16 * J;   // lanes past the last row point at a valid row, unused
+      double* row = A + bidx(i >> 4, J) + (i & 15) * 16;   // row i of block column J
+      const int sw = (i & 15) >> 1;
+      // waves past wave 0 without panel rows have nothing to do
+      const bool busy = w == 0 || 16 * (J + 1) + 48 * w < S::LP;
       double a[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? blk[bel(r & 15, c)] : 0.0;
+      for (int c = 0; c < 16; ++c) a[c] = (busy && live && (r >= 16 || c <= r)) ? row[c ^ sw] : 0.0;
+      __syncthreads();   // every wave has read the diagonal block before wave 0 overwrites it
+      if (busy) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const double d = lane_value(a[k], k);
-        const double inv = d > PIVOT_EPS ? pivot_recip(d) : 0.0;
-        const double lk = a[k] * inv;                  // L[r][k] for r > k
+        for (int k = 0; k < 16; ++k) {
+          const double d = lane_value(a[k], k);
+          const double inv = d > PIVOT_EPS ? pivot_recip(d) : 0.0;
+          const double lk = a[k] * inv;                  // L[row][k] for rows below k
 #pragma unroll
-        for (int c = k + 1; c < 16; ++c) a[c] = fma(-lk, lane_value(a[k], c), a[c]);
-        a[k] = r > k ? lk : a[k];                      // lane k keeps its pivot
-      }
-      if (r < 16) {
-        // lane r's diagonal entry is its pivot; the inverse is recomputed
-        // from it exactly as in the step
-        double dr = a[0];
+          for (int c = k + 1; c < 16; ++c) a[c] = fma(-lk, lane_value(a[k], c), a[c]);
+          a[k] = r > k ? lk : a[k];                      // lane k keeps its pivot
+        }
+        if (r < 16) {
+          if (w == 0) {
+            // lane r's diagonal entry is its pivot; the inverse is recomputed
+            // from it exactly as in the step
+            double dr = a[0];
 #pragma unroll
-        for (int c = 1; c < 16; ++c) dr = c == r ? a[c] : dr;
-        dv[16 * J + r] = dr;
-        iv[16 * J + r] = dr > PIVOT_EPS ? pivot_recip(dr) : 0.0;
+            for (int c = 1; c < 16; ++c) dr = c == r ? a[c] : dr;
+            dv[16 * J + r] = dr;
+            iv[16 * J + r] = dr > PIVOT_EPS ? pivot_recip(dr) : 0.0;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) blk[bel(r, c)] = c < r ? a[c] : 0.0;
+            for (int c = 0; c < 16; ++c) row[c ^ sw] = c < r ? a[c] : 0.0;
+          }
+        } else if (live) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c) row[c ^ sw] = a[c];
+        }
       }
     }
     __syncthreads();
     if (J + 1 == S::T) break;
-    // (b) panel: rows i of blocks I > J
-    {
-      const int i = 16 * (J + 1) + tid;
-      if (i < S::LP) {
-        const double* ljj = A + bidx(J, J);
-        double* row = A + bidx(i >> 4, J) + (i & 15) * 16;
-        const int sw = (i & 15) >> 1;
-        double x[16];
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) x[cc] = row[cc ^ sw];
-        // x <- x L_JJ^-T (unit lower L_JJ), one column at a time
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-#pragma unroll
-          for (int cc = m + 1; cc < 16; ++cc) x[cc] = fma(-x[m], ljj[bel(cc, m)], x[cc]);
-        }
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) row[cc ^ sw] = x[cc] * iv[16 * J + cc];
-      }
-    }
-    __syncthreads();
-    // (c) trailing update A_IK -= (L_IJ D_J) L_KJ^T for J < K <= I, on MFMA
+    // (b) trailing update A_IK -= (L_IJ D_J) L_KJ^T for J < K <= I, on MFMA
     {
       const int nb = S::T - J - 1;
       const int npair = nb * (nb + 1) / 2;
@@ -264,8 +261,10 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
                                                    const double* sc, double (*xv)[L], double (*yv)[L],
                                                    const LevelArgs& a, uint32_t k, uint32_t node, double* fac) {
   using S = BlockShape<L>;
+  __shared__ int need_factor;   // the refinement sweeps will apply to this node
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const bool estimate = a.refine == 1;
+  if (tid == 0) need_factor = a.refine == 2;
   if (estimate)
     for (int e = tid; e < 2 * L; e += 256) xv[e / L][e % L] = probe_entry(e % L, e / L, L);
   ldl_blocked<L>(A, dv, iv);
@@ -286,14 +285,20 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
     for (int i = lane; i < L; i += 64) ss += yv[w - 1][i] * yv[w - 1][i];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off);
-    if (lane == 0 && (double)L * sqrt(ss) > REFINE_KAPPA) atomicOr(a.nt.flags + node, FLAG_REFINE);
+    if (lane == 0 && (double)L * sqrt(ss) > REFINE_KAPPA) {
+      atomicOr(a.nt.flags + node, FLAG_REFINE);
+      need_factor = 1;
+    }
   }
   if (a.refine == 2) {
     if (tid == 0) atomicOr(a.nt.flags + node, FLAG_REFINE);
   } else if (estimate && deflated) {
     atomicOr(a.nt.flags + node, FLAG_REFINE);
+    need_factor = 1;
   }
-  if (fac) {
+  __syncthreads();
+  // the factor is kept only for the nodes the refinement sweeps will visit
+  if (fac && need_factor) {
     double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
     for (int e = tid; e < S::WORDS; e += 256) fo[e] = A[e];
     for (int i = tid; i < L; i += 256) {
@@ -370,10 +375,13 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
 // b_i = B[alpha_i] / alpha_i!.  Equilibration is folded into the assembly:
 // with s_i = 1 / sqrt(G_ii) and w_i = s_i / alpha_i!, the scaled matrix is
 // A_ik = M[alpha_i + alpha_k] w_i w_k and the scaled right-hand side
-// B[alpha_i] w_i.
+// B[alpha_i] w_i.  M and B come from the node's mode-0 partial, or, where
+// the moment pyramid covers the node, M from its pyramid cell and B from the
+// node's B-only partial.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __restrict__ part,
+__global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __restrict__ part_m,
+                                                 const double* __restrict__ part_b, const double* __restrict__ pyr,
                                                  double* __restrict__ fac) {
   constexpr int L = basis_size(P);
   constexpr int NM = basis_size(2 * P);
@@ -391,7 +399,14 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
-  for (int e = tid; e < NOUT; e += 256) mom[e] = part[(size_t)c0 * NOUT + e];
+  const uint32_t* pt = a.pyr_tab ? a.pyr_tab + PYR_TAB_WORDS * a.nt.problem[node] : nullptr;
+  if (pt && pyramid_covers(pt[1], a.level)) {
+    const size_t cell = (size_t)pt[0] + level_first(a.level) + a.nt.prefix[node];
+    for (int e = tid; e < NM; e += 256) mom[e] = pyr[cell * NM + e];
+    for (int i = tid; i < L; i += 256) mom[NM + i] = part_b[(size_t)c0 * L + i];
+  } else {
+    for (int e = tid; e < NM + L; e += 256) mom[e] = part_m[(size_t)c0 * NOUT + e];
+  }
   for (int i = tid; i < L; i += 256) {
     ex[i][0] = B.lx[i];
     ex[i][1] = B.ly[i];
@@ -407,9 +422,33 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
     b[i] = mom[NM + i] * s * f;
   }
   __syncthreads();
-  assemble_blocked<L>(A, [&](int i, int q) {
-    return mom[graded(ex[i][0] + ex[q][0], ex[i][1] + ex[q][1], ex[i][2] + ex[q][2])] * wv[i] * wv[q];
-  });
+  {
+    // storage-order fill (as assemble_blocked) with this thread's row and
+    // column exponents (packed a | b << 8 | c << 16) and weights in registers
+    const int r = tid >> 4, c = (tid & 15) ^ (r >> 1);
+    uint32_t er[S::T], ec[S::T];
+    double wr[S::T], wc[S::T];
+#pragma unroll
+    for (int I = 0; I < S::T; ++I) {
+      const int i = 16 * I + r, q = 16 * I + c;
+      er[I] = i < L ? (uint32_t)ex[i][0] | ((uint32_t)ex[i][1] << 8) | ((uint32_t)ex[i][2] << 16) : 0u;
+      ec[I] = q < L ? (uint32_t)ex[q][0] | ((uint32_t)ex[q][1] << 8) | ((uint32_t)ex[q][2] << 16) : 0u;
+      wr[I] = i < L ? wv[i] : 0.0;
+      wc[I] = q < L ? wv[q] : 0.0;
+    }
+#pragma unroll
+    for (int I = 0; I < S::T; ++I) {
+      const int i = 16 * I + r;
+#pragma unroll
+      for (int J = 0; J <= I; ++J) {
+        const int q = 16 * J + c;
+        const uint32_t e = er[I] + ec[J];
+        const double m = mom[graded((int)(e & 255u), (int)((e >> 8) & 255u), (int)(e >> 16))];
+        A[bidx(I, J) + tid] = (i < L && q < L) ? m * wr[I] * wc[J] : (i == q ? 1.0 : 0.0);
+      }
+    }
+    if (tid < 16) A[S::WORDS + tid] = 0.0;
+  }
   __syncthreads();
   factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a, k, node, fac);
 }
@@ -588,30 +627,6 @@ __global__ void __launch_bounds__(1024) k_chunk_reduce(const uint32_t* __restric
   }
 }
 
-// Cell coordinates (i, j, k) of a Morton prefix with `level` triples.
-__device__ __forceinline__ void decode_cell(uint32_t prefix, int level, uint32_t& ci, uint32_t& cj, uint32_t& ck) {
-  ci = cj = ck = 0;
-  for (int b = level - 1; b >= 0; --b) {
-    const uint32_t t = (prefix >> (3 * b)) & 7u;
-    ci = (ci << 1) | ((t >> 2) & 1u);
-    cj = (cj << 1) | ((t >> 1) & 1u);
-    ck = (ck << 1) | (t & 1u);
-  }
-}
-
-// Centre and dilation of a node: h = (hi - lo) / 2^level, c = lo + (i + 1/2) h,
-// u = (x - c) * (2 / h).  Separate roundings, no fused multiply-add.
-__device__ __forceinline__ void node_geo(const ProblemParams& P, int level, uint32_t prefix, double* geo) {
-  uint32_t c[3];
-  decode_cell(prefix, level, c[0], c[1], c[2]);
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    const double h = ldexp(__dsub_rn(P.hi[ax], P.lo[ax]), -level);
-    geo[ax] = __dadd_rn(P.lo[ax], __dmul_rn((double)c[ax] + 0.5, h));
-    geo[3 + ax] = __ddiv_rn(2.0, h);
-  }
-}
-
 __global__ void k_roots(NodeTable nt, const ProblemParams* __restrict__ prm, int nprob) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nprob) return;
@@ -659,33 +674,41 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     __syncthreads();
   }
   const uint32_t total = s[1023];
+  // each node's first child index (exclusive prefix of the active counts),
+  // in place of its count
   uint32_t run = s[tid] - sum;
-  uint32_t pts = 0;
   for (uint32_t i = b; i < e; ++i) {
+    const uint32_t v = nact[i];
+    nact[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  // one thread per (node, octant): the octant's child, if active
+  uint32_t pts = 0;
+  for (uint32_t pr = tid; pr < 8u * m; pr += 1024u) {
+    const uint32_t i = pr >> 3, o = pr & 7u;
     const uint32_t node = a.node0 + i;
     const uint32_t mask = a.nt.child_mask[node];
-    if (mask) a.nt.first_child[node] = next0 + run;
+    const uint32_t first = next0 + nact[i];
+    if (o == 0 && mask) a.nt.first_child[node] = first;
+    if (!((mask >> o) & 1u)) continue;
+    const uint32_t crun = nact[i] + (uint32_t)__popc(mask & ((1u << o) - 1u));
+    const uint32_t cid = next0 + crun;
     const uint32_t prob = a.nt.problem[node];
-    const uint32_t pre = a.nt.prefix[node];
-    for (int o = 0; o < 8; ++o) {
-      if (!((mask >> o) & 1u)) continue;
-      const uint32_t cid = next0 + run;
-      const uint32_t cpre = (pre << 3) | (uint32_t)o;
-      a.nt.begin[cid] = cbeg[(size_t)i * 8 + o];
-      const uint32_t cn = ccnt[(size_t)i * 8 + o];
-      a.nt.count[cid] = cn;
-      a.nt.prefix[cid] = cpre;
-      a.nt.level[cid] = (uint32_t)(a.level + 1);
-      a.nt.problem[cid] = prob;
-      a.nt.parent[cid] = node;
-      a.nt.first_child[cid] = 0;
-      a.nt.child_mask[cid] = 0;
-      a.nt.flags[cid] = 0;
-      node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
-      next_chunk_off[run] = (cn + CHUNK - 1) / CHUNK;
-      pts += cn;
-      ++run;
-    }
+    const uint32_t cpre = (a.nt.prefix[node] << 3) | o;
+    a.nt.begin[cid] = cbeg[pr];
+    const uint32_t cn = ccnt[pr];
+    a.nt.count[cid] = cn;
+    a.nt.prefix[cid] = cpre;
+    a.nt.level[cid] = (uint32_t)(a.level + 1);
+    a.nt.problem[cid] = prob;
+    a.nt.parent[cid] = node;
+    a.nt.first_child[cid] = 0;
+    a.nt.child_mask[cid] = 0;
+    a.nt.flags[cid] = 0;
+    node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
+    next_chunk_off[crun] = (cn + CHUNK - 1) / CHUNK;
+    pts += cn;
   }
   __syncthreads();
   // total points of the next level (fixed-order integer sum)
@@ -763,13 +786,15 @@ hipError_t launch_solve(int p, const LevelArgs& a, const double* partial, double
 }
 
 template <int P>
-static hipError_t solve_m_impl(const LevelArgs& a, const double* part, double* fac, hipStream_t s) {
+static hipError_t solve_m_impl(const LevelArgs& a, const double* part_m, const double* part_b, const double* pyr,
+                               double* fac, hipStream_t s) {
   if (a.nnodes == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_solve_m<P>, dim3(a.nnodes), dim3(256), 0, s, a, part, fac);
+  hipLaunchKernelGGL(k_solve_m<P>, dim3(a.nnodes), dim3(256), 0, s, a, part_m, part_b, pyr, fac);
   return hipGetLastError();
 }
-hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part, double* fac, hipStream_t s) {
-  FMT_DISPATCH_P(p, solve_m_impl, a, part, fac, s);
+hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part_m, const double* part_b,
+                                const double* pyr, double* fac, hipStream_t s) {
+  FMT_DISPATCH_P(p, solve_m_impl, a, part_m, part_b, pyr, fac, s);
 }
 
 template <int P>

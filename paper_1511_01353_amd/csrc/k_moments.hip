@@ -9,11 +9,19 @@
 // entries (3570), so accumulating the moments takes several times fewer
 // float64 operations per point than forming the Gram, and stays in float64.
 //
-// Layout of the work: a workgroup of NW waves takes one chunk; each wave owns
-// a group of moment "runs" (fixed a, b; c = 0..cmax) chosen at compile time
-// to balance the accumulator count.  A lane walks the chunk's points lane,
-// lane+64, ... keeping its accumulators in registers; the 64 lanes are then
-// summed through LDS in rounds of 16 accumulators, in a fixed order.
+// Layout of the work: a workgroup of NW * SPLIT waves takes one chunk,
+// whose points (coordinates and weight) it first stages in LDS with all of
+// its loads in flight at once.  Each wave owns a group of moment "runs"
+// (fixed a, b; c = 0..cmax) chosen at compile time to balance the
+// accumulator count, and one of SPLIT slices of the chunk's points.  A lane
+// walks its slice's points keeping its accumulators in registers; the 64
+// lanes are then summed through LDS in rounds of RROWS accumulators, and the
+// slices in a fixed order.
+//
+// Modes: 0 = M, B and sum r^2 of a level's nodes; 1 = B of the refinement
+// residual r' = r - Lambda F; 2 = B only (the power moments M of the node come
+// from the moment pyramid); 3 = M only, over the cells of the pyramid's
+// finest level.
 #include <utility>
 
 #include "k_level.h"
@@ -26,23 +34,34 @@ __host__ __device__ constexpr int gidx(int a, int b, int c) {
   return k * (k + 1) * (k + 2) / 6 + (k - a) * (k - a + 1) / 2 + (k - a - b);
 }
 
-// MODE 0 (fit): moments M (|gamma| <= 2p), r-weighted moments B (|alpha| <= p)
-// and sum r^2.  MODE 1 (refinement): B only, weighted by r' = r - Lambda F.
 template <int P, int MODE>
 struct MomentPlan {
+  static constexpr bool HAS_M = MODE == 0 || MODE == 3;
+  static constexpr bool HAS_B = MODE != 3;
+  static constexpr bool HAS_RR = MODE == 0;
   static constexpr int P2 = 2 * P;
-  static constexpr int NM = MODE == 0 ? basis_size(P2) : 0;
-  static constexpr int NB = basis_size(P);
-  static constexpr int NOUT = NM + NB + (MODE == 0 ? 1 : 0);
-  static constexpr int NI_M = MODE == 0 ? (P2 + 1) * (P2 + 2) / 2 : 0;
-  static constexpr int NI_B = (P + 1) * (P + 2) / 2;
-  static constexpr int NI = NI_M + NI_B + (MODE == 0 ? 1 : 0);
+  static constexpr int NM = HAS_M ? basis_size(P2) : 0;
+  static constexpr int NB = HAS_B ? basis_size(P) : 0;
+  static constexpr int NOUT = NM + NB + (HAS_RR ? 1 : 0);
+  static constexpr int NI_M = HAS_M ? (P2 + 1) * (P2 + 2) / 2 : 0;
+  static constexpr int NI_B = HAS_B ? (P + 1) * (P + 2) / 2 : 0;
+  static constexpr int NI = NI_M + NI_B + (HAS_RR ? 1 : 0);
   static constexpr int CAP = 64;   // accumulators per lane budget
-  static constexpr int NW_MAX = MODE == 0 ? 8 : 2;
+  // waves per workgroup: mode 3 runs over many small cells, where smaller
+  // workgroups let more of them share a compute unit
+  static constexpr int WAVES = MODE == 3 ? 4 : 8;
+  static constexpr int NW_MAX = HAS_M ? WAVES : 2;
   static constexpr int NG_MIN = (NOUT + CAP - 1) / CAP;
   static constexpr int NW = NG_MIN < NW_MAX ? (NG_MIN < 1 ? 1 : NG_MIN) : NW_MAX;
   static constexpr int NPASS = (NG_MIN + NW - 1) / NW;
   static constexpr int NG = NW * NPASS;
+  // with few groups, point slices keep the workgroup's waves busy
+  static constexpr int SPLIT = NW >= WAVES ? 1 : WAVES / NW;
+  static constexpr int NTHR = NW * SPLIT * 64;
+  // accumulators per reduction round: 16 when the reduction buffer can
+  // share the LDS of the staged points (one pass over the groups), else 8
+  static constexpr int RROWS = HAS_M && NPASS == 1 ? 16 : 8;
+  static constexpr int PMAX = HAS_M ? P2 : P;    // highest power used
 
   // items: kind 0 = M run, 1 = B run, 2 = sum r^2
   int kind[NI], ia[NI], ib[NI], len[NI], slot[NI], out0[NI];
@@ -52,17 +71,19 @@ struct MomentPlan {
 
   constexpr MomentPlan() : kind(), ia(), ib(), len(), slot(), out0(), gcount(), gitem(), load(), outmap() {
     int n = 0;
-    if (MODE == 0) {
+    if (HAS_M) {
       for (int a = 0; a <= P2; ++a)
         for (int b = 0; a + b <= P2; ++b) {
           kind[n] = 0; ia[n] = a; ib[n] = b; len[n] = P2 - a - b + 1; out0[n] = 0; ++n;
         }
     }
-    for (int a = 0; a <= P; ++a)
-      for (int b = 0; a + b <= P; ++b) {
-        kind[n] = 1; ia[n] = a; ib[n] = b; len[n] = P - a - b + 1; out0[n] = NM; ++n;
-      }
-    if (MODE == 0) { kind[n] = 2; ia[n] = 0; ib[n] = 0; len[n] = 1; out0[n] = NM + NB; ++n; }
+    if (HAS_B) {
+      for (int a = 0; a <= P; ++a)
+        for (int b = 0; a + b <= P; ++b) {
+          kind[n] = 1; ia[n] = a; ib[n] = b; len[n] = P - a - b + 1; out0[n] = NM; ++n;
+        }
+    }
+    if (HAS_RR) { kind[n] = 2; ia[n] = 0; ib[n] = 0; len[n] = 1; out0[n] = NM + NB; ++n; }
     // longest runs first, each to the least loaded group
     int order[NI] = {};
     for (int i = 0; i < NI; ++i) order[i] = i;
@@ -102,6 +123,7 @@ struct Plan {
 
 size_t moment_partial_doubles(int p) { return basis_size(2 * p) + basis_size(p) + 1; }
 size_t moment_refine_doubles(int p) { return basis_size(p); }
+size_t moment_base_doubles(int p) { return basis_size(2 * p); }
 
 // Accumulate item I (compile-time) for one point: a run acc[s + c] += h w^c.
 template <int S, int NA, int P2, size_t... C>
@@ -131,64 +153,78 @@ __device__ __forceinline__ void accumulate(std::index_sequence<T...>, const doub
   (accumulate_item<P, MODE, Plan<P, MODE>::v.gitem[G][T], NA>(pu, pv, pw, wt, acc), ...);
 }
 
-// red: 16 x 65 doubles of LDS owned by this wave.
-template <int P, int MODE, int G, typename TIN>
-__device__ __forceinline__ void moments_group(const LevelArgs& a, uint32_t start, uint32_t end, const double* geo,
-                                              const double* rp, double* red, double* out) {
-  constexpr const MomentPlan<P, MODE>& M = Plan<P, MODE>::v;
+// The chunk's points staged in LDS: coordinates in the input type, and the
+// weight (r, or r' in mode 1) in float64 except in mode 3.
+template <int MODE, typename TIN>
+struct Staged {
+  static constexpr bool HAS_W = MODE != 3;
+  static constexpr size_t BYTES = (size_t)CHUNK * (3 * sizeof(TIN) + (HAS_W ? sizeof(double) : 0));
+  const TIN* x;
+  const TIN* y;
+  const TIN* z;
+  const double* w;
+  __device__ Staged(char* base) {
+    TIN* p = reinterpret_cast<TIN*>(base);
+    x = p;
+    y = p + CHUNK;
+    z = p + 2 * CHUNK;
+    w = reinterpret_cast<const double*>(p + 3 * CHUNK);
+  }
+};
+
+// One wave's share of a chunk: group G of the runs over slice `slice` of the
+// n staged points.  red: RROWS x 65 doubles of LDS owned by this wave; with
+// ALIAS it overlays the staged points, so every wave first finishes its
+// points (workgroup barrier).  The lane sums go to out[] (one slice) or to
+// comb[slice][] (several slices, summed by the caller).
+template <int P, int MODE, int G, typename TIN, bool ALIAS>
+__device__ __forceinline__ void moments_group(const Staged<MODE, TIN>& st, uint32_t n, int slice, const double* geo,
+                                              double* red, double* out) {
+  using MP = MomentPlan<P, MODE>;
+  constexpr const MP& M = Plan<P, MODE>::v;
   constexpr int NA = M.load[G] > 0 ? M.load[G] : 1;
-  static_assert(NA <= MomentPlan<P, MODE>::OUTW, "a moment group exceeds the output map");
-  constexpr int P2 = 2 * P;
+  static_assert(NA <= MP::OUTW, "a moment group exceeds the output map");
+  constexpr int P2 = 2 * P, R = MP::RROWS, STEP = 64 * MP::SPLIT;
   const int lane = threadIdx.x & 63;
   const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
   double acc[NA];
 #pragma unroll
   for (int s = 0; s < NA; ++s) acc[s] = 0.0;
-  // the next point's data is loaded one iteration ahead (index clamped into
-  // the chunk), so its latency overlaps this point's arithmetic
-  double nx = 0.0, ny = 0.0, nz = 0.0, nw = 0.0;
-  if (start + lane < end) {
-    load_point<TIN>(a.px, a.py, a.pz, start + lane, nx, ny, nz);
-    nw = MODE == 1 ? rp[lane] : a.r[start + lane];
-  }
 #pragma unroll 1
-  for (uint32_t i = start + lane; i < end; i += 64) {
-    const double x = nx, y = ny, z = nz, wt = nw;
-    {
-      const uint32_t j = min(i + 64, end - 1);
-      load_point<TIN>(a.px, a.py, a.pz, j, nx, ny, nz);
-      nw = MODE == 1 ? rp[j - start] : a.r[j];
-    }
-    const double u = (x - cx) * sx, v = (y - cy) * sy, w = (z - cz) * sz;
+  for (uint32_t j = (uint32_t)(slice * 64 + lane); j < n; j += STEP) {
+    const double u = ((double)st.x[j] - cx) * sx, v = ((double)st.y[j] - cy) * sy, w = ((double)st.z[j] - cz) * sz;
+    double wt = 0.0;
+    if constexpr (Staged<MODE, TIN>::HAS_W) wt = st.w[j];
     double pu[P2 + 1], pv[P2 + 1], pw[P2 + 1];
     pu[0] = pv[0] = pw[0] = 1.0;
 #pragma unroll
-    for (int k = 1; k <= P2; ++k) {
+    for (int k = 1; k <= MP::PMAX; ++k) {
       pu[k] = pu[k - 1] * u;
       pv[k] = pv[k - 1] * v;
       pw[k] = pw[k - 1] * w;
     }
     accumulate<P, MODE, G, NA>(std::make_index_sequence<M.gcount[G]>{}, pu, pv, pw, wt, acc);
   }
-  // sum over the 64 lanes: rounds of 16 accumulators through LDS; lane l
-  // adds column block (l / 16) of row (l % 16), then the 4 partials combine
+  if constexpr (ALIAS) __syncthreads();
+  // sum over the 64 lanes: rounds of R accumulators through LDS; lane l adds
+  // column block (l / R) of row (l % R), then the 64 / R partials combine
 #pragma unroll
-  for (int s0 = 0; s0 < NA; s0 += 16) {
+  for (int s0 = 0; s0 < NA; s0 += R) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
+    for (int q = 0; q < R; ++q)
       if (s0 + q < NA) red[q * 65 + lane] = acc[s0 + q];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int row = lane & 15, cb = lane >> 4;
+    const int row = lane % R, cb = lane / R;
     double t = 0.0;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) t += red[row * 65 + cb * 16 + c];
-    t += __shfl_xor(t, 16);
-    t += __shfl_xor(t, 32);
+    for (int c = 0; c < R; ++c) t += red[row * 65 + cb * R + c];
+#pragma unroll
+    for (int off = R; off < 64; off <<= 1) t += __shfl_xor(t, off);
     if (cb == 0 && s0 + row < NA) {
       const int o = Plan<P, MODE>::v.outmap[G][s0 + row];
-      if (o >= 0) out[o] = t;
+      if (o >= 0) out[(MP::SPLIT > 1 ? slice * MP::NOUT : 0) + o] = t;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -196,75 +232,144 @@ __device__ __forceinline__ void moments_group(const LevelArgs& a, uint32_t start
   }
 }
 
-template <int P, int MODE, typename TIN, int G = 0>
-__device__ __forceinline__ void dispatch_group(int g, const LevelArgs& a, uint32_t start, uint32_t end,
-                                               const double* geo, const double* rp, double* red, double* out) {
+template <int P, int MODE, typename TIN, bool ALIAS, int G = 0>
+__device__ __forceinline__ void dispatch_group(int g, const Staged<MODE, TIN>& st, uint32_t n, int slice,
+                                               const double* geo, double* red, double* out) {
   if constexpr (G < MomentPlan<P, MODE>::NG) {
-    if (g == G) moments_group<P, MODE, G, TIN>(a, start, end, geo, rp, red, out);
-    else dispatch_group<P, MODE, TIN, G + 1>(g, a, start, end, geo, rp, red, out);
+    if (g == G) moments_group<P, MODE, G, TIN, ALIAS>(st, n, slice, geo, red, out);
+    else dispatch_group<P, MODE, TIN, ALIAS, G + 1>(g, st, n, slice, geo, red, out);
   }
 }
 
 template <int P, int MODE, typename TIN>
-__global__ void __launch_bounds__((MomentPlan<P, MODE>::NW * 64)) k_moments(LevelArgs a, double* __restrict__ part) {
+__global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelArgs a, double* __restrict__ part) {
   using MP = MomentPlan<P, MODE>;
-  constexpr int L = basis_size(P);
-  __shared__ double rp[MODE == 1 ? CHUNK : 1];   // r' = r - Lambda F of the chunk's points
-  __shared__ double red[MP::NW][16 * 65];
+  using ST = Staged<MODE, TIN>;
+  constexpr int L = basis_size(P), NT = MP::NTHR;
+  // one pass over the groups: the reduction buffers overlay the staged points
+  constexpr bool ALIAS = MP::NPASS == 1;
+  constexpr size_t RED_B = (size_t)MP::NW * MP::SPLIT * MP::RROWS * 65 * sizeof(double);
+  constexpr size_t SMEM_B = ALIAS ? (ST::BYTES > RED_B ? ST::BYTES : RED_B) : ST::BYTES + RED_B;
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_B];
+  __shared__ double comb[MP::SPLIT > 1 ? MP::SPLIT * MP::NOUT : 1];
   const uint32_t g = blockIdx.x;
+  // the grid may be an upper bound on the chunk count (pyramid cells)
+  if (g >= a.chunk_off[a.nnodes]) return;
   const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
   const uint32_t node = a.node0 + k;
   const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
   const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
-  const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
+  const uint32_t n = min(nb + nc, start + (uint32_t)CHUNK) - start;
   const double* geo = a.nt.geo + 6 * (size_t)node;
+  if constexpr (MODE == 0 || MODE == 2) {
+    // a level split between the pyramid's nodes (mode 2) and the others
+    if (a.pyr_tab && pyramid_covers(a.pyr_tab[PYR_TAB_WORDS * a.nt.problem[node] + 1], a.level) != (MODE == 2)) return;
+  }
   if constexpr (MODE == 1) {
     if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
-    // r' once per point, four points per thread at a time; the node's
-    // coefficients are wave-uniform and read with scalar loads (read-only
-    // constant address space), so they take no vector registers
+  }
+  TIN* sxw = reinterpret_cast<TIN*>(smem);
+  double* sww = reinterpret_cast<double*>(sxw + 3 * CHUNK);
+  const TIN* gx = (const TIN*)a.px + start;
+  const TIN* gy = (const TIN*)a.py + start;
+  const TIN* gz = (const TIN*)a.pz + start;
+  constexpr int NPT = 4;   // points per thread per round: all their loads are issued together
+  if constexpr (MODE == 1) {
+    // r' = r - Lambda F once per point; the node's coefficients are
+    // wave-uniform and read with scalar loads (read-only constant address
+    // space), so they take no vector registers
     typedef const double __attribute__((address_space(4))) cdouble;
     const cdouble* F = (const cdouble*)(a.nt.coef + (size_t)node * L);
     const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
-    constexpr int NT = MP::NW * 64, NPT = 4;
-    for (uint32_t i0 = start + threadIdx.x; i0 < end; i0 += NPT * NT) {
-      double u[NPT], v[NPT], w[NPT], val[NPT];
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += NPT * NT) {
+      TIN vx[NPT], vy[NPT], vz[NPT];
+      double u[NPT], v[NPT], w[NPT], val[NPT], r[NPT];
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
-        const uint32_t i = min(i0 + q * NT, end - 1);   // tail lanes repeat a point and do not store
-        double x, y, z;
-        load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
-        u[q] = (x - cx) * sx;
-        v[q] = (y - cy) * sy;
-        w[q] = (z - cz) * sz;
+        const uint32_t i = min(i0 + q * NT, n - 1);   // tail lanes repeat a point and do not store
+        vx[q] = gx[i];
+        vy[q] = gy[i];
+        vz[q] = gz[i];
+        r[q] = a.r[start + i];
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        u[q] = ((double)vx[q] - cx) * sx;
+        v[q] = ((double)vy[q] - cy) * sy;
+        w[q] = ((double)vz[q] - cz) * sz;
       }
       poly_eval_multi<P, NPT>(F, u, v, w, val);
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
         const uint32_t i = i0 + q * NT;
-        if (i < end) rp[i - start] = a.r[i] - val[q];
+        if (i < n) {
+          sxw[i] = vx[q];
+          sxw[CHUNK + i] = vy[q];
+          sxw[2 * CHUNK + i] = vz[q];
+          sww[i] = r[q] - val[q];
+        }
       }
     }
-    __syncthreads();
+  } else {
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += NPT * NT) {
+      TIN vx[NPT], vy[NPT], vz[NPT];
+      double r[NPT];
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const uint32_t i = min(i0 + q * NT, n - 1);
+        vx[q] = gx[i];
+        vy[q] = gy[i];
+        vz[q] = gz[i];
+        if constexpr (ST::HAS_W) r[q] = a.r[start + i];
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const uint32_t i = i0 + q * NT;
+        if (i < n) {
+          sxw[i] = vx[q];
+          sxw[CHUNK + i] = vy[q];
+          sxw[2 * CHUNK + i] = vz[q];
+          if constexpr (ST::HAS_W) sww[i] = r[q];
+        }
+      }
+    }
   }
+  __syncthreads();
+  const ST st(smem);
   double* out = part + (size_t)g * MP::NOUT;
   const int w = threadIdx.x >> 6;
+  const int grp = w % MP::NW, slice = w / MP::NW;
+  double* red = reinterpret_cast<double*>(smem + (ALIAS ? 0 : ST::BYTES)) + (size_t)w * MP::RROWS * 65;
+  double* dst = MP::SPLIT > 1 ? comb : out;
   for (int pass = 0; pass < MP::NPASS; ++pass)
-    dispatch_group<P, MODE, TIN>(pass * MP::NW + w, a, start, end, geo, rp, red[w], out);
+    dispatch_group<P, MODE, TIN, ALIAS>(pass * MP::NW + grp, st, n, slice, geo, red, dst);
+  if constexpr (MP::SPLIT > 1) {
+    __syncthreads();
+    for (int o = threadIdx.x; o < MP::NOUT; o += NT) {
+      double t = comb[o];
+#pragma unroll
+      for (int q = 1; q < MP::SPLIT; ++q) t += comb[q * MP::NOUT + o];
+      out[o] = t;
+    }
+  }
+}
+
+template <int P, int MODE>
+static void launch_mode(int dtype, const LevelArgs& a, double* part, hipStream_t s) {
+  dim3 grid(a.nchunks), block(MomentPlan<P, MODE>::NTHR);
+  if (dtype == FMT_F32) hipLaunchKernelGGL((k_moments<P, MODE, float>), grid, block, 0, s, a, part);
+  else hipLaunchKernelGGL((k_moments<P, MODE, double>), grid, block, 0, s, a, part);
 }
 
 template <int P>
 static hipError_t moments_impl(int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s) {
   if (a.nchunks == 0) return hipSuccess;
-  dim3 grid(a.nchunks);
-  if (mode == 0) {
-    dim3 block(MomentPlan<P, 0>::NW * 64);
-    if (dtype == FMT_F32) hipLaunchKernelGGL((k_moments<P, 0, float>), grid, block, 0, s, a, part);
-    else hipLaunchKernelGGL((k_moments<P, 0, double>), grid, block, 0, s, a, part);
-  } else {
-    dim3 block(MomentPlan<P, 1>::NW * 64);
-    if (dtype == FMT_F32) hipLaunchKernelGGL((k_moments<P, 1, float>), grid, block, 0, s, a, part);
-    else hipLaunchKernelGGL((k_moments<P, 1, double>), grid, block, 0, s, a, part);
+  switch (mode) {
+    case 0: launch_mode<P, 0>(dtype, a, part, s); break;
+    case 1: launch_mode<P, 1>(dtype, a, part, s); break;
+    case 2: launch_mode<P, 2>(dtype, a, part, s); break;
+    case 3: launch_mode<P, 3>(dtype, a, part, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

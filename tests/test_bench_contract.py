@@ -21,4 +21,6 @@ def test_algorithmic_work_counts():
     assert bench.eval_flops_per_query(84) == 2 * 84
     # p = 6: 455 power moments + 84 weighted + 1, 91 + 28 runs, 36 powers
     assert bench.moment_flops_per_point(6) == 2 * (455 + 84 + 1) + 119 + 36
+    assert bench.bmoment_flops_per_point(6) == 2 * 84 + 28 + 18
+    assert bench.base_moment_flops_per_point(6) == 2 * 455 + 91 + 36
     assert bench.solve_flops_per_node(84) == 84 ** 3 / 3 + 2 * 84 * 84

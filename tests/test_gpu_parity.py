@@ -301,6 +301,37 @@ def test_batch_equals_single_fits(fmt):
         compare_eval(ot, nodes, pr, qa, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.2)
 
 
+@pytest.mark.parametrize("n,p,depth,clustered,seed", [
+    (300000, 6, 5, False, 31),    # pyramid over levels 0..3, point moments below
+    (200000, 4, 5, True, 32),     # clustered: cells of very different sizes
+    (40000, 8, 2, False, 33),     # the pyramid covers every level
+])
+def test_moment_pyramid_matches_per_level_moments(fmt, n, p, depth, clustered, seed):
+    """Power moments carried up the pyramid against moments accumulated from
+    the points at every level: same tree, coefficients and fitted values
+    equal up to rounding, and the pyramid fit at the oracle's fitted values."""
+    pr = synthetic.small_problem(n, p, seed, tol=1e-8, depth=depth, dtype=np.float32, clustered=clustered)
+    print_case("pyramid", pr)
+    xs = [dev(pr.x), dev(pr.y), dev(pr.z), dev(pr.f)]
+    kw = dict(p=pr.p, tol=pr.tol, max_depth=pr.max_depth)
+    ta = fmt.fmt_fit(fmt.fmt_default_opts(gram=fmt.FMT_GRAM_MOMENTS, **kw), *xs)
+    tb = fmt.fmt_fit(fmt.fmt_default_opts(gram=fmt.FMT_GRAM_MOMENTS_LEVEL, **kw), *xs)
+    na, nb = ta.export_nodes(), tb.export_nodes()
+    for k in ("level", "prefix", "begin", "count"):
+        np.testing.assert_array_equal(na[k], nb[k])
+    ok = (na["flags"] & 1) == 0
+    scale = np.maximum(np.abs(nb["coeffs"][ok]), 1.0)
+    assert np.max(np.abs(na["coeffs"][ok] - nb["coeffs"][ok]) / scale) < 1e-7
+    ra, rb = ta.export_points()["residual"], tb.export_points()["residual"]
+    assert oracle.rms(ra - rb) <= 1e-11
+    if n <= 40000:
+        ot = oracle_fit(pr)
+        nodes, pts = compare_topology(ta, ot)
+        assert fitted_rms(pr, pts, ot) <= FP64_RMS
+    ta.close()
+    tb.close()
+
+
 def test_refinement_applies_where_conditioning_needs_it(fmt):
     """Float64 path: the refinement sweep is applied exactly to nodes whose
     equilibrated normal equations are ill-conditioned (or deflated); the
