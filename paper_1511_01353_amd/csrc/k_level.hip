@@ -68,93 +68,140 @@ __device__ __forceinline__ double pivot_recip(double d) {
 //   (a) the diagonal block and the panel below it in one right-looking pass:
 //       each wave that holds panel rows (up to 48, in lanes 16..63) also
 //       holds the block's 16 rows in lanes 0..15 and factors the block
-//       alongside (redundantly; wave 0 stores it).  At step k the pivot and the column entries A(c, k),
-//       c > k, reach all lanes through v_readlane (scalar registers); each
-//       lane scales its entry k by 1/d_k (its L(row, k)) and updates its
-//       entries c > k.  Entries above the diagonal of a block row collect
-//       values that are never read, so the updates need no mask;
-//   (b) the trailing blocks take A_IK -= (L_IJ D_J) L_KJ^T on float64 MFMA.
+//       alongside (redundantly; wave 0 stores it once the other waves have
+//       read it).  At step k lanes 0..15 publish column k of the block in
+//       LDS and every lane reads the pivot and the entries A(c, k), c > k, as
+//       broadcasts; each lane scales its entry k by 1/d_k (its L(row, k)) and
+//       updates its entries c > k.  Entries above the diagonal of a block row
+//       collect values that are never read, so the updates need no mask;
+//   (b) the trailing blocks take A_IK -= (L_IJ D_J) L_KJ^T on float64 MFMA,
+//       with lookahead: block column J+1 right away, the blocks right of it
+//       by the waves that do not take part in (a) for column J+1, while the
+//       others factor it.
 // Pivots at or below PIVOT_EPS are deflated: their inverse is 0, so their
 // column of L is 0 and the solve gives that unknown 0.
 // ---------------------------------------------------------------------------
+
+// A_IK -= (L_IJ D_J) L_KJ^T for one block pair, by one wave on MFMA.
+__device__ __forceinline__ void trailing_block(double* A, const double* dv, int J, int I, int K, int lane) {
+  double* out = A + bidx(I, K);
+  const double* li = A + bidx(I, J);
+  const double* lk = A + bidx(K, J);
+  solve_d4 acc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = out[bel((lane >> 4) + 4 * q, lane & 15)];
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const int kk = 4 * s4 + (lane >> 4);
+    const double av = -li[bel(lane & 15, kk)] * dv[16 * J + kk];
+    const double bv = lk[bel(lane & 15, kk)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[bel((lane >> 4) + 4 * q, lane & 15)] = acc[q];
+}
+
+// Block pair number p (0-based) of the lower triangle of block columns
+// K0 .. T-1, column by column: (I, K) with K0 <= K <= I < T.
+__device__ __forceinline__ void pair_of(int p, int K0, int T, int& I, int& K) {
+  K = K0;
+  while (p >= T - K) {
+    p -= T - K;
+    ++K;
+  }
+  I = K + p;
+}
+
 template <int L>
 __device__ __forceinline__ void ldl_blocked(double* A, double* dv, double* iv) {
   using S = BlockShape<L>;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   static_assert(S::LP - 16 <= 4 * 48, "the panel rows exceed the lanes of four waves");
+  __shared__ double colbuf[4 * 16];
   for (int J = 0; J < S::T; ++J) {
-    // (a) diagonal block (lanes 0..15 of every wave) and panel rows
-    // 16 (J + 1) + 48 w + lane - 16 (lanes 16..63 of wave w)
-    {
-      const int r = lane;
-      const int i0 = lane < 16 ? 16 * J + lane : 16 * (J + 1) + 48 * w + (lane - 16);
-      const bool live = i0 < S::LP;
-      const int i = live ? i0 : 16 * J;   // lanes past the last row point at a valid row, unused
-      double* row = A + bidx(i >> 4, J) + (i & 15) * 16;   // row i of block column J
-      const int sw = (i & 15) >> 1;
-      // waves past wave 0 without panel rows have nothing to do
-      const bool busy = w == 0 || 16 * (J + 1) + 48 * w < S::LP;
-      double a[16];
+    // waves 0 .. nbusy-1 factor column J (wave w > 0 only if it holds panel rows)
+    int nbusy = 1;
+    while (nbusy < 4 && 16 * (J + 1) + 48 * nbusy < S::LP) ++nbusy;
+    const bool busy = w < nbusy;
+    // trailing pairs of column J-1 right of column J: (I, K), J+1 <= K <= I
+    const int mrest = S::T - J - 1;
+    const int nrest = J >= 1 ? mrest * (mrest + 1) / 2 : 0;
+    if (nbusy == 4 && nrest > 0) {
+      for (int p = w; p < nrest; p += 4) {
+        int I, K;
+        pair_of(p, J + 1, S::T, I, K);
+        trailing_block(A, dv, J - 1, I, K, lane);
+      }
+      __syncthreads();
+    }
+    // (a) diagonal block (lanes 0..15) and panel rows 16 (J + 1) + 48 w +
+    // lane - 16 (lanes 16..63) of the busy waves
+    const int r = lane;
+    const int i0 = lane < 16 ? 16 * J + lane : 16 * (J + 1) + 48 * w + (lane - 16);
+    const bool live = i0 < S::LP;
+    const int i = live ? i0 : 16 * J;   // lanes past the last row point at a valid row, unused
+    double* row = A + bidx(i >> 4, J) + (i & 15) * 16;   // row i of block column J
+    const int sw = (i & 15) >> 1;
+    double a[16];
+    if (busy) {
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = (busy && live && (r >= 16 || c <= r)) ? row[c ^ sw] : 0.0;
-      __syncthreads();   // every wave has read the diagonal block before wave 0 overwrites it
-      if (busy) {
+      for (int c = 0; c < 16; ++c) a[c] = (live && (r >= 16 || c <= r)) ? row[c ^ sw] : 0.0;
+      // steps past the last real row of the block change nothing (the
+      // padding is the identity) and are skipped
+      const int kmax = L - 16 * J < 16 ? L - 16 * J : 16;
+      double* col = colbuf + 16 * w;   // this wave's copy of column k
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const double d = lane_value(a[k], k);
+      for (int k = 0; k < 16; ++k) {
+        if (k < kmax) {
+          // lanes 0..15 publish column k of the block; every lane then reads
+          // the pivot and the entries below it as broadcasts
+          if (r < 16) col[r] = a[k];
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const double d = col[k];
           const double inv = d > PIVOT_EPS ? pivot_recip(d) : 0.0;
           const double lk = a[k] * inv;                  // L[row][k] for rows below k
 #pragma unroll
-          for (int c = k + 1; c < 16; ++c) a[c] = fma(-lk, lane_value(a[k], c), a[c]);
+          for (int c = k + 1; c < 16; ++c) a[c] = fma(-lk, col[c], a[c]);
           a[k] = r > k ? lk : a[k];                      // lane k keeps its pivot
         }
-        if (r < 16) {
-          if (w == 0) {
-            // lane r's diagonal entry is its pivot; the inverse is recomputed
-            // from it exactly as in the step
-            double dr = a[0];
+      }
+      if (r < 16) {
+        if (w == 0) {
+          // lane r's diagonal entry is its pivot; the inverse is recomputed
+          // from it exactly as in the step
+          double dr = a[0];
 #pragma unroll
-            for (int c = 1; c < 16; ++c) dr = c == r ? a[c] : dr;
-            dv[16 * J + r] = dr;
-            iv[16 * J + r] = dr > PIVOT_EPS ? pivot_recip(dr) : 0.0;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) row[c ^ sw] = c < r ? a[c] : 0.0;
-          }
-        } else if (live) {
-#pragma unroll
-          for (int c = 0; c < 16; ++c) row[c ^ sw] = a[c];
+          for (int c = 1; c < 16; ++c) dr = c == r ? a[c] : dr;
+          dv[16 * J + r] = dr;
+          iv[16 * J + r] = dr > PIVOT_EPS ? pivot_recip(dr) : 0.0;
         }
+      } else if (live) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) row[c ^ sw] = a[c];
+      }
+    } else {
+      // the other waves meanwhile apply column J-1 to the blocks right of
+      // column J (column J itself was updated before this step)
+      for (int p = w - nbusy; p < nrest; p += 4 - nbusy) {
+        int I, K;
+        pair_of(p, J + 1, S::T, I, K);
+        trailing_block(A, dv, J - 1, I, K, lane);
       }
     }
     __syncthreads();
-    if (J + 1 == S::T) break;
-    // (b) trailing update A_IK -= (L_IJ D_J) L_KJ^T for J < K <= I, on MFMA
-    {
-      const int nb = S::T - J - 1;
-      const int npair = nb * (nb + 1) / 2;
-      for (int pidx = w; pidx < npair; pidx += 4) {
-        int rem = pidx, I = J + 1;
-        while (rem > I - J - 1) { rem -= I - J; ++I; }
-        const int K = J + 1 + rem;
-        double* out = A + bidx(I, K);
-        const double* li = A + bidx(I, J);
-        const double* lk = A + bidx(K, J);
-        solve_d4 acc;
+    // every wave has read the diagonal block: wave 0 stores its factor
+    if (w == 0 && r < 16) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = out[bel((lane >> 4) + 4 * q, lane & 15)];
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          const int kk = 4 * s4 + (lane >> 4);
-          const double av = -li[bel(lane & 15, kk)] * dv[16 * J + kk];
-          const double bv = lk[bel(lane & 15, kk)];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) out[bel((lane >> 4) + 4 * q, lane & 15)] = acc[q];
-      }
+      for (int c = 0; c < 16; ++c) row[c ^ sw] = c < r ? a[c] : 0.0;
     }
+    if (J + 1 == S::T) break;
+    // (b) lookahead: column J+1 now, (I, J+1) for I > J
+    for (int p = w; p < S::T - J - 1; p += 4) trailing_block(A, dv, J, J + 1 + p, J + 1, lane);
     __syncthreads();
   }
+  __syncthreads();   // the last diagonal block's factor is in place
 }
 
 // ---------------------------------------------------------------------------
