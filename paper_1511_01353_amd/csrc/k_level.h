@@ -177,6 +177,25 @@ __device__ __forceinline__ void node_geo(const ProblemParams& P, int level, uint
   }
 }
 
+// Copy N doubles (N a compile-time count) from global memory to LDS with
+// NT threads: every thread issues all of its loads before its first store,
+// so the copy costs one memory latency rather than one per round.
+template <int NT, int N>
+__device__ __forceinline__ void copy_to_lds(double* __restrict__ dst, const double* __restrict__ src, int tid) {
+  constexpr int R = (N + NT - 1) / NT;
+  double v[R > 0 ? R : 1];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int e = tid + q * NT;
+    v[q] = e < N ? src[e] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int e = tid + q * NT;
+    if (e < N) dst[e] = v[q];
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void load_point(const void* px, const void* py, const void* pz, uint32_t i, double& x,
                                            double& y, double& z) {

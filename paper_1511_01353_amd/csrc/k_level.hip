@@ -448,11 +448,25 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   const uint32_t* pt = a.pyr_tab ? a.pyr_tab + PYR_TAB_WORDS * a.nt.problem[node] : nullptr;
   if (pt && pyramid_covers(pt[1], a.level)) {
+    // M from the pyramid cell, B from the node's B-only partial; all loads
+    // issued before the first store
     const size_t cell = (size_t)pt[0] + level_first(a.level) + a.nt.prefix[node];
-    for (int e = tid; e < NM; e += 256) mom[e] = pyr[cell * NM + e];
-    for (int i = tid; i < L; i += 256) mom[NM + i] = part_b[(size_t)c0 * L + i];
+    const double* ms = pyr + cell * NM;
+    const double* bs = part_b + (size_t)c0 * L;
+    constexpr int RM = (NM + 255) / 256, RB = (L + 255) / 256;
+    double vm[RM], vb[RB];
+#pragma unroll
+    for (int q = 0; q < RM; ++q) vm[q] = tid + 256 * q < NM ? ms[tid + 256 * q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) vb[q] = tid + 256 * q < L ? bs[tid + 256 * q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < RM; ++q)
+      if (tid + 256 * q < NM) mom[tid + 256 * q] = vm[q];
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (tid + 256 * q < L) mom[NM + tid + 256 * q] = vb[q];
   } else {
-    for (int e = tid; e < NM + L; e += 256) mom[e] = part_m[(size_t)c0 * NOUT + e];
+    copy_to_lds<256, NM + L>(mom, part_m + (size_t)c0 * NOUT, tid);
   }
   for (int i = tid; i < L; i += 256) {
     ex[i][0] = B.lx[i];
@@ -519,7 +533,7 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
-  for (int e = tid; e < S::WORDS; e += 256) A[e] = fo[e];
+  copy_to_lds<256, S::WORDS>(A, fo, tid);
   if (tid < 16) A[S::WORDS + tid] = 0.0;
   for (int i = tid; i < L; i += 256) {
     iv[i] = fo[S::WORDS + L + i];

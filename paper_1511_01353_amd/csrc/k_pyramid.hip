@@ -146,68 +146,103 @@ __global__ void __launch_bounds__(1024) k_pyr_base(const uint32_t* __restrict__ 
   }
 }
 
-// Moment (exponents in `code`, 8 bits each) of the pair of children that
-// differ only along AXIS, in their common parent frame along that axis:
-// 2^-n sum_{m <= n} C(n, m) (hi_m + (-1)^(n - m) lo_m), n the exponent on
-// AXIS; binom[17 n + m] = C(n, m).
-template <int AXIS>
-__device__ __forceinline__ double shift_pair(const double* hi, const double* lo, uint32_t code,
-                                             const double* binom) {
-  int x[3] = {(int)(code & 255u), (int)((code >> 8) & 255u), (int)(code >> 16)};
-  const int n = x[AXIS];
-  double sum = 0.0;
-  for (int m = n; m >= 0; --m) {
-    x[AXIS] = m;
-    const int id = graded(x[0], x[1], x[2]);
-    const double h = hi[id], l = lo[id];
-    sum += binom[17 * n + m] * (((n - m) & 1) ? h - l : h + l);
+// Binomial coefficients C(n, m), n, m <= 16, as compile-time constants.
+struct Binomials {
+  double c[17][17];
+  constexpr Binomials() : c() {
+    for (int n = 0; n <= 16; ++n) {
+      c[n][0] = 1.0;
+      for (int m = 1; m <= n; ++m) c[n][m] = c[n - 1][m - 1] + (m <= n - 1 ? c[n - 1][m] : 0.0);
+    }
   }
-  return ldexp(sum, -n);
+};
+
+// The lines of the moment tensor (|gamma| <= P2) along one axis: line j
+// fixes the exponents (f0, f1) of the other two axes, f0 + f1 <= P2.
+template <int P2>
+struct Lines {
+  static constexpr int N = (P2 + 1) * (P2 + 2) / 2;
+  int f0[N], f1[N];
+  constexpr Lines() : f0(), f1() {
+    int j = 0;
+    for (int a = 0; a <= P2; ++a)
+      for (int b = 0; a + b <= P2; ++b) {
+        f0[j] = a;
+        f1[j] = b;
+        ++j;
+      }
+  }
+};
+
+// One line along AXIS (other exponents f0, f1 in axis order) of the pair of
+// children (hi, lo) that differ only along AXIS, in their parent's frame:
+// out_n = 2^-n sum_{m <= n} C(n, m) (hi_m + (-1)^(n - m) lo_m).  The line's
+// entries are read once into registers.
+template <int P2, int AXIS>
+__device__ __forceinline__ void shift_line(const double* hi, const double* lo, double* out, int f0, int f1) {
+  constexpr Binomials BN{};
+  const int len = P2 - f0 - f1 + 1;
+  int idx[P2 + 1];
+  double sp[P2 + 1], sm[P2 + 1];   // hi + lo, hi - lo
+#pragma unroll
+  for (int m = 0; m <= P2; ++m) {
+    const int e = m < len ? m : 0;
+    const int x = AXIS == 0 ? e : f0;
+    const int y = AXIS == 1 ? e : (AXIS == 0 ? f0 : f1);
+    const int z = AXIS == 2 ? e : f1;
+    idx[m] = graded(x, y, z);
+    const double h = hi[idx[m]], l = lo[idx[m]];
+    sp[m] = h + l;
+    sm[m] = h - l;
+  }
+#pragma unroll
+  for (int n = 0; n <= P2; ++n) {
+    if (n < len) {
+      double sum = 0.0;
+#pragma unroll
+      for (int m = 0; m <= n; ++m) sum = fma(BN.c[n][m], ((n - m) & 1) ? sm[m] : sp[m], sum);
+      out[idx[n]] = ldexp(sum, -n);
+    }
+  }
 }
 
 // One level up, for the problems whose pyramid extends below level d: the
 // parent is cell `prefix` of level d of problem list[j], built from its
 // children (8 consecutive entries of level d+1) by shifting along z (pairs
-// 2q, 2q+1), then y, then x.  One workgroup of UP_THREADS per parent.
-constexpr int UP_THREADS = 1024;
+// 2q, 2q+1), then y, then x, one tensor line per thread.  One workgroup of
+// UP_THREADS per parent.
+constexpr int UP_THREADS = 512;
 
 template <int P>
 __global__ void __launch_bounds__(UP_THREADS) k_pyr_up(double* __restrict__ pyr, const uint32_t* __restrict__ tab,
                                                        const uint32_t* __restrict__ list, int d) {
-  constexpr int NM = basis_size(2 * P);
-  constexpr Basis<2 * P> BM{};
+  constexpr int P2 = 2 * P;
+  constexpr int NM = basis_size(P2);
+  constexpr Lines<P2> LN{};
+  constexpr int NL = Lines<P2>::N;
   __shared__ double A[8 * NM], Bv[4 * NM];
-  __shared__ uint32_t ex[NM];
-  __shared__ double binom[17 * 17];
   const int tid = threadIdx.x;
-  if (tid < 17) {
-    // row n of Pascal's triangle (exact in float64 for n <= 16)
-    double v = 1.0;
-    for (int m = 0; m <= tid; ++m) {
-      binom[17 * tid + m] = v;
-      v = v * (double)(tid - m) / (double)(m + 1);
-    }
-  }
   const uint32_t j = blockIdx.x >> (3 * d), pre = blockIdx.x & ((1u << (3 * d)) - 1u);
   const uint32_t base = tab[PYR_TAB_WORDS * list[j]];
   const size_t parent = (size_t)base + level_first(d) + pre;
   const size_t child = (size_t)base + level_first(d + 1) + 8ull * pre;
-  for (int e = tid; e < NM; e += UP_THREADS)
-    ex[e] = (uint32_t)BM.lx[e] | ((uint32_t)BM.ly[e] << 8) | ((uint32_t)BM.lz[e] << 16);
-  const double* src = pyr + child * NM;
-  for (int e = tid; e < 8 * NM; e += UP_THREADS) A[e] = src[e];
+  copy_to_lds<UP_THREADS, 8 * NM>(A, pyr + child * NM, tid);
   __syncthreads();
-  for (int t = tid; t < 4 * NM; t += UP_THREADS) {
-    const int q = t / NM, e = t - q * NM;
-    Bv[t] = shift_pair<2>(A + (2 * q + 1) * NM, A + 2 * q * NM, ex[e], binom);
+  // z: lines (x, y fixed) of the pairs (2q, 2q+1)
+  for (int t = tid; t < 4 * NL; t += UP_THREADS) {
+    const int q = t / NL, l = t - q * NL;
+    shift_line<P2, 2>(A + (2 * q + 1) * NM, A + 2 * q * NM, Bv + q * NM, LN.f0[l], LN.f1[l]);
   }
   __syncthreads();
-  for (int t = tid; t < 2 * NM; t += UP_THREADS) {
-    const int q = t / NM, e = t - q * NM;
-    A[t] = shift_pair<1>(Bv + (2 * q + 1) * NM, Bv + 2 * q * NM, ex[e], binom);
+  // y: lines (x, z fixed) of the pairs (2q, 2q+1) of the z results
+  for (int t = tid; t < 2 * NL; t += UP_THREADS) {
+    const int q = t / NL, l = t - q * NL;
+    shift_line<P2, 1>(Bv + (2 * q + 1) * NM, Bv + 2 * q * NM, A + q * NM, LN.f0[l], LN.f1[l]);
   }
   __syncthreads();
-  for (int e = tid; e < NM; e += UP_THREADS) pyr[parent * NM + e] = shift_pair<0>(A + NM, A, ex[e], binom);
+  // x: lines (y, z fixed), straight to the parent's entry
+  for (int t = tid; t < NL; t += UP_THREADS)
+    shift_line<P2, 0>(A + NM, A, pyr + parent * NM, LN.f0[t], LN.f1[t]);
 }
 
 hipError_t launch_pyr_cells(const uint32_t* skey, uint32_t n, int D, int nprob, const ProblemParams* prm,
