@@ -220,8 +220,7 @@ constexpr int CHUNK = 2048;          // points per (node, chunk) work item
 constexpr int SORT_THREADS = 256;
 constexpr int SORT_ITEMS = 16;       // keys per thread per tile
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
-constexpr int RADIX_BITS = 8;
-constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int MAX_RADIX_BITS = 10;  // radix sort digits are 8 to 10 bits wide
 
 // ---------------------------------------------------------------------------
 // Device node table (structure of arrays, capacity `cap` nodes).

@@ -715,7 +715,9 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       {
         ProfScope ps(KN_RSWEEP, level_points, s);
         HIPCHK(launch_moments(F->p, 1, dtype, a, W.part_b.as<double>(), s));
-        if (multi) HIPCHK(launch_chunk_reduce(a, W.part_b.as<double>(), (uint32_t)rbd, s));
+        // every node refined: sum the chunks in parallel first (the
+        // refinement solve otherwise sums its node's chunks itself)
+        if (multi && a.refine == 2) HIPCHK(launch_chunk_reduce(a, W.part_b.as<double>(), (uint32_t)rbd, s));
       }
       ProfScope ps(KN_RSOLVE, nnodes, s);
       HIPCHK(launch_refine_solve(F->p, a, W.part_b.as<double>(), W.fac.as<double>(), s));

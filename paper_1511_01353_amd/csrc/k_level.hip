@@ -517,7 +517,8 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
 // ---------------------------------------------------------------------------
 // K7: refinement.  The sweep (power moments of r' = r - Lambda F, float64,
 // in k_moments.hip) gives B'[alpha] = sum r' u^alpha per chunk; the solve
-// takes delta = G^{-1} Lambda^T r' with the kept factor and sets F += delta.
+// sums its node's chunks, takes delta = G^{-1} Lambda^T r' with the kept
+// factor and sets F += delta.
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double* __restrict__ part_b,
@@ -531,14 +532,35 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
   if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
-  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
+  // with a.refine == 2 (every node refined) the chunk partials were summed
+  // into the first chunk's slot beforehand; otherwise they are summed here
+  const uint32_t c0 = a.chunk_off[k], c1 = a.refine == 2 ? c0 + 1 : a.chunk_off[k + 1];
   const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
   copy_to_lds<256, S::WORDS>(A, fo, tid);
   if (tid < 16) A[S::WORDS + tid] = 0.0;
+  // B' of the node: its chunks' partials summed here (G interleaved groups of
+  // chunks per moment, then the groups in order)
+  constexpr int G = 256 / L > 0 ? 256 / L : 1;
+  __shared__ double bsum[G][L];
+  if (tid < G * L) {
+    const int i = tid % L, q = tid / L;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    uint32_t g = c0 + (uint32_t)q;
+    for (; g + 7 * G < c1; g += 8 * G) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += part_b[(size_t)(g + u * G) * L + i];
+    }
+    for (; g < c1; g += G) acc[0] += part_b[(size_t)g * L + i];
+    bsum[q][i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  __syncthreads();
   for (int i = tid; i < L; i += 256) {
+    double t = bsum[0][i];
+#pragma unroll
+    for (int q = 1; q < G; ++q) t += bsum[q][i];
     iv[i] = fo[S::WORDS + L + i];
     sc[i] = fo[S::WORDS + 2 * L + i];
-    b[i] = part_b[(size_t)c0 * L + i] * B.inv_fact[i] * fo[S::WORDS + 2 * L + i];
+    b[i] = t * B.inv_fact[i] * fo[S::WORDS + 2 * L + i];
   }
   __syncthreads();
   if (tid < 64) tri_solve_wave<L>(A, iv, b, z);

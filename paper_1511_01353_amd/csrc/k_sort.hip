@@ -67,24 +67,73 @@ __global__ void __launch_bounds__(256) k_query_keys(const T* qx, const T* qy, co
 }
 
 // ---------------------------------------------------------------------------
-// Radix sort, one pass per RADIX_BITS digit.
+// Radix sort, one pass per BITS-bit digit (BITS = 8, 9 or 10, chosen per
+// sort so that the key takes the fewest passes).
 // Tile t of SORT_TILE keys is handled by block t; inside the tile, wave w
 // owns the contiguous quarter [w*TILE/4, (w+1)*TILE/4) and walks it in rounds
 // of 64 keys.
 // ---------------------------------------------------------------------------
+template <int BITS>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n,
                                                              int shift, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[RADIX];
-  for (int i = threadIdx.x; i < RADIX; i += SORT_THREADS) h[i] = 0;
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t h[R];
+  for (int i = threadIdx.x; i < R; i += SORT_THREADS) h[i] = 0;
   __syncthreads();
   uint32_t base = blockIdx.x * SORT_TILE;
 #pragma unroll
   for (int j = 0; j < SORT_ITEMS; ++j) {
     uint32_t i = base + j * SORT_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (R - 1)], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS) hist[d * gridDim.x + blockIdx.x] = h[d];
+  for (int d = threadIdx.x; d < R; d += SORT_THREADS) hist[d * gridDim.x + blockIdx.x] = h[d];
+}
+
+// Exclusive scans, in place, of two arrays x and y of R entries (R a
+// multiple of SORT_THREADS): thread t owns entries [t E, (t + 1) E); waves
+// scan with shuffles, then the wave totals are added in order.  Every
+// thread of the workgroup calls it.
+template <int R>
+__device__ __forceinline__ void exclusive_scan_pair(uint32_t* x, uint32_t* y, uint32_t* wx, uint32_t* wy) {
+  static_assert(R % SORT_THREADS == 0, "digit count must be a multiple of the workgroup size");
+  constexpr int E = R / SORT_THREADS;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t vx[E], vy[E], sx = 0, sy = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    vx[e] = x[tid * E + e];
+    vy[e] = y[tid * E + e];
+    sx += vx[e];
+    sy += vy[e];
+  }
+  uint32_t ix = sx, iy = sy;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t tx = (uint32_t)__shfl_up((int)ix, off), ty = (uint32_t)__shfl_up((int)iy, off);
+    if (lane >= off) {
+      ix += tx;
+      iy += ty;
+    }
+  }
+  if (lane == 63) {
+    wx[w] = ix;
+    wy[w] = iy;
+  }
+  __syncthreads();
+  uint32_t rx = ix - sx, ry = iy - sy;
+  for (int q = 0; q < w; ++q) {
+    rx += wx[q];
+    ry += wy[q];
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    x[tid * E + e] = rx;
+    rx += vx[e];
+    y[tid * E + e] = ry;
+    ry += vy[e];
+  }
+  __syncthreads();
 }
 
 // Exclusive scan of one digit's per-tile counts (workgroup d owns digit d:
@@ -114,7 +163,7 @@ __global__ void __launch_bounds__(256) k_digit_scan(uint32_t* __restrict__ hist,
   if (tid == 0) tot[blockIdx.x] = run;
 }
 
-template <bool FIRST>
+template <bool FIRST, int BITS>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
                                                                 uint32_t* __restrict__ kout,
@@ -122,17 +171,19 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
                                                                 int shift,
                                                                 const uint32_t* __restrict__ offs,
                                                                 const uint32_t* __restrict__ tot) {
+  constexpr int R = 1 << BITS;
   constexpr int WAVES = SORT_THREADS / 64;
   constexpr int QUARTER = SORT_TILE / WAVES;
   constexpr int ROUNDS = QUARTER / 64;
-  __shared__ uint32_t wcnt[WAVES][RADIX];
-  __shared__ uint32_t lofs[RADIX];
-  __shared__ uint32_t goff[RADIX];
-  __shared__ uint32_t dbase[RADIX];
+  __shared__ uint32_t wcnt[WAVES][R];
+  __shared__ uint32_t lofs[R];
+  __shared__ uint32_t goff[R];
+  __shared__ uint32_t dbase[R];
+  __shared__ uint32_t wsum[2][WAVES];
   __shared__ uint32_t sk[SORT_TILE];
   __shared__ uint32_t sv[SORT_TILE];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < WAVES * RADIX; i += SORT_THREADS) (&wcnt[0][0])[i] = 0;
+  for (int i = tid; i < WAVES * R; i += SORT_THREADS) (&wcnt[0][0])[i] = 0;
   __syncthreads();
 
   const uint64_t below_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -143,11 +194,11 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
     const uint32_t i = base + j * 64 + lane;
     const bool valid = i < n;
     const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t d = (k >> shift) & (RADIX - 1);
+    const uint32_t d = (k >> shift) & (R - 1);
     // lanes of this wave holding the same digit
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < RADIX_BITS; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
@@ -165,41 +216,27 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
   }
   __syncthreads();
   // per digit: wave bases and the tile-local digit start
-  if (tid < RADIX) {
+  for (int d = tid; d < R; d += SORT_THREADS) {
     uint32_t run = 0;
 #pragma unroll
     for (int ww = 0; ww < WAVES; ++ww) {
-      uint32_t c = wcnt[ww][tid];
-      wcnt[ww][tid] = run;
+      uint32_t c = wcnt[ww][d];
+      wcnt[ww][d] = run;
       run += c;
     }
-    lofs[tid] = run;   // tile-local digit total for now
-    dbase[tid] = tot[tid];
+    lofs[d] = run;   // tile-local digit total for now
+    dbase[d] = tot[d];
   }
   __syncthreads();
   // exclusive scans of the tile-local and of the global digit totals
-  const uint32_t mine = tid < RADIX ? lofs[tid] : 0u;
-  const uint32_t mine_g = tid < RADIX ? dbase[tid] : 0u;
-  for (int off = 1; off < RADIX; off <<= 1) {
-    const uint32_t v = (tid < RADIX && tid >= off) ? lofs[tid - off] : 0u;
-    const uint32_t vg = (tid < RADIX && tid >= off) ? dbase[tid - off] : 0u;
-    __syncthreads();
-    if (tid < RADIX) {
-      lofs[tid] += v;
-      dbase[tid] += vg;
-    }
-    __syncthreads();
-  }
-  if (tid < RADIX) {
-    lofs[tid] -= mine;
-    goff[tid] = dbase[tid] - mine_g + offs[tid * gridDim.x + blockIdx.x];
-  }
+  exclusive_scan_pair<R>(lofs, dbase, wsum[0], wsum[1]);
+  for (int d = tid; d < R; d += SORT_THREADS) goff[d] = dbase[d] + offs[d * gridDim.x + blockIdx.x];
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < ROUNDS; ++j) {
     const uint32_t i = base + j * 64 + lane;
     if (i < n) {
-      const uint32_t d = (key[j] >> shift) & (RADIX - 1);
+      const uint32_t d = (key[j] >> shift) & (R - 1);
       const uint32_t pos = lofs[d] + wcnt[w][d] + rank[j];
       sk[pos] = key[j];
       sv[pos] = val[j];
@@ -210,7 +247,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
   const uint32_t tn = min((uint32_t)SORT_TILE, n - tile0);
   for (uint32_t i = tid; i < tn; i += SORT_THREADS) {
     const uint32_t k = sk[i];
-    const uint32_t d = (k >> shift) & (RADIX - 1);
+    const uint32_t d = (k >> shift) & (R - 1);
     const uint32_t o = goff[d] + (i - lofs[d]);
     kout[o] = k;
     vout[o] = sv[i];
@@ -223,7 +260,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter(const uint32_t* 
 // coalesced at the element's source position, written coalesced at its
 // destination), so the payload costs neither registers during ranking nor
 // extra LDS.  FIRST: values are source positions (not read).
-template <bool FIRST, typename PT, int NP>
+template <bool FIRST, typename PT, int NP, int BITS>
 __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ vin,
                                                                   PayloadSet<PT, NP> pin,
@@ -232,20 +269,22 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t
                                                                   PayloadSet<PT, NP> pout, uint32_t n, int shift,
                                                                   const uint32_t* __restrict__ offs,
                                                                   const uint32_t* __restrict__ tot) {
+  constexpr int R = 1 << BITS;
   constexpr int WAVES = SORT_THREADS / 64;
   constexpr int QUARTER = SORT_TILE / WAVES;
   constexpr int ROUNDS = QUARTER / 64;
   constexpr int OUTS = SORT_TILE / SORT_THREADS;
   static_assert(sizeof(PT) <= 8, "payload elements of at most 8 bytes");
-  __shared__ uint32_t wcnt[WAVES][RADIX];
-  __shared__ uint32_t lofs[RADIX];
-  __shared__ uint32_t goff[RADIX];
-  __shared__ uint32_t dbase[RADIX];
+  __shared__ uint32_t wcnt[WAVES][R];
+  __shared__ uint32_t lofs[R];
+  __shared__ uint32_t goff[R];
+  __shared__ uint32_t dbase[R];
+  __shared__ uint32_t wsum[2][WAVES];
   __shared__ __attribute__((aligned(16))) uint32_t stage[2 * SORT_TILE];
   uint32_t* sk = stage;
   uint32_t* sv = stage + SORT_TILE;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < WAVES * RADIX; i += SORT_THREADS) (&wcnt[0][0])[i] = 0;
+  for (int i = tid; i < WAVES * R; i += SORT_THREADS) (&wcnt[0][0])[i] = 0;
   __syncthreads();
 
   const uint64_t below_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -269,10 +308,10 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t
     const uint32_t i = base + j * 64 + lane;
     const bool valid = i < n;
     const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t d = (k >> shift) & (RADIX - 1);
+    const uint32_t d = (k >> shift) & (R - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < RADIX_BITS; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
@@ -286,41 +325,28 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t
     key[j] = k;
   }
   __syncthreads();
-  if (tid < RADIX) {
+  for (int d = tid; d < R; d += SORT_THREADS) {
     uint32_t run = 0;
 #pragma unroll
     for (int ww = 0; ww < WAVES; ++ww) {
-      uint32_t c = wcnt[ww][tid];
-      wcnt[ww][tid] = run;
+      uint32_t c = wcnt[ww][d];
+      wcnt[ww][d] = run;
       run += c;
     }
-    lofs[tid] = run;
-    dbase[tid] = tot[tid];
+    lofs[d] = run;   // tile-local digit total for now
+    dbase[d] = tot[d];
   }
   __syncthreads();
-  const uint32_t mine = tid < RADIX ? lofs[tid] : 0u;
-  const uint32_t mine_g = tid < RADIX ? dbase[tid] : 0u;
-  for (int off = 1; off < RADIX; off <<= 1) {
-    const uint32_t v = (tid < RADIX && tid >= off) ? lofs[tid - off] : 0u;
-    const uint32_t vg = (tid < RADIX && tid >= off) ? dbase[tid - off] : 0u;
-    __syncthreads();
-    if (tid < RADIX) {
-      lofs[tid] += v;
-      dbase[tid] += vg;
-    }
-    __syncthreads();
-  }
-  if (tid < RADIX) {
-    lofs[tid] -= mine;
-    goff[tid] = dbase[tid] - mine_g + offs[tid * gridDim.x + blockIdx.x];
-  }
+  // exclusive scans of the tile-local and of the global digit totals
+  exclusive_scan_pair<R>(lofs, dbase, wsum[0], wsum[1]);
+  for (int d = tid; d < R; d += SORT_THREADS) goff[d] = dbase[d] + offs[d * gridDim.x + blockIdx.x];
   __syncthreads();
   // tile-local position of each of this lane's elements
   uint32_t pos[ROUNDS];
 #pragma unroll
   for (int j = 0; j < ROUNDS; ++j) {
     const uint32_t i = base + j * 64 + lane;
-    const uint32_t d = (key[j] >> shift) & (RADIX - 1);
+    const uint32_t d = (key[j] >> shift) & (R - 1);
     pos[j] = lofs[d] + wcnt[w][d] + rank[j];
     if (i < n) {
       sk[pos[j]] = key[j];
@@ -337,7 +363,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_radix_scatter_p(const uint32_t
     const uint32_t i = tid + m * SORT_THREADS;
     if (i < tn) {
       const uint32_t k = sk[i];
-      const uint32_t d = (k >> shift) & (RADIX - 1);
+      const uint32_t d = (k >> shift) & (R - 1);
       dst[m] = goff[d] + (i - lofs[d]);
       kout[dst[m]] = k;
       vout[dst[m]] = sv[i];
@@ -393,14 +419,43 @@ hipError_t launch_query_keys(int dtype, const void* qx, const void* qy, const vo
   return hipGetLastError();
 }
 
+// Digit width for a sort over `bits` key bits: 8, 9 or 10, the narrowest
+// that needs the fewest passes (e.g. 18 bits: two passes of 9).
+static int digit_bits(int bits) {
+  int best = 8, best_p = (bits + 7) / 8;
+  for (int w = 9; w <= MAX_RADIX_BITS; ++w) {
+    const int p = (bits + w - 1) / w;
+    if (p < best_p) {
+      best = w;
+      best_p = p;
+    }
+  }
+  return best;
+}
+
 int radix_sort_passes(int bits) {
-  const int p = (bits + RADIX_BITS - 1) / RADIX_BITS;
-  return p < 1 ? 1 : p;
+  const int w = digit_bits(bits);
+  const int p = (bits + w - 1) / w;
+  return p < 1 ? 1 : p;   // at least one pass so that the index array is written
 }
 
 size_t radix_sort_scratch_words(uint32_t n) {
   uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
-  return (size_t)RADIX * tiles + RADIX + 16;
+  return ((size_t)tiles + 1) * (1u << MAX_RADIX_BITS) + 16;
+}
+
+// One pass (histogram, digit scan, scatter) of the plain sort.
+template <int BITS>
+static void plain_pass(bool iota, const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, uint32_t n,
+                       uint32_t tiles, int shift, uint32_t* hist, uint32_t* tot, hipStream_t s) {
+  hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
+  hipLaunchKernelGGL(k_digit_scan, dim3(1 << BITS), dim3(256), 0, s, hist, tiles, tot);
+  if (iota)
+    hipLaunchKernelGGL((k_radix_scatter<true, BITS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n,
+                       shift, hist, tot);
+  else
+    hipLaunchKernelGGL((k_radix_scatter<false, BITS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n,
+                       shift, hist, tot);
 }
 
 hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
@@ -408,21 +463,16 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32
   *result_in_alt = false;
   if (n == 0) return hipSuccess;
   const uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const int w = digit_bits(bits);
   uint32_t* hist = scratch;
-  uint32_t* tot = scratch + (size_t)RADIX * tiles;
-  int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
-  if (passes < 1) passes = 1;   // at least one pass so that the index array is written
+  uint32_t* tot = scratch + ((size_t)tiles << w);
+  const int passes = radix_sort_passes(bits);
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
   for (int p = 0; p < passes; ++p) {
-    const int shift = p * RADIX_BITS;
-    hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
-    hipLaunchKernelGGL(k_digit_scan, dim3(RADIX), dim3(256), 0, s, hist, tiles, tot);
-    if (p == 0 && vals_are_iota)
-      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
-                         hist, tot);
-    else
-      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, ko, vo, n, shift,
-                         hist, tot);
+    const bool iota = p == 0 && vals_are_iota;
+    if (w == 8) plain_pass<8>(iota, ki, vi, ko, vo, n, tiles, p * w, hist, tot, s);
+    else if (w == 9) plain_pass<9>(iota, ki, vi, ko, vo, n, tiles, p * w, hist, tot, s);
+    else plain_pass<10>(iota, ki, vi, ko, vo, n, tiles, p * w, hist, tot, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t* t = ki; ki = ko; ko = t;
@@ -432,13 +482,29 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32
   return hipSuccess;
 }
 
+// One pass of the payload sort.
+template <typename PT, int NP, int BITS>
+static void payload_pass(bool first, const uint32_t* ki, const uint32_t* vi, const PayloadSet<PT, NP>& pi,
+                         uint32_t* ko, uint32_t* vo, const PayloadSet<PT, NP>& po, uint32_t n, uint32_t tiles,
+                         int shift, uint32_t* hist, uint32_t* tot, hipStream_t s) {
+  hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
+  hipLaunchKernelGGL(k_digit_scan, dim3(1 << BITS), dim3(256), 0, s, hist, tiles, tot);
+  if (first)
+    hipLaunchKernelGGL((k_radix_scatter_p<true, PT, NP, BITS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi,
+                       ko, vo, po, n, shift, hist, tot);
+  else
+    hipLaunchKernelGGL((k_radix_scatter_p<false, PT, NP, BITS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi,
+                       ko, vo, po, n, shift, hist, tot);
+}
+
 template <typename PT, int NP>
 static hipError_t radix_sort_payload_t(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                        const void* const* pin, void* const* pay, void* const* pay_alt, uint32_t n,
                                        int bits, uint32_t* scratch, hipStream_t s, bool* result_in_alt) {
   const uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const int w = digit_bits(bits);
   uint32_t* hist = scratch;
-  uint32_t* tot = scratch + (size_t)RADIX * tiles;
+  uint32_t* tot = scratch + ((size_t)tiles << w);
   const int passes = radix_sort_passes(bits);
   uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
   PayloadSet<PT, NP> src, a, b;
@@ -451,15 +517,9 @@ static hipError_t radix_sort_payload_t(uint32_t* keys, uint32_t* vals, uint32_t*
   // sets alternate like the keys
   PayloadSet<PT, NP> pi = src, po = b;
   for (int p = 0; p < passes; ++p) {
-    const int shift = p * RADIX_BITS;
-    hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, ki, n, shift, hist);
-    hipLaunchKernelGGL(k_digit_scan, dim3(RADIX), dim3(256), 0, s, hist, tiles, tot);
-    if (p == 0)
-      hipLaunchKernelGGL((k_radix_scatter_p<true, PT, NP>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi, ko,
-                         vo, po, n, shift, hist, tot);
-    else
-      hipLaunchKernelGGL((k_radix_scatter_p<false, PT, NP>), dim3(tiles), dim3(SORT_THREADS), 0, s, ki, vi, pi,
-                         ko, vo, po, n, shift, hist, tot);
+    if (w == 8) payload_pass<PT, NP, 8>(p == 0, ki, vi, pi, ko, vo, po, n, tiles, p * w, hist, tot, s);
+    else if (w == 9) payload_pass<PT, NP, 9>(p == 0, ki, vi, pi, ko, vo, po, n, tiles, p * w, hist, tot, s);
+    else payload_pass<PT, NP, 10>(p == 0, ki, vi, pi, ko, vo, po, n, tiles, p * w, hist, tot, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     std::swap(ki, ko);

@@ -135,6 +135,7 @@ def print_case(name, pr):
     (5000, 0, 3, 0.0, 14, np.float64),
     (3000, 5, 2, 1e-7, 15, np.float64),
     (40000, 8, 2, 1e-8, 16, np.float32),       # calL = 165: the largest basis
+    (6000, 1, 10, 1e-9, 17, np.float64),       # D = 10: 30-bit keys, three 10-bit sort passes
 ])
 def test_fp64_path_matches_oracle(fmt, n, p, depth, tol, seed, dtype):
     pr = synthetic.small_problem(n, p, seed, tol=tol, depth=depth, dtype=dtype, nq=5000)
