@@ -141,7 +141,7 @@ __device__ __forceinline__ void accumulate_item(const double (&pu)[2 * P + 1], c
     acc[s] += wt * wt;
   } else {
     double h = pu[ea] * pv[eb];
-    if constexpr (k == 1) h *= wt;
+    if constexpr (k == 1 && MomentPlan<P, MODE>::HAS_M) h *= wt;
     acc_run<s, NA, 2 * P>(std::make_index_sequence<n>{}, h, pw, acc);
   }
 }
@@ -196,7 +196,10 @@ __device__ __forceinline__ void moments_group(const Staged<MODE, TIN>& st, uint3
     double wt = 0.0;
     if constexpr (Staged<MODE, TIN>::HAS_W) wt = st.w[j];
     double pu[P2 + 1], pv[P2 + 1], pw[P2 + 1];
-    pu[0] = pv[0] = pw[0] = 1.0;
+    // the B-only modes fold the weight into the w powers (one product per
+    // run fewer); the others weight the B runs' leading product
+    pu[0] = pv[0] = 1.0;
+    pw[0] = MP::HAS_M ? 1.0 : wt;
 #pragma unroll
     for (int k = 1; k <= MP::PMAX; ++k) {
       pu[k] = pu[k - 1] * u;
