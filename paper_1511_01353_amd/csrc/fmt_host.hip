@@ -939,7 +939,7 @@ static void ensure_composed(Forest& F, int problem, hipStream_t s) {
   }
   HIPCHK(hipStreamWaitEvent(s, F.cell_ev[problem], 0));
   if (!F.composed) {
-    F.nb_ccoef.alloc(sizeof(double) * (size_t)F.L * std::max<uint32_t>(F.nodes, 1));
+    F.nb_ccoef.alloc(sizeof(double) * (size_t)ccoef_stride(F.L) * std::max<uint32_t>(F.nodes, 1));
     {
       ProfScope ps(KN_COMPOSE, F.nodes, s);
       HIPCHK(launch_compose(F.p, F.table(), F.nodes, F.nb_ccoef.as<double>(), s));

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t nodes, d
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int e = lane; e < L; e += 64) cc[(size_t)v * L + e] = cur[e];
+  for (int e = lane; e < ccoef_stride(L); e += 64) cc[(size_t)v * ccoef_stride(L) + e] = e < L ? cur[e] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -126,16 +126,27 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
 // query's cell, exactly as the fit computes it, so no geometry is loaded.
 // In sorted mode the coordinates arrive in key order (moved by the sort),
 // skeys holds their keys and perm their positions in the caller's order,
-// where the result is written.  A wave whose queries all reach one node
-// reads that node's coefficients with wave-uniform (scalar) loads.
+// where the result is written.
+// Coefficient rows: a wave whose queries all reach one node reads the row
+// with wave-uniform (scalar) loads.  Otherwise the rows come through LDS in
+// four rounds of 16 queries: the 4 lanes of a quad load one query's row
+// together (each instruction reads 64 contiguous bytes per query, one cache
+// line, instead of one line per lane), and the query's own lane evaluates it.
 // ---------------------------------------------------------------------------
-template <int P, typename TQ>
-__global__ void __launch_bounds__(256) k_eval(EvalTree t, const double* __restrict__ cc, const TQ* __restrict__ qx,
-                                              const TQ* __restrict__ qy, const TQ* __restrict__ qz,
-                                              const uint32_t* __restrict__ perm, const uint32_t* __restrict__ skeys,
-                                              uint32_t nq, double* __restrict__ out) {
+constexpr int EVAL_THREADS = 128;
+
+template <int P, typename TIN>
+__global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double* __restrict__ cc,
+                                                       const TIN* __restrict__ qx, const TIN* __restrict__ qy,
+                                                       const TIN* __restrict__ qz, const uint32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ skeys, uint32_t nq,
+                                                       double* __restrict__ out) {
   constexpr int L = basis_size(P);
+  constexpr int CS = ccoef_stride(L);
+  constexpr int WAVES = EVAL_THREADS / 64;
+  __shared__ __attribute__((aligned(16))) double rows[WAVES][16 * CS];
   const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool valid = i0 < nq;
   const uint32_t i = valid ? i0 : nq - 1;   // tail lanes repeat the last query and do not store
   const uint32_t src = perm ? perm[i] : i;   // caller's position of query i
@@ -167,15 +178,42 @@ __global__ void __launch_bounds__(256) k_eval(EvalTree t, const double* __restri
   const double* fr = t.lvl + 6 * d;
   const double u = (x - __dadd_rn(t.prm.lo[0], __dmul_rn((double)ci + 0.5, fr[0]))) * fr[3];
   const double v = (y - __dadd_rn(t.prm.lo[1], __dmul_rn((double)cj + 0.5, fr[1]))) * fr[4];
-  const double w = (z - __dadd_rn(t.prm.lo[2], __dmul_rn((double)ck + 0.5, fr[2]))) * fr[5];
+  const double ww = (z - __dadd_rn(t.prm.lo[2], __dmul_rn((double)ck + 0.5, fr[2]))) * fr[5];
   const uint32_t n0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)node);
-  double val;
+  double val = 0.0;
   if (__ballot(node != n0) == 0) {
     // read-only constant address space + a wave-uniform address: scalar loads
     typedef const double __attribute__((address_space(4))) cdouble;
-    val = poly_eval<P, double>((const cdouble*)(cc + (size_t)n0 * L), u, v, w);
+    val = poly_eval<P, double>((const cdouble*)(cc + (size_t)n0 * CS), u, v, ww);
   } else {
-    val = poly_eval<P, double>(cc + (size_t)node * L, u, v, w);
+    double* buf = rows[w];
+    const int q4 = lane >> 2, part = lane & 3;
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+      // the quad's query: lane 16 r + q4
+      const uint32_t nd = (uint32_t)__shfl((int)node, 16 * r + q4);
+      const double2* srow = reinterpret_cast<const double2*>(cc + (size_t)nd * CS);
+      double2* drow = reinterpret_cast<double2*>(buf + q4 * CS);
+      constexpr int PAIRS = CS / 2, STEPS = (PAIRS + 3) / 4;
+      double2 vals[STEPS];
+#pragma unroll
+      for (int k = 0; k < STEPS; ++k) {
+        const int pr = 4 * k + part;
+        vals[k] = pr < PAIRS ? srow[pr] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int k = 0; k < STEPS; ++k) {
+        const int pr = 4 * k + part;
+        if (pr < PAIRS) drow[pr] = vals[k];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if ((lane >> 4) == r) val = poly_eval<P, double>(buf + (lane & 15) * CS, u, v, ww);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
   if (valid) out[src] = val;
 }
@@ -204,7 +242,7 @@ static hipError_t eval_impl(int dtype, const EvalTree& t, const double* cc, cons
                             const void* qz, const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out,
                             hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  dim3 grid((nq + 255) / 256), block(256);
+  dim3 grid((nq + EVAL_THREADS - 1) / EVAL_THREADS), block(EVAL_THREADS);
   if (dtype == FMT_F32)
     hipLaunchKernelGGL((k_eval<P, float>), grid, block, 0, s, t, cc, (const float*)qx, (const float*)qy,
                        (const float*)qz, perm, skeys, nq, out);

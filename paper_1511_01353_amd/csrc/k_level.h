@@ -120,7 +120,11 @@ hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint3
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
                        uint32_t seq, hipStream_t s);
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
-// Composite coefficients of every node (its chain's polynomials in its frame).
+// Row stride (doubles) of the composite coefficient table: calL rounded up to
+// even, so that every row starts on a 16-byte boundary.
+__host__ __device__ constexpr int ccoef_stride(int L) { return L + (L & 1); }
+// Composite coefficients of every node (its chain's polynomials in its
+// frame), ccoef_stride(calL) doubles per node.
 hipError_t launch_compose(int p, const NodeTable& nt, uint32_t nodes, double* cc, hipStream_t s);
 // Cell table of one tree: 8^T entries, see EvalTree::cells.
 // Also writes the frame table lvl (LVL_DOUBLES) of the tree's problem.
