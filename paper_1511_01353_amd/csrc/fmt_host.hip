@@ -942,7 +942,8 @@ static void ensure_composed(Forest& F, int problem, hipStream_t s) {
     F.nb_ccoef.alloc(sizeof(double) * (size_t)ccoef_stride(F.L) * std::max<uint32_t>(F.nodes, 1));
     {
       ProfScope ps(KN_COMPOSE, F.nodes, s);
-      HIPCHK(launch_compose(F.p, F.table(), F.nodes, F.nb_ccoef.as<double>(), s));
+      for (size_t d = 0; d < F.level_start.size(); ++d)
+        HIPCHK(launch_compose(F.p, F.table(), F.level_start[d], F.level_count[d], F.nb_ccoef.as<double>(), s));
     }
     hipEvent_t ev = nullptr;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1191,7 +1192,16 @@ fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_
     F->probs[0].prm = prm;
     F->probs[0].root = 0;
     F->probs[0].n = 0;
-    F->level_start.assign(1, 0);
+    // nodes are in level order: one range per level
+    F->level_start.clear();
+    F->level_count.clear();
+    for (uint32_t j = 0; j < M; ++j) {
+      if (j == 0 || hl[j] != hl[j - 1]) {
+        F->level_start.push_back(j);
+        F->level_count.push_back(0);
+      }
+      ++F->level_count.back();
+    }
     F->depth_present = (int)*std::max_element(hl.begin(), hl.end());
     fmt_tree* t = new fmt_tree();
     t->forest = F;

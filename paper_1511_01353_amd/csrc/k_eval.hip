@@ -16,14 +16,16 @@ namespace fmt {
 // half of the parent cell, -1 for the lower), so one scaled monomial
 // re-expands as
 //   u_p^l / l! = sum_{k <= l} (u_c^k / k!) sigma^(l-k) / (2^l (l-k)!),
-// applied axis by axis.  Walking from the root along the node's prefix,
-// C <- shift(C) + F_child at every level gives the node's composite.
-// One wave per node, four nodes per workgroup; roots are stored first, one
-// per problem, in problem order.
+// applied axis by axis: a node's composite is its parent's composite shifted
+// into its frame plus its own polynomial (a root's is its own).  One launch
+// per level, parents before children; one wave per node, four nodes per
+// workgroup.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t nodes, double* __restrict__ cc) {
+__global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t first, uint32_t count,
+                                                 double* __restrict__ cc) {
   constexpr int L = basis_size(P);
+  constexpr int CS = ccoef_stride(L);
   constexpr Basis<P> B{};
   __shared__ double buf[4][2][L];
   __shared__ int ex[L][3];
@@ -34,18 +36,21 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t nodes, d
     ex[i][2] = B.lz[i];
   }
   __syncthreads();
-  const uint32_t v = blockIdx.x * 4 + (uint32_t)w;
-  if (v >= nodes) return;   // the whole wave leaves; no workgroup barrier follows
-  const int lv = (int)nt.level[v];
-  const uint32_t pre = nt.prefix[v];
-  uint32_t node = nt.problem[v];   // the root of v's problem
+  const uint32_t k = blockIdx.x * 4 + (uint32_t)w;
+  if (k >= count) return;   // the whole wave leaves; no workgroup barrier follows
+  const uint32_t v = first + k;
   double* cur = buf[w][0];
   double* nxt = buf[w][1];
-  for (int e = lane; e < L; e += 64) cur[e] = nt.coef[(size_t)node * L + e];
-  for (int d = 0; d < lv; ++d) {
-    const uint32_t o = (pre >> (3 * (lv - d - 1))) & 7u;
-    const uint32_t m = nt.child_mask[node];
-    node = nt.first_child[node] + (uint32_t)__popc(m & ((1u << o) - 1u));
+  const double* F = nt.coef + (size_t)v * L;
+  double own[(L + 63) / 64];
+#pragma unroll
+  for (int q = 0; q < (L + 63) / 64; ++q) own[q] = lane + 64 * q < L ? F[lane + 64 * q] : 0.0;
+  if (nt.level[v] > 0) {
+    const uint32_t par = nt.parent[v];
+    const uint32_t o = nt.prefix[v] & 7u;
+#pragma unroll
+    for (int q = 0; q < (L + 63) / 64; ++q)
+      if (lane + 64 * q < L) cur[lane + 64 * q] = cc[(size_t)par * CS + lane + 64 * q];
 #pragma unroll
     for (int axis = 0; axis < 3; ++axis) {
       const double sg = ((o >> (2 - axis)) & 1u) ? 1.0 : -1.0;
@@ -54,13 +59,13 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t nodes, d
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int e = lane; e < L; e += 64) {
         int xyz[3] = {ex[e][0], ex[e][1], ex[e][2]};
-        const int k = xyz[axis];
-        const int top = P - (xyz[0] + xyz[1] + xyz[2] - k);
-        double sum = 0.0, t = ldexp(1.0, -k);
-        for (int l = k; l <= top; ++l) {
+        const int kk = xyz[axis];
+        const int top = P - (xyz[0] + xyz[1] + xyz[2] - kk);
+        double sum = 0.0, t = ldexp(1.0, -kk);
+        for (int l = kk; l <= top; ++l) {
           xyz[axis] = l;
           sum = fma(cur[graded(xyz[0], xyz[1], xyz[2])], t, sum);
-          t *= sg / (2.0 * (double)(l + 1 - k));
+          t *= sg / (2.0 * (double)(l + 1 - kk));
         }
         nxt[e] = sum;
       }
@@ -71,12 +76,15 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t nodes, d
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int e = lane; e < L; e += 64) cur[e] += nt.coef[(size_t)node * L + e];
+#pragma unroll
+    for (int q = 0; q < (L + 63) / 64; ++q)
+      if (lane + 64 * q < L) own[q] += cur[lane + 64 * q];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int e = lane; e < ccoef_stride(L); e += 64) cc[(size_t)v * ccoef_stride(L) + e] = e < L ? cur[e] : 0.0;
+#pragma unroll
+  for (int q = 0; q < (CS + 63) / 64; ++q) {
+    const int e = lane + 64 * q;
+    if (e < CS) cc[(size_t)v * CS + e] = e < L ? own[q] : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -219,14 +227,14 @@ __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double*
 }
 
 template <int P>
-static hipError_t compose_impl(const NodeTable& nt, uint32_t nodes, double* cc, hipStream_t s) {
-  if (nodes == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compose<P>, dim3((nodes + 3) / 4), dim3(256), 0, s, nt, nodes, cc);
+static hipError_t compose_impl(const NodeTable& nt, uint32_t first, uint32_t count, double* cc, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compose<P>, dim3((count + 3) / 4), dim3(256), 0, s, nt, first, count, cc);
   return hipGetLastError();
 }
 
-hipError_t launch_compose(int p, const NodeTable& nt, uint32_t nodes, double* cc, hipStream_t s) {
-  FMT_DISPATCH_P(p, compose_impl, nt, nodes, cc, s);
+hipError_t launch_compose(int p, const NodeTable& nt, uint32_t first, uint32_t count, double* cc, hipStream_t s) {
+  FMT_DISPATCH_P(p, compose_impl, nt, first, count, cc, s);
 }
 
 hipError_t launch_cell_table(const NodeTable& nt, uint32_t root, int T, const ProblemParams& prm, double* lvl,

@@ -123,9 +123,10 @@ hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32
 // Row stride (doubles) of the composite coefficient table: calL rounded up to
 // even, so that every row starts on a 16-byte boundary.
 __host__ __device__ constexpr int ccoef_stride(int L) { return L + (L & 1); }
-// Composite coefficients of every node (its chain's polynomials in its
-// frame), ccoef_stride(calL) doubles per node.
-hipError_t launch_compose(int p, const NodeTable& nt, uint32_t nodes, double* cc, hipStream_t s);
+// Composite coefficients (a node's chain of polynomials in its frame),
+// ccoef_stride(calL) doubles per node, of the nodes first .. first+count-1,
+// all of one level; the parents' rows must be in place.
+hipError_t launch_compose(int p, const NodeTable& nt, uint32_t first, uint32_t count, double* cc, hipStream_t s);
 // Cell table of one tree: 8^T entries, see EvalTree::cells.
 // Also writes the frame table lvl (LVL_DOUBLES) of the tree's problem.
 hipError_t launch_cell_table(const NodeTable& nt, uint32_t root, int T, const ProblemParams& prm, double* lvl,
