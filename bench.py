@@ -98,8 +98,13 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
     add("bmoments", "alu", bmoment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("base_moments", "alu", base_moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("solve", "alu", solve_flops_per_node(L), "TFLOP/s", PEAK_TFLOPS["fp64"])
-    add("refine_solve", "alu", 2.0 * L * L, "TFLOP/s", PEAK_TFLOPS["fp64"])
-    add("refine_sweep", "alu", refine_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    if path == "mixed":
+        # every node is refined; on the float64 path only the nodes the
+        # condition estimate flags are, a count the host does not see, so the
+        # launches' units (all of the level's points and nodes) would overstate
+        # the work
+        add("refine_solve", "alu", 2.0 * L * L, "TFLOP/s", PEAK_TFLOPS["fp64"])
+        add("refine_sweep", "alu", refine_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     # residual: coordinates + residual read, residual written, key read
     add("residual", "hbm", 3 * coord_bytes + 8 + 8 + 4, "GB/s", PEAK_HBM_GBS)
     # sort: per pass read and write key and index, and the payload (the fit
