@@ -1,0 +1,93 @@
+"""The paper's scoping experiments (Section 4) on one GPU.
+
+The 3-D Franke function (eq. eqF1) is fitted on N_p uniform random points in
+[0,1]^3 and evaluated on a separate random grid of N_q = N_p points, for a
+sweep of orders, tolerances tau and grid sizes; for each case the total RMS
+and max errors against the true function at the query points, the octree
+node count and the fit / evaluation times are reported (one JSON object per
+line, then a summary line).  The float64 path and float64 storage are used
+throughout: the errors of interest go well below float32 rounding.
+
+  python -m paper_1511_01353_amd.scoping [--orders 4,8] [--taus 1e-6,1e-8,1e-10,1e-12]
+                                          [--sizes 4,5,6,7] [--depth 10]
+
+Orders above FMT_MAX_P (8) are not supported by this implementation.
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def run_case(fmt, torch, pr, tau, depth, reps=3):
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()   # noqa: E731
+    x, y, z, f = dev(pr.x), dev(pr.y), dev(pr.z), dev(pr.f)
+    qx, qy, qz = dev(pr.qx), dev(pr.qy), dev(pr.qz)
+    opts = fmt.fmt_default_opts(p=pr.p, tol=tau, max_depth=depth)
+    out = torch.empty(pr.qx.shape[0], dtype=torch.float64, device="cuda")
+    fit_ms, eval_ms = [], []
+    tree = None
+    for _ in range(reps):
+        if tree is not None:
+            tree.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tree = fmt.fmt_fit(opts, x, y, z, f)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tree.eval(qx, qy, qz, out)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fit_ms.append((t1 - t0) * 1e3)
+        eval_ms.append((t2 - t1) * 1e3)
+    info = tree.info()
+    got = out.cpu().numpy()
+    err = got - pr.qf_true
+    tree.close()
+    return {
+        "p": pr.p, "calL": (pr.p + 1) * (pr.p + 2) * (pr.p + 3) // 6, "n": int(pr.x.shape[0]), "tau": tau,
+        "nodes": int(info.nodes), "depth": int(info.depth),
+        "per_level": [int(info.per_level[d]) for d in range(info.depth + 1)],
+        "E_rms": float(np.sqrt(np.mean(err * err))), "E_inf": float(np.max(np.abs(err))),
+        "fit_ms": float(np.median(fit_ms)), "eval_ms": float(np.median(eval_ms)),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="scoping experiments on the 3-D Franke function")
+    ap.add_argument("--orders", default="4,8")
+    ap.add_argument("--taus", default="1e-6,1e-8,1e-10,1e-12")
+    ap.add_argument("--sizes", default="4,5,6,7", help="grid sizes as powers of 8")
+    ap.add_argument("--depth", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=6000)
+    args = ap.parse_args(argv)
+    import torch
+    if not torch.cuda.is_available():
+        print("scoping: needs a GPU", file=sys.stderr)
+        return 2
+    import paper_1511_01353_amd as fmt
+    import synthetic
+    fmt.load_library()
+    orders = [int(v) for v in args.orders.split(",")]
+    taus = [float(v) for v in args.taus.split(",")]
+    sizes = [8 ** int(v) for v in args.sizes.split(",")]
+    rows = []
+    for k, n in enumerate(sizes):
+        for p in orders:
+            pr = synthetic.scoping_problem(n, p, taus[0], args.seed + k, depth=args.depth)
+            for tau in taus:
+                r = run_case(fmt, torch, pr, tau, args.depth)
+                rows.append(r)
+                print(json.dumps(r), flush=True)
+    best = min(rows, key=lambda r: r["E_rms"])
+    compact = [r for r in rows if r["nodes"] < 1000]
+    best_compact = min(compact, key=lambda r: r["E_rms"]) if compact else None
+    print(json.dumps({"summary": {"cases": len(rows), "best_E_rms": best,
+                                  "best_E_rms_below_1000_nodes": best_compact}}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

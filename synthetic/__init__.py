@@ -142,6 +142,15 @@ def _make(name, x, y, z, fun, p, tol, depth, q=None, dtype=np.float64):
     return pr
 
 
+def scoping_problem(n: int, p: int, tol: float, seed: int, depth: int = 10) -> Problem:
+    """The paper's scoping workload (Section 4): the 3-D Franke function on n
+    uniform random points in [0,1]^3 (float64), evaluated on a separate random
+    grid of the same size."""
+    x, y, z = uniform_points(n, seed, np.float64)
+    q = uniform_points(n, seed + 700, np.float64)
+    return _make(f"scoping(n={n},p={p},tol={tol})", x, y, z, franke3d, p, tol, depth, q, np.float64)
+
+
 def config1(seed: int = 1000) -> Problem:
     """N=4096 uniform, 4 bumps, p=4, uniform depth 3 (tol 0), 8192 queries, float64."""
     b = draw_bumps(seed + 500)
