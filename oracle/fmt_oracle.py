@@ -35,6 +35,11 @@ What is computed (all arithmetic IEEE float64; float32 inputs promoted exactly):
   octant at depth d+1 is the three bits (x highest) of the cells at that depth.
   A point on a split plane goes to the upper octant; a point at x = hi goes to
   the last cell.
+* Fixed-topology transform (the operator I' of Section 3 with the node set
+  held fixed): for new values f on the same points, Alg. 2 at every node of an
+  existing tree, parents before children, each node fitting the residual its
+  ancestors left; no octant test is taken, so the map f -> coefficients is
+  linear.
 * Evaluation (the practical form f'_q = Lambda'_q F_p of Section 2, summed over
   the tree as the residual decomposition implies): for a query, walk from the
   root down while the node holding the query's cell exists, adding each node's
@@ -52,7 +57,7 @@ import scipy.linalg
 __all__ = [
     "rank_stride", "basis_size", "exponents", "moments",
     "quantise", "morton", "node_frame", "mesh_to_moments",
-    "Tree", "fit", "evaluate", "rms", "max_abs",
+    "Tree", "fit", "fit_fixed", "evaluate", "rms", "max_abs",
 ]
 
 EPS = np.finfo(np.float64).eps
@@ -283,6 +288,41 @@ def fit(x, y, z, f, p: int, tol: float, max_depth: int,
     return Tree(p=p, tol=float(tol), max_depth=D, lo=lo, hi=hi, level=level, prefix=prefix,
                 begin=begin, count=count, coeffs=coeffs, rank_deficient=rdef, margin=margin,
                 keys=keys, order=order, residual=r, leaf=leaf, decisions=decisions)
+
+
+def fit_fixed(tree: Tree, x, y, z, f) -> Tree:
+    """Alg. 2 at every node of `tree` for new values f on the tree's points.
+
+    The node set, point ranges and frames are the tree's; nodes are taken in
+    (level, prefix) order, so every node fits the residual left by all of its
+    ancestors (siblings hold disjoint points, so this is the order Alg. 1's
+    recursion produces for each node).  Returns a tree with the same topology
+    and the new coefficients, rank flags and final residual.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    D = tree.max_depth
+    if x.shape[0] != tree.keys.shape[0] or f.shape[0] != x.shape[0]:
+        raise ValueError("the values must live on the tree's points")
+    qx, qy, qz = _cells(x, y, z, tree.lo, tree.hi, D)
+    if not np.array_equal(morton(qx, qy, qz, D), tree.keys):
+        raise ValueError("the points differ from the tree's points")
+    r = f.copy()
+    coeffs = np.zeros_like(tree.coeffs)
+    rdef = np.zeros(tree.nodes, dtype=bool)
+    for i in range(tree.nodes):
+        d = int(tree.level[i])
+        idx = tree.order[tree.begin[i]:tree.begin[i] + tree.count[i]]
+        c, s = node_frame(d, _prefix_cell(int(tree.prefix[i]), d), tree.lo, tree.hi)
+        u = (x[idx] - c[0]) * s[0]
+        v = (y[idx] - c[1]) * s[1]
+        w = (z[idx] - c[2]) * s[2]
+        F, rdef[i] = mesh_to_moments(u, v, w, r[idx], tree.p)
+        r[idx] = residual_update(u, v, w, r[idx], F, tree.p)
+        coeffs[i] = F
+    return dataclasses.replace(tree, coeffs=coeffs, rank_deficient=rdef, residual=r, decisions=[])
 
 
 def evaluate(tree: Tree, qx, qy, qz) -> np.ndarray:

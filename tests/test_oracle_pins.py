@@ -458,6 +458,91 @@ def test_franke_error_falls_with_order():
 
 
 # ----------------------------------------------------------------------------
+# fixed-topology transform (the node set of a fitted tree, new values)
+# ----------------------------------------------------------------------------
+def _split_tree(seed=41):
+    pr = synthetic.small_problem(6000, 3, seed=seed, tol=1e-9, depth=3)
+    return pr, oracle.fit(pr.x, pr.y, pr.z, pr.f, pr.p, pr.tol, pr.max_depth)
+
+
+def pin_fixed_topology_reproduces_fit():
+    """Refitting the values a tree was built from walks the same nodes with the
+    same residuals as Alg. 1 did: identical coefficients and residual."""
+    pr, t = _split_tree()
+    assert t.nodes > 9
+    t2 = oracle.fit_fixed(t, pr.x, pr.y, pr.z, pr.f)
+    np.testing.assert_array_equal(t2.coeffs, t.coeffs)
+    np.testing.assert_array_equal(t2.residual, t.residual)
+
+
+def test_fixed_topology_reproduces_fit():
+    pin_fixed_topology_reproduces_fit()
+
+
+def pin_fixed_topology_polynomial():
+    """A degree <= p field on a tree built from other values: the root takes
+    the node-frame Taylor coefficients, every other node ~0, the residual
+    vanishes, and the node set is kept although this field would not split."""
+    pr, t = _split_tree()
+    poly = random_poly(pr.p, 5)
+    f2 = poly_eval(poly, pr.x, pr.y, pr.z)
+    t2 = oracle.fit_fixed(t, pr.x, pr.y, pr.z, f2)
+    assert t2.nodes == t.nodes
+    for j, e in enumerate(oracle.exponents(pr.p)):
+        want = poly_derivative_at(poly, e, (0.5, 0.5, 0.5)) * 0.5 ** sum(e)
+        assert abs(t2.coeffs[0, j] - want) < 1e-11, (e, t2.coeffs[0, j], want)
+    assert np.max(np.abs(t2.coeffs[1:])) < 1e-10
+    assert oracle.max_abs(t2.residual) < 1e-12
+
+
+def test_fixed_topology_polynomial():
+    pin_fixed_topology_polynomial()
+
+
+def pin_fixed_topology_linear_and_orthogonal():
+    """The fixed-topology map is linear in the values, and at every leaf the
+    final residual of any field is orthogonal to the basis (Lambda^T r = 0)."""
+    pr, t = _split_tree()
+    rng = np.random.default_rng(7)
+    f1 = rng.standard_normal(pr.n)
+    f2 = np.sin(7 * pr.x) * pr.y
+    a = oracle.fit_fixed(t, pr.x, pr.y, pr.z, f1)
+    b = oracle.fit_fixed(t, pr.x, pr.y, pr.z, f2)
+    c = oracle.fit_fixed(t, pr.x, pr.y, pr.z, 2.0 * f1 - 3.0 * f2)
+    scale = np.max(np.abs(2.0 * a.coeffs)) + np.max(np.abs(3.0 * b.coeffs))
+    assert np.max(np.abs(c.coeffs - (2.0 * a.coeffs - 3.0 * b.coeffs))) < 1e-12 * scale
+    parents = {(int(l) - 1, int(pf) >> 3) for l, pf in zip(t.level, t.prefix) if l > 0}
+    leaves = 0
+    for i in range(t.nodes):
+        if (int(t.level[i]), int(t.prefix[i])) in parents:
+            continue
+        idx = t.order[t.begin[i]:t.begin[i] + t.count[i]]
+        cell = fo._prefix_cell(int(t.prefix[i]), int(t.level[i]))
+        cc, s = oracle.node_frame(int(t.level[i]), cell, t.lo, t.hi)
+        lam = oracle.moments((pr.x[idx] - cc[0]) * s[0], (pr.y[idx] - cc[1]) * s[1], (pr.z[idx] - cc[2]) * s[2],
+                             pr.p)
+        g = lam.T @ a.residual[idx]
+        # rounding is relative to the values the node's fits started from
+        assert np.max(np.abs(g)) <= 1e-11 * np.linalg.norm(lam) * np.linalg.norm(f1[idx])
+        leaves += 1
+    assert leaves >= 8
+
+
+def test_fixed_topology_linear_and_orthogonal():
+    pin_fixed_topology_linear_and_orthogonal()
+
+
+def test_fixed_topology_rejects_other_points():
+    pr, t = _split_tree()
+    x = pr.x.copy()
+    x[0] = 1.0 - x[0]
+    with pytest.raises(ValueError):
+        oracle.fit_fixed(t, x, pr.y, pr.z, pr.f)
+    with pytest.raises(ValueError):
+        oracle.fit_fixed(t, pr.x[:-1], pr.y[:-1], pr.z[:-1], pr.f[:-1])
+
+
+# ----------------------------------------------------------------------------
 # mutation tests: a planted mistake in the oracle must fail a pin
 # ----------------------------------------------------------------------------
 def _mutant_moments_no_factorial(u, v, w, p):
@@ -495,8 +580,17 @@ def _mutant_drop_last_block(u, v, w, r, p, block=fo.QR_BLOCK_ROWS):
     return _orig_mtm(u[:keep], v[:keep], w[:keep], r[:keep], p, block)
 
 
+def _mutant_fit_fixed_children_first(tree, x, y, z, f):
+    rev = np.arange(tree.nodes)[::-1]
+    t = fo.dataclasses.replace(tree, level=tree.level[rev], prefix=tree.prefix[rev], begin=tree.begin[rev],
+                               count=tree.count[rev], coeffs=tree.coeffs[rev])
+    out = _orig_fit_fixed(t, x, y, z, f)
+    return fo.dataclasses.replace(tree, coeffs=out.coeffs[rev], residual=out.residual)
+
+
 _orig_frame = fo.node_frame
 _orig_mtm = fo.mesh_to_moments
+_orig_fit_fixed = fo.fit_fixed
 
 MUTANTS = [
     ("moments", _mutant_moments_no_factorial),
@@ -506,11 +600,13 @@ MUTANTS = [
     ("node_frame", _mutant_frame_full_width),
     ("residual_update", _mutant_residual_sign),
     ("mesh_to_moments", _mutant_drop_last_block),
+    ("fit_fixed", _mutant_fit_fixed_children_first),
 ]
 
 PINS = [pin_basis_sizes, pin_graded_order, pin_moments_exact, pin_morton_matches_geometric,
         pin_exact_rational_ls, pin_polynomial_reproduction, pin_resolution_of_identity,
-        pin_projection_orthogonality, pin_monotone_residual, pin_mean_hierarchy]
+        pin_projection_orthogonality, pin_monotone_residual, pin_mean_hierarchy,
+        pin_fixed_topology_reproduces_fit, pin_fixed_topology_polynomial, pin_fixed_topology_linear_and_orthogonal]
 
 
 @pytest.mark.parametrize("name,mutant", MUTANTS, ids=[m[0] for m in MUTANTS])
