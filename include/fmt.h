@@ -46,6 +46,7 @@ extern "C" {
 #define FMT_MAX_P 8          /* largest supported total degree (calL = 165) */
 #define FMT_MAX_DEPTH 10     /* deepest supported level; keys use 3*D bits */
 #define FMT_MAX_LEVELS (FMT_MAX_DEPTH + 1)
+#define FMT_REFIT_MAX_FIELDS 4096   /* value fields one fmt_refit call takes */
 
 typedef enum {
   FMT_OK = 0,
@@ -217,6 +218,37 @@ fmt_status fmt_tree_export_points(const fmt_tree* tree, uint32_t* keys, uint32_t
 fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_t* level,
                            const uint32_t* prefix, const double* coeffs, void* stream,
                            fmt_tree** out);
+
+/*
+ * Fixed-topology transform: refit `m` new value fields on the points of a
+ * fitted tree, keeping its node set.  The map from values to coefficients is
+ * then linear (the operator I' of Section 2, eq. identityprime, applied
+ * through the tree's nodes): every node of the tree is fitted (Alg. 2) to the
+ * residual its ancestors leave of the new field, parents before children,
+ * and no octant test is taken.  The power moments and the factor of each
+ * node are formed once and shared by the m fields; each field then costs the
+ * r-weighted moments, one solve with the kept factor and the residual update
+ * per level.  Normal equations in float64 power moments, whatever path the
+ * tree was fitted with; the tree's refine_steps apply where the conditioning
+ * estimate asks for them (see fmt_fit_opts.refine_steps).
+ *   tree       : a tree from fmt_fit or fmt_fit_batch (not an imported one).
+ *   x, y, z    : device arrays of n values of `dtype`: the points the tree was
+ *                fitted on, in the same order (each point is checked against
+ *                the cell the tree recorded for it).
+ *   f          : device array of m * n values of `dtype`, field j at f + j n,
+ *                in the points' order.  Not modified.
+ *   n          : the tree's point count.
+ *   m          : 1 .. FMT_REFIT_MAX_FIELDS.
+ *   out        : host array of m handles, each a new single-problem tree with
+ *                the source tree's nodes (export order and prefixes equal),
+ *                its field's coefficients and final residual; release each
+ *                with fmt_tree_destroy.  The source tree is unchanged.
+ * Runs on `stream` and returns once the trees are complete.  Errors:
+ * INVALID_ARG (bad argument, an imported tree, n differs, a point differs
+ * from the tree's), OOM, NUMERIC, DEVICE.  On error every out[j] is NULL.
+ */
+fmt_status fmt_refit(const fmt_tree* tree, const void* x, const void* y, const void* z, const void* f,
+                     int64_t n, int m, int dtype, void* stream, fmt_tree** out);
 
 /*
  * Kernel timing (a profiling aid, not part of the method).  While enabled,

@@ -56,9 +56,11 @@ struct ProfRecord {
 };
 const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce", "solve", "refine_sweep",
                               "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval", "compose",
-                              "bmoments", "base_moments", "pyramid"};
+                              "bmoments", "base_moments", "pyramid", "refit_gather", "refit_moments",
+                              "refit_factor", "refit_bmoments", "refit_solve", "refit_residual"};
 enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
-       KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_BMOM, KN_BASEM, KN_PYR, KN_COUNT };
+       KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_BMOM, KN_BASEM, KN_PYR, KN_XGATHER, KN_XMOM, KN_XFACTOR,
+       KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_COUNT };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof_pending;
@@ -794,6 +796,60 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   return F;
 }
 
+// Node table of a single-problem forest from its nodes in (level, prefix)
+// order (level, prefix, first sorted point, count): parents, first children
+// and child masks from the (level, prefix) pairs, frames from the box, flags
+// cleared, level ranges and depth.  Coefficients are uploaded when hcoef is
+// given.  Fails on a duplicate node or a missing parent.  The uploads are
+// asynchronous on s from host vectors: the caller synchronises s before they
+// go out of scope.
+void build_single_nodes(Forest& F, const std::vector<uint32_t>& hl, const std::vector<uint32_t>& hp,
+                        const std::vector<uint32_t>& hb, const std::vector<uint32_t>& hc, const double* hcoef,
+                        const ProblemParams& prm, hipStream_t s) {
+  const uint32_t M = (uint32_t)hl.size();
+  std::map<std::pair<uint32_t, uint32_t>, uint32_t> pos;
+  for (uint32_t j = 0; j < M; ++j)
+    if (!pos.emplace(std::make_pair(hl[j], hp[j]), j).second) fail(FMT_E_INVALID_ARG, "duplicate node");
+  std::vector<uint32_t> hprob(M, 0), hpar(M), hfc(M, 0), hcm(M, 0), hf(M, 0);
+  for (uint32_t j = 0; j < M; ++j) {
+    if (hl[j] == 0) {
+      hpar[j] = j;
+      continue;
+    }
+    auto it = pos.find(std::make_pair(hl[j] - 1, hp[j] >> 3));
+    if (it == pos.end()) fail(FMT_E_INVALID_ARG, "a node's parent is missing");
+    const uint32_t par = it->second;
+    hpar[j] = par;
+    if (hcm[par] == 0) hfc[par] = j;
+    hcm[par] |= 1u << (hp[j] & 7u);
+  }
+  F.alloc_nodes(std::max<uint32_t>(M, 1));
+  F.nodes = M;
+  auto up = [&](DevBuf& b, const void* h, size_t bytes) {
+    if (bytes) HIPCHK(hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, s));
+  };
+  up(F.nb_begin, hb.data(), 4ull * M); up(F.nb_count, hc.data(), 4ull * M); up(F.nb_prefix, hp.data(), 4ull * M);
+  up(F.nb_level, hl.data(), 4ull * M); up(F.nb_problem, hprob.data(), 4ull * M);
+  up(F.nb_parent, hpar.data(), 4ull * M); up(F.nb_first_child, hfc.data(), 4ull * M);
+  up(F.nb_child_mask, hcm.data(), 4ull * M); up(F.nb_flags, hf.data(), 4ull * M);
+  if (hcoef) up(F.nb_coef, hcoef, 8ull * M * F.L);
+  DevBuf dprm(sizeof(ProblemParams));
+  up(dprm, &prm, sizeof(ProblemParams));
+  HIPCHK(launch_node_geo(F.table(), dprm.as<ProblemParams>(), M, s));
+  HIPCHK(hipStreamSynchronize(s));   // dprm and the host vectors above die here
+  // nodes are in level order: one range per level
+  F.level_start.clear();
+  F.level_count.clear();
+  for (uint32_t j = 0; j < M; ++j) {
+    if (j == 0 || hl[j] != hl[j - 1]) {
+      F.level_start.push_back(j);
+      F.level_count.push_back(0);
+    }
+    ++F.level_count.back();
+  }
+  F.depth_present = M ? (int)*std::max_element(hl.begin(), hl.end()) : 0;
+}
+
 fmt_status guard(const std::function<void()>& body) {
   try {
     body();
@@ -823,6 +879,191 @@ void ensure_tree_nodes(fmt_tree* t) {
   for (uint32_t i = 0; i < F.nodes; ++i)
     if ((int)F.h_problem[i] == t->problem) t->nodes.push_back(i);
   t->nodes_ready = true;
+}
+
+// Fixed-topology refit of m value fields on the points of tree t (see
+// fmt_refit).  Per level: the power moments M of every node once (mode 3),
+// its factor once, then per field the r-weighted moments B (mode 2), the
+// solve with the kept factor, the refinement sweeps where the conditioning
+// estimate asks for them, and the residual update.  Returns m single-problem
+// forests holding the tree's node set.
+std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, const void* y, const void* z,
+                                                   const void* f, int m, int dtype, hipStream_t s) {
+  Forest& S = *t.forest;
+  const ProblemInfo& P = S.probs[t.problem];
+  const uint32_t N = (uint32_t)P.n, off = P.prm.offset;
+  const int p = S.p;
+  const uint32_t L = (uint32_t)S.L;
+  const uint32_t M = (uint32_t)t.nodes.size();
+  std::vector<uint32_t> hl(M), hp(M), hb(M), hc(M);
+  for (uint32_t j = 0; j < M; ++j) {
+    const uint32_t i = t.nodes[j];
+    hl[j] = S.h_level[i];
+    hp[j] = S.h_prefix[i];
+    hb[j] = S.h_begin[i] - off;
+    hc[j] = S.h_count[i];
+  }
+  ProblemParams prm = P.prm;
+  prm.offset = 0;
+
+  std::vector<std::shared_ptr<Forest>> outs(m);
+  for (int j = 0; j < m; ++j) {
+    auto F = std::make_shared<Forest>();
+    F->p = p;
+    F->L = (int)L;
+    F->D = S.D;
+    F->path = FMT_PATH_FP64;
+    F->dtype = dtype;
+    F->refine = S.refine;
+    F->gram = FMT_GRAM_MOMENTS_LEVEL;
+    F->nprob = 1;
+    F->stream = s;
+    F->device = S.device;
+    F->ntot = N;
+    F->probs.resize(1);
+    F->probs[0].prm = prm;
+    F->probs[0].root = 0;
+    F->probs[0].n = P.n;
+    F->skey.alloc(4ull * N);
+    F->order.alloc(4ull * N);
+    F->resid.alloc(8ull * N);
+    outs[j] = F;
+  }
+  Forest& F0 = *outs[0];
+  build_single_nodes(F0, hl, hp, hb, hc, nullptr, prm, s);
+  const uint32_t kmask = 3 * S.D >= 32 ? 0xffffffffu : ((1u << (3 * S.D)) - 1u);
+  HIPCHK(launch_slice_points(S.skey.as<uint32_t>(), S.order.as<uint32_t>(), off, N, kmask, F0.skey.as<uint32_t>(),
+                             F0.order.as<uint32_t>(), s));
+  for (int j = 1; j < m; ++j) {
+    Forest& F = *outs[j];
+    F.alloc_nodes(std::max<uint32_t>(M, 1));
+    F.nodes = M;
+    F.level_start = F0.level_start;
+    F.level_count = F0.level_count;
+    F.depth_present = F0.depth_present;
+    auto cp = [&](DevBuf& dst, const DevBuf& src, size_t bytes) {
+      if (bytes) HIPCHK(hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyDeviceToDevice, s));
+    };
+    const size_t un = 4ull * M;
+    cp(F.nb_begin, F0.nb_begin, un); cp(F.nb_count, F0.nb_count, un); cp(F.nb_prefix, F0.nb_prefix, un);
+    cp(F.nb_level, F0.nb_level, un); cp(F.nb_problem, F0.nb_problem, un); cp(F.nb_parent, F0.nb_parent, un);
+    cp(F.nb_first_child, F0.nb_first_child, un); cp(F.nb_child_mask, F0.nb_child_mask, un);
+    cp(F.nb_geo, F0.nb_geo, 48ull * M);
+    cp(F.skey, F0.skey, 4ull * N);
+    cp(F.order, F0.order, 4ull * N);
+  }
+
+  // per level: first node, nodes, points and chunk offsets (concatenated)
+  const size_t nlev = F0.level_start.size();
+  std::vector<uint32_t> choff, cbase(nlev), nchk(nlev), lpts(nlev);
+  uint32_t max_chunks = 1, max_nodes = 1;
+  for (size_t d = 0; d < nlev; ++d) {
+    cbase[d] = (uint32_t)choff.size();
+    uint32_t run = 0, pts = 0;
+    for (uint32_t k = F0.level_start[d]; k < F0.level_start[d] + F0.level_count[d]; ++k) {
+      choff.push_back(run);
+      run += (hc[k] + CHUNK - 1) / CHUNK;
+      pts += hc[k];
+    }
+    choff.push_back(run);
+    nchk[d] = run;
+    lpts[d] = pts;
+    max_chunks = std::max(max_chunks, run);
+    max_nodes = std::max(max_nodes, F0.level_count[d]);
+  }
+  F0.level_points = lpts;
+
+  Workspace& W = workspace_for(s);
+  std::lock_guard<std::mutex> wlock(W.mu);
+  const size_t esz = dtype == FMT_F32 ? 4 : 8;
+  const uint32_t NMB = (uint32_t)moment_base_doubles(p);
+  for (DevBuf* b : {&W.px, &W.py, &W.pz}) b->reserve(esz * N);
+  W.partial.reserve(8ull * NMB * max_chunks);
+  W.part_b.reserve(8ull * L * max_chunks);
+  W.part_ss.reserve(8ull * 16 * max_chunks);
+  W.fac.reserve(8ull * factor_doubles(p) * max_nodes);
+  W.chunk_a.reserve(4ull * choff.size());
+  W.status.reserve(64);
+  char* stg = W.staging(4ull * choff.size());
+  std::memcpy(stg, choff.data(), 4ull * choff.size());
+  HIPCHK(hipMemcpyAsync(W.chunk_a.p, stg, 4ull * choff.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
+  {
+    ProfScope ps(KN_XGATHER, (double)N * (1 + m), s);
+    HIPCHK(launch_refit_gather(dtype, S.order.as<uint32_t>(), S.skey.as<uint32_t>(), off, N, x, y, z, P.prm, S.D,
+                               W.px.p, W.py.p, W.pz.p, W.status.as<uint32_t>(), s));
+    for (int j = 0; j < m; ++j)
+      HIPCHK(launch_gather_fields(dtype, S.order.as<uint32_t>(), off, N, (const char*)f + esz * N * (size_t)j, 1, 0,
+                                  outs[j]->resid.as<double>(), 0, s));
+  }
+
+  for (size_t d = 0; d < nlev; ++d) {
+    LevelArgs a{};
+    a.nt = F0.table();
+    a.node0 = F0.level_start[d];
+    a.nnodes = F0.level_count[d];
+    a.chunk_off = W.chunk_a.as<uint32_t>() + cbase[d];
+    a.nchunks = nchk[d];
+    a.px = W.px.p;
+    a.py = W.py.p;
+    a.pz = W.pz.p;
+    a.skey = F0.skey.as<uint32_t>();
+    a.level = (int)d;
+    a.D = S.D;
+    a.tol = 0.0;
+    // float64 moments: refinement where the conditioning estimate asks for it
+    a.refine = S.refine > 0 ? 1 : 0;
+    a.pyr_tab = nullptr;
+    const bool multi = a.nchunks > a.nnodes;
+    {
+      ProfScope ps(KN_XMOM, lpts[d], s);
+      HIPCHK(launch_moments(p, 3, dtype, a, W.partial.as<double>(), s));
+      if (multi) HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), NMB, s));
+    }
+    {
+      ProfScope ps(KN_XFACTOR, a.nnodes, s);
+      HIPCHK(launch_factor_moments(p, a, W.partial.as<double>(), W.fac.as<double>(), s));
+    }
+    for (int j = 0; j < m; ++j) {
+      LevelArgs b = a;
+      b.nt.coef = outs[j]->nb_coef.as<double>();
+      b.r = outs[j]->resid.as<double>();
+      {
+        ProfScope ps(KN_XBMOM, lpts[d], s);
+        HIPCHK(launch_moments(p, 2, dtype, b, W.part_b.as<double>(), s));
+        if (multi) HIPCHK(launch_chunk_reduce(b, W.part_b.as<double>(), L, s));
+      }
+      {
+        ProfScope ps(KN_XSOLVE, a.nnodes, s);
+        HIPCHK(launch_factor_solve(p, b, W.part_b.as<double>(), W.fac.as<double>(), s));
+      }
+      for (int it = 0; it < S.refine; ++it) {
+        {
+          ProfScope ps(KN_RSWEEP, lpts[d], s);
+          HIPCHK(launch_moments(p, 1, dtype, b, W.part_b.as<double>(), s));
+        }
+        ProfScope ps(KN_RSOLVE, a.nnodes, s);
+        HIPCHK(launch_refine_solve(p, b, W.part_b.as<double>(), W.fac.as<double>(), s));
+      }
+      {
+        ProfScope ps(KN_XRESID, lpts[d], s);
+        HIPCHK(launch_residual(p, dtype, b, W.part_ss.as<double>(), s));
+      }
+    }
+  }
+  // the rank and refinement flags belong to the node set: every field's tree
+  // gets the same ones, then its own non-finite marks
+  for (int j = 1; j < m; ++j) {
+    outs[j]->level_points = lpts;
+    if (M) HIPCHK(hipMemcpyAsync(outs[j]->nb_flags.p, F0.nb_flags.p, 4ull * M, hipMemcpyDeviceToDevice, s));
+  }
+  for (int j = 0; j < m; ++j) HIPCHK(launch_check_coef(p, outs[j]->table(), M, W.status.as<uint32_t>(), s));
+  HIPCHK(hipMemcpyAsync(W.host_counters + 4, W.status.p, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const uint32_t st = W.host_counters[4];
+  if (st & STATUS_MISMATCH) fail(FMT_E_INVALID_ARG, "the points differ from the points the tree was fitted on");
+  if (st & STATUS_NONFINITE) fail(FMT_E_NUMERIC, "a non-finite coefficient was produced");
+  return outs;
 }
 
 }  // namespace
@@ -1149,64 +1390,59 @@ fmt_status fmt_tree_import(const fmt_fit_opts* opts, int64_t nodes, const uint8_
     });
     if (level[idx[0]] != 0 || (nodes > 1 && level[idx[1]] == 0)) fail(FMT_E_INVALID_ARG, "exactly one root needed");
     const uint32_t M = (uint32_t)nodes;
-    std::map<std::pair<uint32_t, uint32_t>, uint32_t> pos;
-    for (uint32_t j = 0; j < M; ++j) {
-      auto key = std::make_pair((uint32_t)level[idx[j]], prefix[idx[j]]);
-      if (pos.count(key)) fail(FMT_E_INVALID_ARG, "duplicate node");
-      pos[key] = j;
-    }
-    std::vector<uint32_t> hb(M, 0), hc(M, 0), hp(M), hl(M), hprob(M, 0), hpar(M), hfc(M, 0), hcm(M, 0), hf(M, 0);
+    std::vector<uint32_t> hb(M, 0), hc(M, 0), hp(M), hl(M);
     std::vector<double> hcoef((size_t)M * L);
     for (uint32_t j = 0; j < M; ++j) {
       const int64_t i = idx[j];
       hp[j] = prefix[i];
       hl[j] = level[i];
       std::memcpy(hcoef.data() + (size_t)j * L, coeffs + i * L, sizeof(double) * L);
-      if (hl[j] == 0) {
-        hpar[j] = j;
-        continue;
-      }
-      auto it = pos.find(std::make_pair(hl[j] - 1, hp[j] >> 3));
-      if (it == pos.end()) fail(FMT_E_INVALID_ARG, "a node's parent is missing");
-      const uint32_t par = it->second;
-      hpar[j] = par;
-      if (hcm[par] == 0) hfc[par] = j;
-      hcm[par] |= 1u << (hp[j] & 7u);
     }
-    F->alloc_nodes(M);
-    F->nodes = M;
-    auto up = [&](DevBuf& b, const void* h, size_t bytes) {
-      HIPCHK(hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, s));
-    };
-    up(F->nb_begin, hb.data(), 4ull * M); up(F->nb_count, hc.data(), 4ull * M); up(F->nb_prefix, hp.data(), 4ull * M);
-    up(F->nb_level, hl.data(), 4ull * M); up(F->nb_problem, hprob.data(), 4ull * M);
-    up(F->nb_parent, hpar.data(), 4ull * M); up(F->nb_first_child, hfc.data(), 4ull * M);
-    up(F->nb_child_mask, hcm.data(), 4ull * M); up(F->nb_flags, hf.data(), 4ull * M);
-    up(F->nb_coef, hcoef.data(), 8ull * M * L);
     ProblemParams prm = make_params(*opts, 0, 0);
-    DevBuf dprm(sizeof(ProblemParams));
-    up(dprm, &prm, sizeof(ProblemParams));
-    HIPCHK(launch_node_geo(F->table(), dprm.as<ProblemParams>(), M, s));
+    build_single_nodes(*F, hl, hp, hb, hc, hcoef.data(), prm, s);
     HIPCHK(hipStreamSynchronize(s));
     F->probs.resize(1);
     F->probs[0].prm = prm;
     F->probs[0].root = 0;
     F->probs[0].n = 0;
-    // nodes are in level order: one range per level
-    F->level_start.clear();
-    F->level_count.clear();
-    for (uint32_t j = 0; j < M; ++j) {
-      if (j == 0 || hl[j] != hl[j - 1]) {
-        F->level_start.push_back(j);
-        F->level_count.push_back(0);
-      }
-      ++F->level_count.back();
-    }
-    F->depth_present = (int)*std::max_element(hl.begin(), hl.end());
     fmt_tree* t = new fmt_tree();
     t->forest = F;
     t->problem = 0;
     *out = t;
+  });
+}
+
+fmt_status fmt_refit(const fmt_tree* tree, const void* x, const void* y, const void* z, const void* f, int64_t n,
+                     int m, int dtype, void* stream, fmt_tree** out) {
+  if (out && m > 0 && m <= FMT_REFIT_MAX_FIELDS)
+    for (int j = 0; j < m; ++j) out[j] = nullptr;
+  return guard([&] {
+    if (!tree || !out) fail(FMT_E_INVALID_ARG, "NULL tree or out");
+    if (m < 1 || m > FMT_REFIT_MAX_FIELDS) fail(FMT_E_INVALID_ARG, "m out of range 1..FMT_REFIT_MAX_FIELDS");
+    if (dtype != FMT_F32 && dtype != FMT_F64) fail(FMT_E_INVALID_ARG, "dtype must be FMT_F32 or FMT_F64");
+    if (!x || !y || !z || !f) fail(FMT_E_INVALID_ARG, "NULL input pointer");
+    fmt_tree* t = const_cast<fmt_tree*>(tree);
+    ensure_tree_nodes(t);
+    const ProblemInfo& P = t->forest->probs[t->problem];
+    if (P.n == 0) fail(FMT_E_INVALID_ARG, "the tree holds no points (an imported tree)");
+    if (n != P.n) fail(FMT_E_INVALID_ARG, "n differs from the tree's point count");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (t->forest->device != dev) fail(FMT_E_INVALID_ARG, "the tree lives on another device");
+    auto outs = refit_forests(*t, x, y, z, f, m, dtype, (hipStream_t)stream);
+    std::vector<fmt_tree*> made;
+    try {
+      for (int j = 0; j < m; ++j) {
+        fmt_tree* h = new fmt_tree();
+        h->forest = outs[j];
+        h->problem = 0;
+        made.push_back(h);
+      }
+    } catch (...) {
+      for (auto* h : made) delete h;
+      throw;
+    }
+    for (int j = 0; j < m; ++j) out[j] = made[j];
   });
 }
 

@@ -110,6 +110,14 @@ hipError_t launch_pyr_base(const uint32_t* off, uint32_t ncell, const double* pa
 hipError_t launch_pyr_up(int p, double* pyr, const uint32_t* tab, const uint32_t* list, uint32_t nlist, int d,
                          hipStream_t s);
 hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s);
+// Factor only: the equilibrated normal equations of every node from the
+// mode-3 partials (chunks summed beforehand), factored into fac
+// (factor_doubles(p) per node of the level), with the condition estimate
+// (a.refine == 1) and the rank flags.  No coefficients are written.
+hipError_t launch_factor_moments(int p, const LevelArgs& a, const double* part_m, double* fac, hipStream_t s);
+// F = G^-1 Lambda^T r on every node from the mode-2 partials (chunks summed
+// beforehand) and the factors of launch_factor_moments.
+hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s);
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s);
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
                            uint32_t* nact, hipStream_t s);

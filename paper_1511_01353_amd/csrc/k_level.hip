@@ -303,7 +303,9 @@ __device__ __forceinline__ double probe_entry(int i, int which, int L) {
   return ((h >> 7) & 1u ? 1.0 : -1.0) * rsqrt((double)L);
 }
 
-template <int L>
+// With SOLVE false only the factor is made (no right-hand side): it is
+// always stored, and b, z may be null.
+template <int L, bool SOLVE = true>
 __device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dv, double* iv,
                                                    const double* sc, double (*xv)[L], double (*yv)[L],
                                                    const LevelArgs& a, uint32_t k, uint32_t node, double* fac) {
@@ -311,20 +313,22 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
   __shared__ int need_factor;   // the refinement sweeps will apply to this node
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const bool estimate = a.refine == 1;
-  if (tid == 0) need_factor = a.refine == 2;
+  if (tid == 0) need_factor = !SOLVE || a.refine == 2;
   if (estimate)
     for (int e = tid; e < 2 * L; e += 256) xv[e / L][e % L] = probe_entry(e % L, e / L, L);
   ldl_blocked<L>(A, dv, iv);
   // wave 0 solves for the coefficients; waves 1 and 2 meanwhile apply the
   // inverse to the two probe vectors (|G^-1 x| <= 1 / lambda_min, close to
   // it for all but exceptional x), a condition estimate at no extra latency
-  if (w == 0) tri_solve_wave<L>(A, iv, b, z);
-  else if (estimate && w <= 2) tri_solve_wave<L>(A, iv, xv[w - 1], yv[w - 1]);
+  if (w == 0) {
+    if constexpr (SOLVE) tri_solve_wave<L>(A, iv, b, z);
+  } else if (estimate && w <= 2) {
+    tri_solve_wave<L>(A, iv, xv[w - 1], yv[w - 1]);
+  }
   __syncthreads();
-  double* F = a.nt.coef + (size_t)node * L;
   bool deflated = false;
   for (int i = tid; i < L; i += 256) {
-    F[i] = sc[i] * z[i];
+    if constexpr (SOLVE) a.nt.coef[(size_t)node * L + i] = sc[i] * z[i];
     if (iv[i] == 0.0) deflated = true;
   }
   if (estimate && (w == 1 || w == 2)) {
@@ -417,6 +421,63 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a, k, node, fac);
 }
 
+// Equilibrated normal equations from power moments in LDS: mom[0 .. NM) the
+// power moments M (graded order up to degree 2p); with bm, the r-weighted
+// moments B (calL of them) give the scaled right-hand side b.  Fills the
+// exponent table ex, the scales sc (1 / sqrt(G_ii)) and weights wv
+// (sc / alpha!), then the blocked matrix A_ik = M[alpha_i + alpha_k] w_i w_k
+// in storage order (padding = identity, zero row cleared).  All 256 threads;
+// the workgroup's stores of mom (and bm) before the call are published by
+// the first barrier inside; the caller synchronises before reading A.
+template <int P>
+__device__ __forceinline__ void assemble_moments(double* A, const double* mom, const double* bm, double* b,
+                                                 double* sc, double* wv, int (*ex)[3]) {
+  constexpr int L = basis_size(P);
+  constexpr Basis<P> B{};
+  using S = BlockShape<L>;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < L; i += 256) {
+    ex[i][0] = B.lx[i];
+    ex[i][1] = B.ly[i];
+    ex[i][2] = B.lz[i];
+  }
+  __syncthreads();
+  for (int i = tid; i < L; i += 256) {
+    const double f = B.inv_fact[i];
+    const double gii = mom[graded(2 * ex[i][0], 2 * ex[i][1], 2 * ex[i][2])] * f * f;
+    const double s = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+    sc[i] = s;
+    wv[i] = s * f;
+    if (bm) b[i] = bm[i] * s * f;
+  }
+  __syncthreads();
+  // storage-order fill (as assemble_blocked) with this thread's row and
+  // column exponents (packed a | b << 8 | c << 16) and weights in registers
+  const int r = tid >> 4, c = (tid & 15) ^ (r >> 1);
+  uint32_t er[S::T], ec[S::T];
+  double wr[S::T], wc[S::T];
+#pragma unroll
+  for (int I = 0; I < S::T; ++I) {
+    const int i = 16 * I + r, q = 16 * I + c;
+    er[I] = i < L ? (uint32_t)ex[i][0] | ((uint32_t)ex[i][1] << 8) | ((uint32_t)ex[i][2] << 16) : 0u;
+    ec[I] = q < L ? (uint32_t)ex[q][0] | ((uint32_t)ex[q][1] << 8) | ((uint32_t)ex[q][2] << 16) : 0u;
+    wr[I] = i < L ? wv[i] : 0.0;
+    wc[I] = q < L ? wv[q] : 0.0;
+  }
+#pragma unroll
+  for (int I = 0; I < S::T; ++I) {
+    const int i = 16 * I + r;
+#pragma unroll
+    for (int J = 0; J <= I; ++J) {
+      const int q = 16 * J + c;
+      const uint32_t e = er[I] + ec[J];
+      const double m = mom[graded((int)(e & 255u), (int)((e >> 8) & 255u), (int)(e >> 16))];
+      A[bidx(I, J) + tid] = (i < L && q < L) ? m * wr[I] * wc[J] : (i == q ? 1.0 : 0.0);
+    }
+  }
+  if (tid < 16) A[S::WORDS + tid] = 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // K6 from power moments: G_ik = M[alpha_i + alpha_k] / (alpha_i! alpha_k!),
 // b_i = B[alpha_i] / alpha_i!.  Equilibration is folded into the assembly:
@@ -433,7 +494,6 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   constexpr int L = basis_size(P);
   constexpr int NM = basis_size(2 * P);
   constexpr int NOUT = NM + L + 1;
-  constexpr Basis<P> B{};
   using S = BlockShape<L>;
   __shared__ double A[S::WORDS + 16];   // + the zero row
   __shared__ double mom[NOUT > 4 * L ? NOUT : 4 * L];
@@ -468,50 +528,36 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   } else {
     copy_to_lds<256, NM + L>(mom, part_m + (size_t)c0 * NOUT, tid);
   }
-  for (int i = tid; i < L; i += 256) {
-    ex[i][0] = B.lx[i];
-    ex[i][1] = B.ly[i];
-    ex[i][2] = B.lz[i];
-  }
-  __syncthreads();
-  for (int i = tid; i < L; i += 256) {
-    const double f = B.inv_fact[i];
-    const double gii = mom[graded(2 * ex[i][0], 2 * ex[i][1], 2 * ex[i][2])] * f * f;
-    const double s = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
-    sc[i] = s;
-    wv[i] = s * f;
-    b[i] = mom[NM + i] * s * f;
-  }
-  __syncthreads();
-  {
-    // storage-order fill (as assemble_blocked) with this thread's row and
-    // column exponents (packed a | b << 8 | c << 16) and weights in registers
-    const int r = tid >> 4, c = (tid & 15) ^ (r >> 1);
-    uint32_t er[S::T], ec[S::T];
-    double wr[S::T], wc[S::T];
-#pragma unroll
-    for (int I = 0; I < S::T; ++I) {
-      const int i = 16 * I + r, q = 16 * I + c;
-      er[I] = i < L ? (uint32_t)ex[i][0] | ((uint32_t)ex[i][1] << 8) | ((uint32_t)ex[i][2] << 16) : 0u;
-      ec[I] = q < L ? (uint32_t)ex[q][0] | ((uint32_t)ex[q][1] << 8) | ((uint32_t)ex[q][2] << 16) : 0u;
-      wr[I] = i < L ? wv[i] : 0.0;
-      wc[I] = q < L ? wv[q] : 0.0;
-    }
-#pragma unroll
-    for (int I = 0; I < S::T; ++I) {
-      const int i = 16 * I + r;
-#pragma unroll
-      for (int J = 0; J <= I; ++J) {
-        const int q = 16 * J + c;
-        const uint32_t e = er[I] + ec[J];
-        const double m = mom[graded((int)(e & 255u), (int)((e >> 8) & 255u), (int)(e >> 16))];
-        A[bidx(I, J) + tid] = (i < L && q < L) ? m * wr[I] * wc[J] : (i == q ? 1.0 : 0.0);
-      }
-    }
-    if (tid < 16) A[S::WORDS + tid] = 0.0;
-  }
+  assemble_moments<P>(A, mom, mom + NM, b, sc, wv, ex);
   __syncthreads();
   factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a, k, node, fac);
+}
+
+// ---------------------------------------------------------------------------
+// Factor only, from the mode-3 partials (M alone): the same equilibrated
+// matrix as k_solve_m, factored and stored for every node, with the
+// condition estimate and flags.  One workgroup per node; used where several
+// right-hand sides share one node set (the fixed-topology transform).
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256) k_factor_m(LevelArgs a, const double* __restrict__ part_m,
+                                                  double* __restrict__ fac) {
+  constexpr int L = basis_size(P);
+  constexpr int NM = basis_size(2 * P);
+  using S = BlockShape<L>;
+  __shared__ double A[S::WORDS + 16];   // + the zero row
+  __shared__ double mom[NM > 4 * L ? NM : 4 * L];
+  __shared__ double dv[S::LP], iv[S::LP], sc[L], wv[L];
+  __shared__ int ex[L][3];
+  double(*xv)[L] = reinterpret_cast<double(*)[L]>(mom);
+  double(*yv)[L] = reinterpret_cast<double(*)[L]>(mom + 2 * L);
+  const int tid = threadIdx.x;
+  const uint32_t k = blockIdx.x;
+  const uint32_t node = a.node0 + k;
+  copy_to_lds<256, NM>(mom, part_m + (size_t)a.chunk_off[k] * NM, tid);
+  assemble_moments<P>(A, mom, nullptr, nullptr, sc, wv, ex);
+  __syncthreads();
+  factor_solve_store<L, false>(A, nullptr, nullptr, dv, iv, sc, xv, yv, a, k, node, fac);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,9 +566,13 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
 // sums its node's chunks, takes delta = G^{-1} Lambda^T r' with the kept
 // factor and sets F += delta.
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double* __restrict__ part_b,
-                                                      const double* __restrict__ fac) {
+// The solve with a kept factor, shared by the refinement (FIRST false:
+// F += delta on the flagged nodes) and by the first solve of a right-hand
+// side against factors made beforehand (FIRST true: F = G^-1 Lambda^T r on
+// every node, chunk partials summed beforehand).
+template <int P, bool FIRST>
+__device__ __forceinline__ void solve_with_factor(const LevelArgs& a, const double* __restrict__ part_b,
+                                                  const double* __restrict__ fac) {
   constexpr int L = basis_size(P);
   constexpr Basis<P> B{};
   using S = BlockShape<L>;
@@ -531,10 +581,10 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
-  if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
+  if (!FIRST && !(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: no refinement here
   // with a.refine == 2 (every node refined) the chunk partials were summed
   // into the first chunk's slot beforehand; otherwise they are summed here
-  const uint32_t c0 = a.chunk_off[k], c1 = a.refine == 2 ? c0 + 1 : a.chunk_off[k + 1];
+  const uint32_t c0 = a.chunk_off[k], c1 = (FIRST || a.refine == 2) ? c0 + 1 : a.chunk_off[k + 1];
   const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
   copy_to_lds<256, S::WORDS>(A, fo, tid);
   if (tid < 16) A[S::WORDS + tid] = 0.0;
@@ -566,7 +616,19 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
   __syncthreads();
   double* F = a.nt.coef + (size_t)node * L;
-  for (int i = tid; i < L; i += 256) F[i] += sc[i] * z[i];
+  for (int i = tid; i < L; i += 256) F[i] = FIRST ? sc[i] * z[i] : F[i] + sc[i] * z[i];
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double* __restrict__ part_b,
+                                                      const double* __restrict__ fac) {
+  solve_with_factor<P, false>(a, part_b, fac);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_factor_solve(LevelArgs a, const double* __restrict__ part_b,
+                                                      const double* __restrict__ fac) {
+  solve_with_factor<P, true>(a, part_b, fac);
 }
 
 // ---------------------------------------------------------------------------
@@ -888,6 +950,26 @@ static hipError_t rsolve_impl(const LevelArgs& a, const double* part_b, const do
 }
 hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
   FMT_DISPATCH_P(p, rsolve_impl, a, part_b, fac, s);
+}
+
+template <int P>
+static hipError_t factor_m_impl(const LevelArgs& a, const double* part_m, double* fac, hipStream_t s) {
+  if (a.nnodes == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_factor_m<P>, dim3(a.nnodes), dim3(256), 0, s, a, part_m, fac);
+  return hipGetLastError();
+}
+hipError_t launch_factor_moments(int p, const LevelArgs& a, const double* part_m, double* fac, hipStream_t s) {
+  FMT_DISPATCH_P(p, factor_m_impl, a, part_m, fac, s);
+}
+
+template <int P>
+static hipError_t fsolve_impl(const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
+  if (a.nnodes == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_factor_solve<P>, dim3(a.nnodes), dim3(256), 0, s, a, part_b, fac);
+  return hipGetLastError();
+}
+hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
+  FMT_DISPATCH_P(p, fsolve_impl, a, part_b, fac, s);
 }
 
 template <int P>

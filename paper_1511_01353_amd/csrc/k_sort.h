@@ -20,6 +20,7 @@ struct PayloadSet {
 
 constexpr uint32_t STATUS_DOMAIN = 1u;
 constexpr uint32_t STATUS_NONFINITE = 2u;
+constexpr uint32_t STATUS_MISMATCH = 4u;   // a point is not the one the tree recorded
 
 // cat: if cat.x is set, the inputs are also copied there, concatenated in
 // global point order (x, y, z, f).
@@ -47,5 +48,24 @@ hipError_t radix_sort_payload(int dtype, int np, uint32_t* keys, uint32_t* vals,
                               uint32_t n, int bits, uint32_t* scratch, hipStream_t s, bool* result_in_alt);
 // r[i] = (double)f[i]
 hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, hipStream_t s);
+
+// The points of one problem of a fitted forest in its key order, for a
+// fixed-topology refit: px[i] = x[order[off + i] - off] (likewise y, z) for
+// i < n, with the cell key of each gathered point (problem box P, depth
+// `depth`) checked against skey[off + i] (its low 3 depth bits); a point
+// outside the box, a differing key or a permutation entry out of range sets
+// STATUS_MISMATCH.
+hipError_t launch_refit_gather(int dtype, const uint32_t* order, const uint32_t* skey, uint32_t off, uint32_t n,
+                               const void* x, const void* y, const void* z, const ProblemParams& P, int depth,
+                               void* px, void* py, void* pz, uint32_t* status, hipStream_t s);
+// m value fields in key order, widened: r[j rstride + i] =
+// f[j fstride + order[off + i] - off] for j < m, i < n (entries whose
+// permutation value is out of range are left unwritten).
+hipError_t launch_gather_fields(int dtype, const uint32_t* order, uint32_t off, uint32_t n, const void* f, int m,
+                                uint64_t fstride, double* r, uint64_t rstride, hipStream_t s);
+// One problem's keys and permutation as a single-problem forest holds them:
+// okey[i] = skey[off + i] & kmask, oorder[i] = order[off + i] - off.
+hipError_t launch_slice_points(const uint32_t* skey, const uint32_t* order, uint32_t off, uint32_t n, uint32_t kmask,
+                               uint32_t* okey, uint32_t* oorder, hipStream_t s);
 
 }  // namespace fmt

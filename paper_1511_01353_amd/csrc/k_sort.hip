@@ -569,5 +569,88 @@ hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, hipStre
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_refit_gather(const uint32_t* __restrict__ order,
+                                                      const uint32_t* __restrict__ skey, uint32_t off, uint32_t n,
+                                                      const T* __restrict__ x, const T* __restrict__ y,
+                                                      const T* __restrict__ z, ProblemParams P, int depth,
+                                                      T* __restrict__ px, T* __restrict__ py, T* __restrict__ pz,
+                                                      uint32_t* status) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t j = order[off + i] - off;
+  if (j >= n) {
+    atomicOr(status, STATUS_MISMATCH);
+    return;
+  }
+  const T vx = x[j], vy = y[j], vz = z[j];
+  px[i] = vx;
+  py[i] = vy;
+  pz[i] = vz;
+  const double dx = (double)vx, dy = (double)vy, dz = (double)vz;
+  bool bad = !(dx >= P.lo[0] && dx <= P.hi[0] && dy >= P.lo[1] && dy <= P.hi[1] && dz >= P.lo[2] && dz <= P.hi[2]);
+  const uint32_t cmax = (1u << depth) - 1u;
+  const uint32_t key = (spread3(cell_of(dx, P.lo[0], P.qscale[0], cmax, &bad)) << 2) |
+                       (spread3(cell_of(dy, P.lo[1], P.qscale[1], cmax, &bad)) << 1) |
+                       spread3(cell_of(dz, P.lo[2], P.qscale[2], cmax, &bad));
+  const uint32_t kmask = depth > 0 ? (1u << (3 * depth)) - 1u : 0u;
+  if (bad || key != (skey[off + i] & kmask)) atomicOr(status, STATUS_MISMATCH);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_fields(const uint32_t* __restrict__ order, uint32_t off, uint32_t n,
+                                                       const T* __restrict__ f, uint64_t fstride,
+                                                       double* __restrict__ r, uint64_t rstride) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t j = order[off + i] - off;
+  if (j < n) r[(uint64_t)blockIdx.y * rstride + i] = (double)f[(uint64_t)blockIdx.y * fstride + j];
+}
+
+__global__ void __launch_bounds__(256) k_slice_points(const uint32_t* __restrict__ skey,
+                                                      const uint32_t* __restrict__ order, uint32_t off, uint32_t n,
+                                                      uint32_t kmask, uint32_t* __restrict__ okey,
+                                                      uint32_t* __restrict__ oorder) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  okey[i] = skey[off + i] & kmask;
+  oorder[i] = order[off + i] - off;
+}
+
+hipError_t launch_refit_gather(int dtype, const uint32_t* order, const uint32_t* skey, uint32_t off, uint32_t n,
+                               const void* x, const void* y, const void* z, const ProblemParams& P, int depth,
+                               void* px, void* py, void* pz, uint32_t* status, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == FMT_F32)
+    hipLaunchKernelGGL(k_refit_gather<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, order, skey, off, n,
+                       (const float*)x, (const float*)y, (const float*)z, P, depth, (float*)px, (float*)py,
+                       (float*)pz, status);
+  else
+    hipLaunchKernelGGL(k_refit_gather<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, order, skey, off, n,
+                       (const double*)x, (const double*)y, (const double*)z, P, depth, (double*)px, (double*)py,
+                       (double*)pz, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_fields(int dtype, const uint32_t* order, uint32_t off, uint32_t n, const void* f, int m,
+                                uint64_t fstride, double* r, uint64_t rstride, hipStream_t s) {
+  if (n == 0 || m <= 0) return hipSuccess;
+  const dim3 grid(blocks_for(n, 256), (unsigned)m);
+  if (dtype == FMT_F32)
+    hipLaunchKernelGGL(k_gather_fields<float>, grid, dim3(256), 0, s, order, off, n, (const float*)f, fstride, r,
+                       rstride);
+  else
+    hipLaunchKernelGGL(k_gather_fields<double>, grid, dim3(256), 0, s, order, off, n, (const double*)f, fstride, r,
+                       rstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_points(const uint32_t* skey, const uint32_t* order, uint32_t off, uint32_t n, uint32_t kmask,
+                               uint32_t* okey, uint32_t* oorder, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_points, dim3(blocks_for(n, 256)), dim3(256), 0, s, skey, order, off, n, kmask, okey,
+                     oorder);
+  return hipGetLastError();
+}
 
 }  // namespace fmt

@@ -38,10 +38,11 @@ FMT_GRAM_MOMENTS_LEVEL = 2
 FMT_MAX_P = 8
 FMT_MAX_DEPTH = 10
 FMT_MAX_LEVELS = FMT_MAX_DEPTH + 1
+FMT_REFIT_MAX_FIELDS = 4096
 
 EXPORTED = [
     "fmt_default_opts", "fmt_fit", "fmt_fit_batch", "fmt_eval", "fmt_tree_wait", "fmt_tree_get_info",
-    "fmt_tree_export_nodes", "fmt_tree_export_points", "fmt_tree_import", "fmt_tree_destroy",
+    "fmt_tree_export_nodes", "fmt_tree_export_points", "fmt_tree_import", "fmt_refit", "fmt_tree_destroy",
     "fmt_last_error", "fmt_version", "fmt_profile_enable", "fmt_profile_reset", "fmt_profile_read",
 ]
 
@@ -100,6 +101,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fmt_tree_import.argtypes = [POINTER(fmt_fit_opts), c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                     POINTER(T)]
     lib.fmt_tree_import.restype = c_int
+    lib.fmt_refit.argtypes = [T, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int, c_int, c_void_p,
+                              POINTER(c_void_p)]
+    lib.fmt_refit.restype = c_int
     lib.fmt_tree_destroy.argtypes = [T]
     lib.fmt_tree_destroy.restype = None
     lib.fmt_last_error.argtypes = []
@@ -257,6 +261,24 @@ def fmt_tree_import(opts: fmt_fit_opts, level, prefix, coeffs, stream=None) -> "
     _check(load_library().fmt_tree_import(ctypes.byref(opts), level.shape[0], _hptr(level), _hptr(prefix),
                                           _hptr(coeffs), _stream(stream), ctypes.byref(h)))
     return Tree(h, opts, 0)
+
+
+def fmt_refit(tree: "Tree", x, y, z, f, stream=None) -> list:
+    """f: (n,) or (m, n) contiguous device tensor of values on the tree's points;
+    returns m new trees (the tree's node set, the fields' coefficients)."""
+    n = x.numel()
+    if not (y.numel() == z.numel() == n):
+        raise ValueError("x, y, z must have the same length")
+    m = 1 if f.dim() == 1 else f.shape[0]
+    if f.numel() != m * n:
+        raise ValueError("f must hold m fields of n values")
+    dt = _dtype_code(x)
+    if not (_dtype_code(y) == _dtype_code(z) == _dtype_code(f) == dt):
+        raise ValueError("x, y, z, f must share one dtype")
+    out = (c_void_p * max(m, 1))()
+    _check(load_library().fmt_refit(tree.handle, _dptr(x), _dptr(y), _dptr(z), _dptr(f), n, m, dt,
+                                    _stream(stream), out))
+    return [Tree(c_void_p(out[j]), tree.opts, n) for j in range(m)]
 
 
 def fmt_tree_destroy(tree: "Tree"):

@@ -19,8 +19,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("fmt_fit", "fmt_fit_batch", "fmt_eval", "fmt_tree_wait", "fmt_tree_get_info",
-              "fmt_tree_export_nodes", "fmt_tree_export_points", "fmt_tree_import", "fmt_tree_destroy",
-              "fmt_last_error"):
+              "fmt_tree_export_nodes", "fmt_tree_export_points", "fmt_tree_import", "fmt_refit",
+              "fmt_tree_destroy", "fmt_last_error"):
         assert n in names
 
 
@@ -57,4 +57,7 @@ def test_host_side_calls_without_gpu():
     assert lib.fmt_fit(ctypes.byref(bad), None, None, None, None, 100, 0, None, ctypes.byref(h)) == m.FMT_E_INVALID_ARG
     ok = m.fmt_default_opts()
     assert lib.fmt_fit(ctypes.byref(ok), None, None, None, None, 100, 7, None, ctypes.byref(h)) == m.FMT_E_INVALID_ARG
+    out = (ctypes.c_void_p * 2)()
+    assert lib.fmt_refit(None, None, None, None, None, 100, 2, 0, None, out) == m.FMT_E_INVALID_ARG
+    assert not out[0] and not out[1]
     lib.fmt_tree_destroy(None)
