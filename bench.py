@@ -132,6 +132,77 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
     return out
 
 
+def refit_rooflines(kern: dict, p: int, L: int, coord_bytes: int, steps: int):
+    """Rooflines of the fixed-topology refit's kernel classes (same definition
+    as kernel_rooflines: algorithmic work over summed launch durations)."""
+    out = {}
+    def add(name, bound, per_unit, unit, peak):
+        st = kern.get(name)
+        if not st or st["ms_per_step"] <= 0:
+            return
+        sec = st["ms_per_step"] * steps / 1e3
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        ach = st["units"] * per_unit / sec / scale
+        out[name] = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak,
+                         avg_launch_ms=st["avg_launch_ms"], work_per_unit=per_unit,
+                         units_per_step=st["units"] / steps, traffic=None)
+    # power moments M once per level (mode 3), the factor once per node
+    add("refit_moments", "alu", base_moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("refit_factor", "alu", L ** 3 / 3.0, "TFLOP/s", PEAK_TFLOPS["fp64"])
+    # per field: B (mode 2), two triangular solves, the residual update
+    add("refit_bmoments", "alu", bmoment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("refit_solve", "alu", 2.0 * L * L, "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("refit_residual", "hbm", 3 * coord_bytes + 8 + 8 + 4, "GB/s", PEAK_HBM_GBS)
+    return out
+
+
+def refit_leg(fmt, tree_opts, X, Y, Z, pr, m: int, steps: int, warmup: int):
+    """Fixed-topology refit of m new fields on the headline tree: wall time
+    per call (inputs resident, the call returns with the trees complete) and
+    per-kernel launch durations in a second, profiled pass."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    fields = np.stack([synthetic.bumps_value(synthetic.draw_bumps(900 + j), pr.x, pr.y, pr.z).astype(pr.x.dtype)
+                       for j in range(m)])
+    FF = torch.from_numpy(fields).cuda()
+    tree = fmt.fmt_fit(tree_opts, X, Y, Z, torch.from_numpy(np.ascontiguousarray(pr.f)).cuda())
+    for _ in range(warmup):
+        for t in fmt.fmt_refit(tree, X, Y, Z, FF):
+            t.close()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        outs = fmt.fmt_refit(tree, X, Y, Z, FF)
+        times.append(time.perf_counter() - t0)
+        for t in outs:
+            t.close()
+    fmt.fmt_profile_reset()
+    fmt.fmt_profile_enable(True)
+    for _ in range(steps):
+        for t in fmt.fmt_refit(tree, X, Y, Z, FF):
+            t.close()
+    torch.cuda.synchronize()
+    fmt.fmt_profile_enable(False)
+    prof = fmt.fmt_profile_read()
+    nodes = int(tree.info().nodes)
+    tree.close()
+    kern = {k: dict(launches=v[0], ms_per_step=v[1] / steps, avg_launch_ms=(v[1] / v[0] if v[0] else 0.0),
+                    units=v[2]) for k, v in prof.items() if v[0]}
+    L = basis_count(pr.p)
+    t50 = statistics.median(times)
+    return {
+        "fields": m, "n": pr.n, "nodes": nodes,
+        "ms_p50": 1e3 * t50, "ms_p99": 1e3 * float(np.percentile(times, 99)),
+        "field_pts_per_s": m * pr.n / t50,
+        "rooflines": refit_rooflines(kern, pr.p, L, pr.x.dtype.itemsize, steps),
+        "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in st.items()}
+                    for k, st in kern.items()},
+    }
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -175,6 +246,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="time only the headline path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 17)
+    ap.add_argument("--refit-fields", type=int, default=8,
+                    help="value fields of the fixed-topology refit leg (0: skip it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device to device (a plain copy kernel of known size "
                          "against which hardware byte counters are scaled)")
@@ -283,6 +356,13 @@ def main():
         v["traffic"] = traffic.get(k) if traffic else None
     gram_roof = roofs.get("gram")
 
+    refit = None
+    if args.refit_fields > 0:
+        opts = fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth,
+                                    path=fmt.FMT_PATH_MIXED if args.path == "mixed" else fmt.FMT_PATH_FP64,
+                                    refine_steps=args.mixed_refine if args.path == "mixed" else args.fp64_refine)
+        refit = refit_leg(fmt, opts, X, Y, Z, pr, args.refit_fields, args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pr, args.cpu_sample)
@@ -316,6 +396,7 @@ def main():
         "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in st.items()}
                     for k, st in h["kernels"].items()},
         "mixed_vs_fp64": cmp,
+        "refit": refit,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -132,31 +132,48 @@ void prof_resolve() {
 // ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
+// Owning device allocation, or a non-owning view of part of one (view()).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;
   DevBuf() = default;
   explicit DevBuf(size_t n) { alloc(n); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) { o.p = nullptr; o.bytes = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      owned = o.owned;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
+  static DevBuf view(void* base, size_t offset, size_t n) {
+    DevBuf b;
+    b.p = (char*)base + offset;
+    b.bytes = n;
+    b.owned = false;
+    return b;
+  }
   void alloc(size_t n) {
     release();
     if (n == 0) n = 256;
     hip_check(hipMalloc(&p, n), "hipMalloc");
     bytes = n;
+    owned = true;
   }
   // grow-only reallocation (contents are not kept)
   void reserve(size_t n) {
     if (n > bytes) alloc(std::max(n, bytes + bytes / 2));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
@@ -173,6 +190,9 @@ struct Workspace {
   // frames, chunk counts, entries, chunk offsets and chunk partials; the
   // B-only partials of the levels it covers
   DevBuf pyr, pyr_tab, pyr_begin, pyr_count, pyr_geo, pyr_nchk, pyr_dst, pyr_off, pyr_part, part_m2;
+  // fixed-topology refit: every field's coefficients and residual, one block
+  // per field
+  DevBuf rf_coef, rf_resid;
   uint32_t* host_counters = nullptr;
   // host-visible, fine-grained words the topology kernel writes the next
   // level's counters and a sequence number into (host view and device view)
@@ -319,12 +339,42 @@ struct Forest {
     for (const DevBuf& t : cell_tab) b += t.bytes;
     return b;
   }
+  // The node table lives in one allocation: the node set's arrays (begin ..
+  // child_mask, geo) first, topo_bytes of them, then flags and coefficients.
+  DevBuf node_block;
+  size_t topo_bytes = 0;
   void alloc_nodes(uint32_t cap) {
-    const size_t u = sizeof(uint32_t) * (size_t)cap;
-    nb_begin.alloc(u); nb_count.alloc(u); nb_prefix.alloc(u); nb_level.alloc(u); nb_problem.alloc(u);
-    nb_parent.alloc(u); nb_first_child.alloc(u); nb_child_mask.alloc(u); nb_flags.alloc(u);
-    nb_geo.alloc(sizeof(double) * 6 * (size_t)cap);
-    nb_coef.alloc(sizeof(double) * (size_t)L * (size_t)cap);
+    const size_t u = sizeof(uint32_t) * (size_t)cap, g = sizeof(double) * 6 * (size_t)cap;
+    const size_t c = sizeof(double) * (size_t)L * (size_t)cap;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    topo_bytes = 8 * al(u) + al(g);
+    node_block.alloc(topo_bytes + al(u) + al(c));
+    void* b = node_block.p;
+    DevBuf* u32[8] = {&nb_begin, &nb_count, &nb_prefix, &nb_level, &nb_problem, &nb_parent, &nb_first_child,
+                      &nb_child_mask};
+    for (int q = 0; q < 8; ++q) *u32[q] = DevBuf::view(b, q * al(u), u);
+    nb_geo = DevBuf::view(b, 8 * al(u), g);
+    nb_flags = DevBuf::view(b, topo_bytes, u);
+    nb_coef = DevBuf::view(b, topo_bytes + al(u), c);
+  }
+  // Take over another forest's node table (block and views).
+  void adopt_nodes(Forest& o) {
+    nb_begin = std::move(o.nb_begin); nb_count = std::move(o.nb_count); nb_prefix = std::move(o.nb_prefix);
+    nb_level = std::move(o.nb_level); nb_problem = std::move(o.nb_problem); nb_parent = std::move(o.nb_parent);
+    nb_first_child = std::move(o.nb_first_child); nb_child_mask = std::move(o.nb_child_mask);
+    nb_flags = std::move(o.nb_flags); nb_geo = std::move(o.nb_geo); nb_coef = std::move(o.nb_coef);
+    node_block = std::move(o.node_block);
+    topo_bytes = o.topo_bytes;
+  }
+  // Per-point arrays (keys, permutation, residual) in one allocation.
+  DevBuf point_block;
+  void alloc_points(uint32_t n) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t u = 4ull * n;
+    point_block.alloc(2 * al(u) + 8ull * n);
+    skey = DevBuf::view(point_block.p, 0, u);
+    order = DevBuf::view(point_block.p, al(u), u);
+    resid = DevBuf::view(point_block.p, 2 * al(u), 8ull * n);
   }
   void fetch_host() {
     std::lock_guard<std::mutex> g(host_mu);
@@ -434,9 +484,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   std::lock_guard<std::mutex> wlock(W.mu);
 
   // per-point storage kept by the forest
-  F->skey.alloc(4ull * N);
-  F->order.alloc(4ull * N);
-  F->resid.alloc(8ull * N);
+  F->alloc_points(N);
   W.keys_alt.reserve(4ull * N);
   W.vals_alt.reserve(4ull * N);
   W.sort_scratch.reserve(4 * radix_sort_scratch_words(N));
@@ -763,11 +811,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   // when the capacity bound would hold much more memory than the nodes need
   const size_t per_node = 4ull * 9 + 48ull + 8ull * L;
   if ((uint64_t)cap * per_node <= (64ull << 20) || (uint64_t)cap <= 2ull * F->nodes) {
-    F->nb_begin = std::move(tmp.nb_begin); F->nb_count = std::move(tmp.nb_count);
-    F->nb_prefix = std::move(tmp.nb_prefix); F->nb_level = std::move(tmp.nb_level);
-    F->nb_problem = std::move(tmp.nb_problem); F->nb_parent = std::move(tmp.nb_parent);
-    F->nb_first_child = std::move(tmp.nb_first_child); F->nb_child_mask = std::move(tmp.nb_child_mask);
-    F->nb_flags = std::move(tmp.nb_flags); F->nb_geo = std::move(tmp.nb_geo); F->nb_coef = std::move(tmp.nb_coef);
+    F->adopt_nodes(tmp);
   } else {
     F->alloc_nodes(std::max<uint32_t>(F->nodes, 1));
     auto cp = [&](DevBuf& dst, const DevBuf& src, size_t bytes) {
@@ -807,47 +851,62 @@ void build_single_nodes(Forest& F, const std::vector<uint32_t>& hl, const std::v
                         const std::vector<uint32_t>& hb, const std::vector<uint32_t>& hc, const double* hcoef,
                         const ProblemParams& prm, hipStream_t s) {
   const uint32_t M = (uint32_t)hl.size();
-  std::map<std::pair<uint32_t, uint32_t>, uint32_t> pos;
-  for (uint32_t j = 0; j < M; ++j)
-    if (!pos.emplace(std::make_pair(hl[j], hp[j]), j).second) fail(FMT_E_INVALID_ARG, "duplicate node");
-  std::vector<uint32_t> hprob(M, 0), hpar(M), hfc(M, 0), hcm(M, 0), hf(M, 0);
-  for (uint32_t j = 0; j < M; ++j) {
-    if (hl[j] == 0) {
-      hpar[j] = j;
-      continue;
-    }
-    auto it = pos.find(std::make_pair(hl[j] - 1, hp[j] >> 3));
-    if (it == pos.end()) fail(FMT_E_INVALID_ARG, "a node's parent is missing");
-    const uint32_t par = it->second;
-    hpar[j] = par;
-    if (hcm[par] == 0) hfc[par] = j;
-    hcm[par] |= 1u << (hp[j] & 7u);
-  }
-  F.alloc_nodes(std::max<uint32_t>(M, 1));
-  F.nodes = M;
-  auto up = [&](DevBuf& b, const void* h, size_t bytes) {
-    if (bytes) HIPCHK(hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, s));
-  };
-  up(F.nb_begin, hb.data(), 4ull * M); up(F.nb_count, hc.data(), 4ull * M); up(F.nb_prefix, hp.data(), 4ull * M);
-  up(F.nb_level, hl.data(), 4ull * M); up(F.nb_problem, hprob.data(), 4ull * M);
-  up(F.nb_parent, hpar.data(), 4ull * M); up(F.nb_first_child, hfc.data(), 4ull * M);
-  up(F.nb_child_mask, hcm.data(), 4ull * M); up(F.nb_flags, hf.data(), 4ull * M);
-  if (hcoef) up(F.nb_coef, hcoef, 8ull * M * F.L);
-  DevBuf dprm(sizeof(ProblemParams));
-  up(dprm, &prm, sizeof(ProblemParams));
-  HIPCHK(launch_node_geo(F.table(), dprm.as<ProblemParams>(), M, s));
-  HIPCHK(hipStreamSynchronize(s));   // dprm and the host vectors above die here
-  // nodes are in level order: one range per level
+  // level ranges (nodes are in (level, prefix) order)
   F.level_start.clear();
   F.level_count.clear();
   for (uint32_t j = 0; j < M; ++j) {
     if (j == 0 || hl[j] != hl[j - 1]) {
       F.level_start.push_back(j);
       F.level_count.push_back(0);
+    } else if (hp[j] == hp[j - 1]) {
+      fail(FMT_E_INVALID_ARG, "duplicate node");
     }
     ++F.level_count.back();
   }
-  F.depth_present = M ? (int)*std::max_element(hl.begin(), hl.end()) : 0;
+  F.alloc_nodes(std::max<uint32_t>(M, 1));
+  F.nodes = M;
+  // host image of the node set's arrays, laid out as on the device
+  const size_t u = 4ull * std::max<uint32_t>(M, 1), ua = (u + 255) & ~(size_t)255;
+  std::vector<uint32_t> img(F.topo_bytes / 4 + ua / 4, 0u);   // + flags (zero)
+  uint32_t* hbeg = img.data();
+  uint32_t* hcnt = hbeg + ua / 4;
+  uint32_t* hpre = hbeg + 2 * ua / 4;
+  uint32_t* hlev = hbeg + 3 * ua / 4;
+  uint32_t* hpar = hbeg + 5 * ua / 4;
+  uint32_t* hfc = hbeg + 6 * ua / 4;
+  uint32_t* hcm = hbeg + 7 * ua / 4;
+  size_t d = 0;   // level index of node j
+  for (uint32_t j = 0; j < M; ++j) {
+    while (d + 1 < F.level_start.size() && F.level_start[d + 1] <= j) ++d;
+    hbeg[j] = hb[j];
+    hcnt[j] = hc[j];
+    hpre[j] = hp[j];
+    hlev[j] = hl[j];
+    if (hl[j] == 0) {
+      hpar[j] = j;
+      continue;
+    }
+    // the parent: prefix >> 3 in the previous level present, which must be level hl[j] - 1
+    if (d == 0 || hl[F.level_start[d - 1]] != hl[j] - 1) fail(FMT_E_INVALID_ARG, "a node's parent is missing");
+    const uint32_t* lo = hp.data() + F.level_start[d - 1];
+    const uint32_t* hi = lo + F.level_count[d - 1];
+    const uint32_t* it = std::lower_bound(lo, hi, hp[j] >> 3);
+    if (it == hi || *it != (hp[j] >> 3)) fail(FMT_E_INVALID_ARG, "a node's parent is missing");
+    const uint32_t par = (uint32_t)(it - hp.data());
+    hpar[j] = par;
+    if (hcm[par] == 0) hfc[par] = j;
+    hcm[par] |= 1u << (hp[j] & 7u);
+  }
+  // one upload of the whole image (geo is computed on the device below; the
+  // flags after it start at zero)
+  HIPCHK(hipMemcpyAsync(F.node_block.p, img.data(), 8 * ua, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(F.nb_flags.p, img.data() + F.topo_bytes / 4, u, hipMemcpyHostToDevice, s));
+  if (hcoef && M) HIPCHK(hipMemcpyAsync(F.nb_coef.p, hcoef, 8ull * M * F.L, hipMemcpyHostToDevice, s));
+  DevBuf dprm(sizeof(ProblemParams));
+  HIPCHK(hipMemcpyAsync(dprm.p, &prm, sizeof(ProblemParams), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_node_geo(F.table(), dprm.as<ProblemParams>(), M, s));
+  HIPCHK(hipStreamSynchronize(s));   // dprm and the host image die here
+  F.depth_present = M ? (int)hl[M - 1] : 0;
 }
 
 fmt_status guard(const std::function<void()>& body) {
@@ -924,9 +983,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     F->probs[0].prm = prm;
     F->probs[0].root = 0;
     F->probs[0].n = P.n;
-    F->skey.alloc(4ull * N);
-    F->order.alloc(4ull * N);
-    F->resid.alloc(8ull * N);
+    F->alloc_points(N);
     outs[j] = F;
   }
   Forest& F0 = *outs[0];
@@ -941,16 +998,10 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     F.level_start = F0.level_start;
     F.level_count = F0.level_count;
     F.depth_present = F0.depth_present;
-    auto cp = [&](DevBuf& dst, const DevBuf& src, size_t bytes) {
-      if (bytes) HIPCHK(hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyDeviceToDevice, s));
-    };
-    const size_t un = 4ull * M;
-    cp(F.nb_begin, F0.nb_begin, un); cp(F.nb_count, F0.nb_count, un); cp(F.nb_prefix, F0.nb_prefix, un);
-    cp(F.nb_level, F0.nb_level, un); cp(F.nb_problem, F0.nb_problem, un); cp(F.nb_parent, F0.nb_parent, un);
-    cp(F.nb_first_child, F0.nb_first_child, un); cp(F.nb_child_mask, F0.nb_child_mask, un);
-    cp(F.nb_geo, F0.nb_geo, 48ull * M);
-    cp(F.skey, F0.skey, 4ull * N);
-    cp(F.order, F0.order, 4ull * N);
+    // the node set's arrays and the keys and permutation: one copy each
+    HIPCHK(hipMemcpyAsync(F.node_block.p, F0.node_block.p, F0.topo_bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(F.point_block.p, F0.point_block.p, (char*)F0.resid.p - (char*)F0.point_block.p,
+                          hipMemcpyDeviceToDevice, s));
   }
 
   // per level: first node, nodes, points and chunk offsets (concatenated)
@@ -977,12 +1028,14 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
   std::lock_guard<std::mutex> wlock(W.mu);
   const size_t esz = dtype == FMT_F32 ? 4 : 8;
   const uint32_t NMB = (uint32_t)moment_base_doubles(p);
+  const size_t cstride = (size_t)M * L;
   for (DevBuf* b : {&W.px, &W.py, &W.pz}) b->reserve(esz * N);
   W.partial.reserve(8ull * NMB * max_chunks);
-  W.part_b.reserve(8ull * L * max_chunks);
-  W.part_ss.reserve(8ull * 16 * max_chunks);
+  W.part_b.reserve(8ull * L * max_chunks * (size_t)m);
   W.fac.reserve(8ull * factor_doubles(p) * max_nodes);
   W.chunk_a.reserve(4ull * choff.size());
+  W.rf_coef.reserve(8ull * std::max<size_t>(cstride, 1) * m);
+  W.rf_resid.reserve(8ull * N * m);
   W.status.reserve(64);
   char* stg = W.staging(4ull * choff.size());
   std::memcpy(stg, choff.data(), 4ull * choff.size());
@@ -992,14 +1045,13 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     ProfScope ps(KN_XGATHER, (double)N * (1 + m), s);
     HIPCHK(launch_refit_gather(dtype, S.order.as<uint32_t>(), S.skey.as<uint32_t>(), off, N, x, y, z, P.prm, S.D,
                                W.px.p, W.py.p, W.pz.p, W.status.as<uint32_t>(), s));
-    for (int j = 0; j < m; ++j)
-      HIPCHK(launch_gather_fields(dtype, S.order.as<uint32_t>(), off, N, (const char*)f + esz * N * (size_t)j, 1, 0,
-                                  outs[j]->resid.as<double>(), 0, s));
+    HIPCHK(launch_gather_fields(dtype, S.order.as<uint32_t>(), off, N, f, m, N, W.rf_resid.as<double>(), N, s));
   }
 
   for (size_t d = 0; d < nlev; ++d) {
     LevelArgs a{};
     a.nt = F0.table();
+    a.nt.coef = W.rf_coef.as<double>();
     a.node0 = F0.level_start[d];
     a.nnodes = F0.level_count[d];
     a.chunk_off = W.chunk_a.as<uint32_t>() + cbase[d];
@@ -1007,9 +1059,11 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     a.px = W.px.p;
     a.py = W.py.p;
     a.pz = W.pz.p;
+    a.r = W.rf_resid.as<double>();
     a.skey = F0.skey.as<uint32_t>();
     a.level = (int)d;
-    a.D = S.D;
+    // no octant statistics: the node set is fixed
+    a.D = (int)d;
     a.tol = 0.0;
     // float64 moments: refinement where the conditioning estimate asks for it
     a.refine = S.refine > 0 ? 1 : 0;
@@ -1024,32 +1078,37 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
       ProfScope ps(KN_XFACTOR, a.nnodes, s);
       HIPCHK(launch_factor_moments(p, a, W.partial.as<double>(), W.fac.as<double>(), s));
     }
-    for (int j = 0; j < m; ++j) {
-      LevelArgs b = a;
-      b.nt.coef = outs[j]->nb_coef.as<double>();
-      b.r = outs[j]->resid.as<double>();
-      {
-        ProfScope ps(KN_XBMOM, lpts[d], s);
-        HIPCHK(launch_moments(p, 2, dtype, b, W.part_b.as<double>(), s));
-        if (multi) HIPCHK(launch_chunk_reduce(b, W.part_b.as<double>(), L, s));
-      }
-      {
-        ProfScope ps(KN_XSOLVE, a.nnodes, s);
-        HIPCHK(launch_factor_solve(p, b, W.part_b.as<double>(), W.fac.as<double>(), s));
-      }
-      for (int it = 0; it < S.refine; ++it) {
-        {
-          ProfScope ps(KN_RSWEEP, lpts[d], s);
-          HIPCHK(launch_moments(p, 1, dtype, b, W.part_b.as<double>(), s));
-        }
-        ProfScope ps(KN_RSOLVE, a.nnodes, s);
-        HIPCHK(launch_refine_solve(p, b, W.part_b.as<double>(), W.fac.as<double>(), s));
-      }
-      {
-        ProfScope ps(KN_XRESID, lpts[d], s);
-        HIPCHK(launch_residual(p, dtype, b, W.part_ss.as<double>(), s));
-      }
+    // all fields in each launch (grid rows)
+    a.nfields = (uint32_t)m;
+    a.rstride = N;
+    a.cstride = cstride;
+    {
+      ProfScope ps(KN_XBMOM, (double)lpts[d] * m, s);
+      HIPCHK(launch_moments(p, 2, dtype, a, W.part_b.as<double>(), s));
+      if (multi) HIPCHK(launch_chunk_reduce(a, W.part_b.as<double>(), L, s));
     }
+    {
+      ProfScope ps(KN_XSOLVE, (double)a.nnodes * m, s);
+      HIPCHK(launch_factor_solve(p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
+    }
+    for (int it = 0; it < S.refine; ++it) {
+      {
+        ProfScope ps(KN_RSWEEP, (double)lpts[d] * m, s);
+        HIPCHK(launch_moments(p, 1, dtype, a, W.part_b.as<double>(), s));
+      }
+      ProfScope ps(KN_RSOLVE, (double)a.nnodes * m, s);
+      HIPCHK(launch_refine_solve(p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
+    }
+    {
+      ProfScope ps(KN_XRESID, (double)lpts[d] * m, s);
+      HIPCHK(launch_residual(p, dtype, a, nullptr, s));
+    }
+  }
+  for (int j = 0; j < m; ++j) {
+    if (M) HIPCHK(hipMemcpyAsync(outs[j]->nb_coef.p, W.rf_coef.as<double>() + cstride * j, 8ull * cstride,
+                                 hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(outs[j]->resid.p, W.rf_resid.as<double>() + (size_t)N * j, 8ull * N,
+                          hipMemcpyDeviceToDevice, s));
   }
   // the rank and refinement flags belong to the node set: every field's tree
   // gets the same ones, then its own non-finite marks

@@ -27,7 +27,16 @@ struct LevelArgs {
   // when no problem has one.  Nodes at levels d <= kp take M from the
   // pyramid (pyramid_covers)
   const uint32_t* pyr_tab;
+  // several right-hand sides in one launch (the fixed-topology refit): grid
+  // index y = j selects the residual r + j rstride, the coefficients
+  // nt.coef + j cstride and the field's own block of chunk partials (nchunks
+  // chunks per field); nfields <= 1 is one field
+  uint32_t nfields = 1;
+  uint64_t rstride = 0, cstride = 0;
 };
+
+// Grid rows of a launch over the fields of a LevelArgs.
+inline unsigned field_rows(const LevelArgs& a) { return a.nfields > 1 ? a.nfields : 1u; }
 
 // Moment pyramid tables (k_pyramid.hip).  The per-problem words: first
 // pyramid entry, depth kp (0: none), first flat finest cell, unused.
@@ -72,7 +81,7 @@ size_t gram_partial_doubles(int p);
 size_t factor_doubles(int p);
 
 // Sum each multi-chunk node's chunk partials (`width` doubles per chunk) into
-// its first chunk slot.
+// its first chunk slot (per field: a.nchunks * width doubles each).
 hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, hipStream_t s);
 hipError_t launch_node_geo(const NodeTable& nt, const ProblemParams* prm, uint32_t n, hipStream_t s);
 hipError_t launch_roots(const NodeTable& nt, const ProblemParams* prm, int nprob, hipStream_t s);

@@ -585,6 +585,7 @@ __device__ __forceinline__ void solve_with_factor(const LevelArgs& a, const doub
   // with a.refine == 2 (every node refined) the chunk partials were summed
   // into the first chunk's slot beforehand; otherwise they are summed here
   const uint32_t c0 = a.chunk_off[k], c1 = (FIRST || a.refine == 2) ? c0 + 1 : a.chunk_off[k + 1];
+  part_b += (size_t)blockIdx.y * a.nchunks * L;   // the field's partials
   const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
   copy_to_lds<256, S::WORDS>(A, fo, tid);
   if (tid < 16) A[S::WORDS + tid] = 0.0;
@@ -615,7 +616,7 @@ __device__ __forceinline__ void solve_with_factor(const LevelArgs& a, const doub
   __syncthreads();
   if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
   __syncthreads();
-  double* F = a.nt.coef + (size_t)node * L;
+  double* F = a.nt.coef + (size_t)blockIdx.y * a.cstride + (size_t)node * L;
   for (int i = tid; i < L; i += 256) F[i] = FIRST ? sc[i] * z[i] : F[i] + sc[i] * z[i];
 }
 
@@ -652,7 +653,9 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
   const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
   const double* geo = a.nt.geo + 6 * (size_t)node;
   const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
-  for (int i = tid; i < L; i += 256) Fs[i] = a.nt.coef[(size_t)node * L + i];
+  const uint32_t fj = blockIdx.y;   // field of a multi-field launch
+  double* rr = a.r + (size_t)fj * a.rstride;
+  for (int i = tid; i < L; i += 256) Fs[i] = a.nt.coef[(size_t)fj * a.cstride + (size_t)node * L + i];
   __syncthreads();
   const bool stats = a.level < a.D;
   const int shift = stats ? 3 * (a.D - a.level - 1) : 0;
@@ -667,8 +670,8 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
     double x, y, z;
     load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
     const double val = poly_eval<P, double>(Fs, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
-    const double rn = a.r[i] - val;
-    a.r[i] = rn;
+    const double rn = rr[i] - val;
+    rr[i] = rn;
     const uint32_t o = (a.skey[i] >> shift) & 7u;
     const double r2 = rn * rn;
 #pragma unroll
@@ -695,6 +698,7 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
     }
   }
   __syncthreads();
+  part_ss += (size_t)fj * a.nchunks * 16;
   if (tid < 8) part_ss[(size_t)g * 16 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
   else if (tid < 16)
     part_ss[(size_t)g * 16 + tid] =
@@ -743,8 +747,10 @@ __global__ void __launch_bounds__(256) k_children(LevelArgs a, const double* __r
 // thread), and the sixteen group sums are added in a fixed tree.
 // Single-chunk nodes exit at once.
 __global__ void __launch_bounds__(1024) k_chunk_reduce(const uint32_t* __restrict__ chunk_off, uint32_t nnodes,
-                                                       double* __restrict__ buf, uint32_t width, uint32_t eblocks) {
+                                                       double* __restrict__ buf, uint32_t width, uint32_t eblocks,
+                                                       uint64_t fstride) {
   __shared__ double part[16][64];
+  buf += (size_t)blockIdx.y * fstride;   // the field's partials
   const uint32_t k = blockIdx.x / eblocks;
   if (k >= nnodes) return;
   const uint32_t c0 = chunk_off[k], c1 = chunk_off[k + 1];
@@ -945,7 +951,7 @@ hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part_m,
 template <int P>
 static hipError_t rsolve_impl(const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
   if (a.nnodes == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_refine_solve<P>, dim3(a.nnodes), dim3(256), 0, s, a, part_b, fac);
+  hipLaunchKernelGGL(k_refine_solve<P>, dim3(a.nnodes, field_rows(a)), dim3(256), 0, s, a, part_b, fac);
   return hipGetLastError();
 }
 hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
@@ -965,7 +971,7 @@ hipError_t launch_factor_moments(int p, const LevelArgs& a, const double* part_m
 template <int P>
 static hipError_t fsolve_impl(const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
   if (a.nnodes == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_factor_solve<P>, dim3(a.nnodes), dim3(256), 0, s, a, part_b, fac);
+  hipLaunchKernelGGL(k_factor_solve<P>, dim3(a.nnodes, field_rows(a)), dim3(256), 0, s, a, part_b, fac);
   return hipGetLastError();
 }
 hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
@@ -975,8 +981,9 @@ hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, 
 template <int P>
 static hipError_t resid_impl(int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {
   if (a.nchunks == 0) return hipSuccess;
-  if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float>), dim3(a.nchunks), dim3(256), 0, s, a, part_ss);
-  else hipLaunchKernelGGL((k_residual<P, double>), dim3(a.nchunks), dim3(256), 0, s, a, part_ss);
+  const dim3 grid(a.nchunks, field_rows(a));
+  if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float>), grid, dim3(256), 0, s, a, part_ss);
+  else hipLaunchKernelGGL((k_residual<P, double>), grid, dim3(256), 0, s, a, part_ss);
   return hipGetLastError();
 }
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {
@@ -1006,8 +1013,8 @@ hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint3
 hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, hipStream_t s) {
   if (a.nnodes == 0 || a.nchunks <= a.nnodes) return hipSuccess;
   const uint32_t eblocks = (width + 63) / 64;
-  hipLaunchKernelGGL(k_chunk_reduce, dim3(a.nnodes * eblocks), dim3(1024), 0, s, a.chunk_off, a.nnodes, buf, width,
-                     eblocks);
+  hipLaunchKernelGGL(k_chunk_reduce, dim3(a.nnodes * eblocks, field_rows(a)), dim3(1024), 0, s, a.chunk_off,
+                     a.nnodes, buf, width, eblocks, (uint64_t)a.nchunks * width);
   return hipGetLastError();
 }
 

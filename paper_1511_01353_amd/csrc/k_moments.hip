@@ -264,6 +264,8 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
   const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
   const uint32_t n = min(nb + nc, start + (uint32_t)CHUNK) - start;
   const double* geo = a.nt.geo + 6 * (size_t)node;
+  const uint32_t fj = blockIdx.y;   // field of a multi-field launch
+  const double* rin = a.r + (size_t)fj * a.rstride;
   if constexpr (MODE == 0 || MODE == 2) {
     // a level split between the pyramid's nodes (mode 2) and the others
     if (a.pyr_tab && pyramid_covers(a.pyr_tab[PYR_TAB_WORDS * a.nt.problem[node] + 1], a.level) != (MODE == 2)) return;
@@ -282,7 +284,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
     // wave-uniform and read with scalar loads (read-only constant address
     // space), so they take no vector registers
     typedef const double __attribute__((address_space(4))) cdouble;
-    const cdouble* F = (const cdouble*)(a.nt.coef + (size_t)node * L);
+    const cdouble* F = (const cdouble*)(a.nt.coef + (size_t)fj * a.cstride + (size_t)node * L);
     const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
     for (uint32_t i0 = threadIdx.x; i0 < n; i0 += NPT * NT) {
       TIN vx[NPT], vy[NPT], vz[NPT];
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
         vx[q] = gx[i];
         vy[q] = gy[i];
         vz[q] = gz[i];
-        r[q] = a.r[start + i];
+        r[q] = rin[start + i];
       }
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
@@ -323,7 +325,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
         vx[q] = gx[i];
         vy[q] = gy[i];
         vz[q] = gz[i];
-        if constexpr (ST::HAS_W) r[q] = a.r[start + i];
+        if constexpr (ST::HAS_W) r[q] = rin[start + i];
       }
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
@@ -339,7 +341,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
   }
   __syncthreads();
   const ST st(smem);
-  double* out = part + (size_t)g * MP::NOUT;
+  double* out = part + ((size_t)fj * a.nchunks + g) * MP::NOUT;
   const int w = threadIdx.x >> 6;
   const int grp = w % MP::NW, slice = w / MP::NW;
   double* red = reinterpret_cast<double*>(smem + (ALIAS ? 0 : ST::BYTES)) + (size_t)w * MP::RROWS * 65;
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
 
 template <int P, int MODE>
 static void launch_mode(int dtype, const LevelArgs& a, double* part, hipStream_t s) {
-  dim3 grid(a.nchunks), block(MomentPlan<P, MODE>::NTHR);
+  dim3 grid(a.nchunks, field_rows(a)), block(MomentPlan<P, MODE>::NTHR);
   if (dtype == FMT_F32) hipLaunchKernelGGL((k_moments<P, MODE, float>), grid, block, 0, s, a, part);
   else hipLaunchKernelGGL((k_moments<P, MODE, double>), grid, block, 0, s, a, part);
 }

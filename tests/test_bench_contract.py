@@ -24,3 +24,16 @@ def test_algorithmic_work_counts():
     assert bench.bmoment_flops_per_point(6) == 2 * 84 + 28 + 18
     assert bench.base_moment_flops_per_point(6) == 2 * 455 + 91 + 36
     assert bench.solve_flops_per_node(84) == 84 ** 3 / 3 + 2 * 84 * 84
+
+
+def test_refit_rooflines_from_launch_records():
+    sys.path.insert(0, ROOT)
+    import bench
+    # two steps; the refit's factor class covered 100 nodes in 2 ms in total
+    kern = {"refit_factor": dict(launches=10, ms_per_step=1.0, avg_launch_ms=0.2, units=100.0),
+            "refit_residual": dict(launches=10, ms_per_step=0.5, avg_launch_ms=0.1, units=2.0e6)}
+    r = bench.refit_rooflines(kern, 6, 84, 4, 2)
+    assert abs(r["refit_factor"]["achieved"] - 100 * 84 ** 3 / 3 / 2e-3 / 1e12) < 1e-12
+    assert r["refit_factor"]["unit"] == "TFLOP/s" and r["refit_factor"]["peak"] == 78.6
+    assert abs(r["refit_residual"]["achieved"] - 2e6 * 32 / 1e-3 / 1e9) < 1e-9
+    assert r["refit_residual"]["bound"] == "hbm"
