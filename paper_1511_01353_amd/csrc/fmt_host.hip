@@ -190,9 +190,6 @@ struct Workspace {
   // frames, chunk counts, entries, chunk offsets and chunk partials; the
   // B-only partials of the levels it covers
   DevBuf pyr, pyr_tab, pyr_begin, pyr_count, pyr_geo, pyr_nchk, pyr_dst, pyr_off, pyr_part, part_m2;
-  // fixed-topology refit: every field's coefficients and residual, one block
-  // per field
-  DevBuf rf_coef, rf_resid;
   uint32_t* host_counters = nullptr;
   // host-visible, fine-grained words the topology kernel writes the next
   // level's counters and a sequence number into (host view and device view)
@@ -343,19 +340,25 @@ struct Forest {
   // child_mask, geo) first, topo_bytes of them, then flags and coefficients.
   DevBuf node_block;
   size_t topo_bytes = 0;
-  void alloc_nodes(uint32_t cap) {
+  static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+  static size_t node_bytes(uint32_t cap, int L) {
+    const size_t u = sizeof(uint32_t) * (size_t)cap;
+    return 8 * al256(u) + al256(48ull * cap) + al256(u) + al256(sizeof(double) * (size_t)L * cap);
+  }
+  // Node arrays for `cap` nodes as views into base (node_bytes(cap, L) bytes).
+  void place_nodes(void* base, uint32_t cap) {
     const size_t u = sizeof(uint32_t) * (size_t)cap, g = sizeof(double) * 6 * (size_t)cap;
-    const size_t c = sizeof(double) * (size_t)L * (size_t)cap;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    topo_bytes = 8 * al(u) + al(g);
-    node_block.alloc(topo_bytes + al(u) + al(c));
-    void* b = node_block.p;
+    topo_bytes = 8 * al256(u) + al256(g);
     DevBuf* u32[8] = {&nb_begin, &nb_count, &nb_prefix, &nb_level, &nb_problem, &nb_parent, &nb_first_child,
                       &nb_child_mask};
-    for (int q = 0; q < 8; ++q) *u32[q] = DevBuf::view(b, q * al(u), u);
-    nb_geo = DevBuf::view(b, 8 * al(u), g);
-    nb_flags = DevBuf::view(b, topo_bytes, u);
-    nb_coef = DevBuf::view(b, topo_bytes + al(u), c);
+    for (int q = 0; q < 8; ++q) *u32[q] = DevBuf::view(base, q * al256(u), u);
+    nb_geo = DevBuf::view(base, 8 * al256(u), g);
+    nb_flags = DevBuf::view(base, topo_bytes, u);
+    nb_coef = DevBuf::view(base, topo_bytes + al256(u), sizeof(double) * (size_t)L * cap);
+  }
+  void alloc_nodes(uint32_t cap) {
+    node_block.alloc(node_bytes(cap, L));
+    place_nodes(node_block.p, cap);
   }
   // Take over another forest's node table (block and views).
   void adopt_nodes(Forest& o) {
@@ -368,14 +371,19 @@ struct Forest {
   }
   // Per-point arrays (keys, permutation, residual) in one allocation.
   DevBuf point_block;
-  void alloc_points(uint32_t n) {
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t u = 4ull * n;
-    point_block.alloc(2 * al(u) + 8ull * n);
-    skey = DevBuf::view(point_block.p, 0, u);
-    order = DevBuf::view(point_block.p, al(u), u);
-    resid = DevBuf::view(point_block.p, 2 * al(u), 8ull * n);
+  static size_t point_bytes(uint32_t n) { return 2 * al256(4ull * n) + 8ull * n; }
+  void place_points(void* base, uint32_t n) {
+    skey = DevBuf::view(base, 0, 4ull * n);
+    order = DevBuf::view(base, al256(4ull * n), 4ull * n);
+    resid = DevBuf::view(base, 2 * al256(4ull * n), 8ull * n);
   }
+  void alloc_points(uint32_t n) {
+    point_block.alloc(point_bytes(n));
+    place_points(point_block.p, n);
+  }
+  // storage shared with other forests (the trees of one refit call), kept
+  // alive while any of them lives
+  std::shared_ptr<DevBuf> shared;
   void fetch_host() {
     std::lock_guard<std::mutex> g(host_mu);
     if (host_ready) return;
@@ -863,7 +871,7 @@ void build_single_nodes(Forest& F, const std::vector<uint32_t>& hl, const std::v
     }
     ++F.level_count.back();
   }
-  F.alloc_nodes(std::max<uint32_t>(M, 1));
+  if (!F.nb_begin.p) F.alloc_nodes(std::max<uint32_t>(M, 1));
   F.nodes = M;
   // host image of the node set's arrays, laid out as on the device
   const size_t u = 4ull * std::max<uint32_t>(M, 1), ua = (u + 255) & ~(size_t)255;
@@ -899,7 +907,7 @@ void build_single_nodes(Forest& F, const std::vector<uint32_t>& hl, const std::v
   }
   // one upload of the whole image (geo is computed on the device below; the
   // flags after it start at zero)
-  HIPCHK(hipMemcpyAsync(F.node_block.p, img.data(), 8 * ua, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(F.nb_begin.p, img.data(), 8 * ua, hipMemcpyHostToDevice, s));   // start of the node arrays
   HIPCHK(hipMemcpyAsync(F.nb_flags.p, img.data() + F.topo_bytes / 4, u, hipMemcpyHostToDevice, s));
   if (hcoef && M) HIPCHK(hipMemcpyAsync(F.nb_coef.p, hcoef, 8ull * M * F.L, hipMemcpyHostToDevice, s));
   DevBuf dprm(sizeof(ProblemParams));
@@ -965,6 +973,12 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
   ProblemParams prm = P.prm;
   prm.offset = 0;
 
+  // one allocation for every field's tree: m node tables, then m point
+  // arrays, at fixed strides (the kernels address field j by them)
+  const uint32_t cap = std::max<uint32_t>(M, 1);
+  const size_t NB = Forest::node_bytes(cap, (int)L), PB = Forest::al256(Forest::point_bytes(N));
+  auto blk = std::make_shared<DevBuf>((NB + PB) * (size_t)m);
+  char* base = blk->as<char>();
   std::vector<std::shared_ptr<Forest>> outs(m);
   for (int j = 0; j < m; ++j) {
     auto F = std::make_shared<Forest>();
@@ -983,7 +997,9 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     F->probs[0].prm = prm;
     F->probs[0].root = 0;
     F->probs[0].n = P.n;
-    F->alloc_points(N);
+    F->shared = blk;
+    F->place_nodes(base + NB * j, cap);
+    F->place_points(base + NB * m + PB * j, N);
     outs[j] = F;
   }
   Forest& F0 = *outs[0];
@@ -991,17 +1007,17 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
   const uint32_t kmask = 3 * S.D >= 32 ? 0xffffffffu : ((1u << (3 * S.D)) - 1u);
   HIPCHK(launch_slice_points(S.skey.as<uint32_t>(), S.order.as<uint32_t>(), off, N, kmask, F0.skey.as<uint32_t>(),
                              F0.order.as<uint32_t>(), s));
+  // the other trees: the node set's arrays, keys and permutation replicated
+  HIPCHK(launch_replicate(base, F0.topo_bytes, base + NB, NB, m - 1, s));
+  HIPCHK(launch_replicate(F0.skey.p, (size_t)((char*)F0.resid.p - (char*)F0.skey.p), (char*)F0.skey.p + PB, PB,
+                          m - 1, s));
   for (int j = 1; j < m; ++j) {
     Forest& F = *outs[j];
-    F.alloc_nodes(std::max<uint32_t>(M, 1));
     F.nodes = M;
     F.level_start = F0.level_start;
     F.level_count = F0.level_count;
     F.depth_present = F0.depth_present;
-    // the node set's arrays and the keys and permutation: one copy each
-    HIPCHK(hipMemcpyAsync(F.node_block.p, F0.node_block.p, F0.topo_bytes, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(F.point_block.p, F0.point_block.p, (char*)F0.resid.p - (char*)F0.point_block.p,
-                          hipMemcpyDeviceToDevice, s));
+    F.topo_bytes = F0.topo_bytes;
   }
 
   // per level: first node, nodes, points and chunk offsets (concatenated)
@@ -1028,14 +1044,11 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
   std::lock_guard<std::mutex> wlock(W.mu);
   const size_t esz = dtype == FMT_F32 ? 4 : 8;
   const uint32_t NMB = (uint32_t)moment_base_doubles(p);
-  const size_t cstride = (size_t)M * L;
   for (DevBuf* b : {&W.px, &W.py, &W.pz}) b->reserve(esz * N);
   W.partial.reserve(8ull * NMB * max_chunks);
   W.part_b.reserve(8ull * L * max_chunks * (size_t)m);
   W.fac.reserve(8ull * factor_doubles(p) * max_nodes);
   W.chunk_a.reserve(4ull * choff.size());
-  W.rf_coef.reserve(8ull * std::max<size_t>(cstride, 1) * m);
-  W.rf_resid.reserve(8ull * N * m);
   W.status.reserve(64);
   char* stg = W.staging(4ull * choff.size());
   std::memcpy(stg, choff.data(), 4ull * choff.size());
@@ -1045,13 +1058,12 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     ProfScope ps(KN_XGATHER, (double)N * (1 + m), s);
     HIPCHK(launch_refit_gather(dtype, S.order.as<uint32_t>(), S.skey.as<uint32_t>(), off, N, x, y, z, P.prm, S.D,
                                W.px.p, W.py.p, W.pz.p, W.status.as<uint32_t>(), s));
-    HIPCHK(launch_gather_fields(dtype, S.order.as<uint32_t>(), off, N, f, m, N, W.rf_resid.as<double>(), N, s));
+    HIPCHK(launch_gather_fields(dtype, S.order.as<uint32_t>(), off, N, f, m, N, F0.resid.as<double>(), PB / 8, s));
   }
 
   for (size_t d = 0; d < nlev; ++d) {
     LevelArgs a{};
     a.nt = F0.table();
-    a.nt.coef = W.rf_coef.as<double>();
     a.node0 = F0.level_start[d];
     a.nnodes = F0.level_count[d];
     a.chunk_off = W.chunk_a.as<uint32_t>() + cbase[d];
@@ -1059,7 +1071,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     a.px = W.px.p;
     a.py = W.py.p;
     a.pz = W.pz.p;
-    a.r = W.rf_resid.as<double>();
+    a.r = F0.resid.as<double>();
     a.skey = F0.skey.as<uint32_t>();
     a.level = (int)d;
     // no octant statistics: the node set is fixed
@@ -1080,8 +1092,8 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     }
     // all fields in each launch (grid rows)
     a.nfields = (uint32_t)m;
-    a.rstride = N;
-    a.cstride = cstride;
+    a.rstride = PB / 8;
+    a.cstride = NB / 8;
     {
       ProfScope ps(KN_XBMOM, (double)lpts[d] * m, s);
       HIPCHK(launch_moments(p, 2, dtype, a, W.part_b.as<double>(), s));
@@ -1104,18 +1116,10 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
       HIPCHK(launch_residual(p, dtype, a, nullptr, s));
     }
   }
-  for (int j = 0; j < m; ++j) {
-    if (M) HIPCHK(hipMemcpyAsync(outs[j]->nb_coef.p, W.rf_coef.as<double>() + cstride * j, 8ull * cstride,
-                                 hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(outs[j]->resid.p, W.rf_resid.as<double>() + (size_t)N * j, 8ull * N,
-                          hipMemcpyDeviceToDevice, s));
-  }
   // the rank and refinement flags belong to the node set: every field's tree
   // gets the same ones, then its own non-finite marks
-  for (int j = 1; j < m; ++j) {
-    outs[j]->level_points = lpts;
-    if (M) HIPCHK(hipMemcpyAsync(outs[j]->nb_flags.p, F0.nb_flags.p, 4ull * M, hipMemcpyDeviceToDevice, s));
-  }
+  for (int j = 1; j < m; ++j) outs[j]->level_points = lpts;
+  HIPCHK(launch_replicate(F0.nb_flags.p, 4ull * M, (char*)F0.nb_flags.p + NB, NB, m - 1, s));
   for (int j = 0; j < m; ++j) HIPCHK(launch_check_coef(p, outs[j]->table(), M, W.status.as<uint32_t>(), s));
   HIPCHK(hipMemcpyAsync(W.host_counters + 4, W.status.p, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

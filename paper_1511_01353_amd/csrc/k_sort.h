@@ -65,6 +65,8 @@ hipError_t launch_gather_fields(int dtype, const uint32_t* order, uint32_t off, 
                                 uint64_t fstride, double* r, uint64_t rstride, hipStream_t s);
 // One problem's keys and permutation as a single-problem forest holds them:
 // okey[i] = skey[off + i] & kmask, oorder[i] = order[off + i] - off.
+// rows copies of `bytes` bytes (a multiple of 4) from src: row q to dst + q stride.
+hipError_t launch_replicate(const void* src, size_t bytes, void* dst, size_t stride, int rows, hipStream_t s);
 hipError_t launch_slice_points(const uint32_t* skey, const uint32_t* order, uint32_t off, uint32_t n, uint32_t kmask,
                                uint32_t* okey, uint32_t* oorder, hipStream_t s);
 

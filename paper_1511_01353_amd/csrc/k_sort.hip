@@ -617,6 +617,21 @@ __global__ void __launch_bounds__(256) k_slice_points(const uint32_t* __restrict
   oorder[i] = order[off + i] - off;
 }
 
+__global__ void __launch_bounds__(256) k_replicate(const uint32_t* __restrict__ src, uint64_t words,
+                                                   uint32_t* __restrict__ dst, uint64_t stride_words) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) dst[(uint64_t)blockIdx.y * stride_words + i] = src[i];
+}
+
+hipError_t launch_replicate(const void* src, size_t bytes, void* dst, size_t stride, int rows, hipStream_t s) {
+  if (rows <= 0 || bytes == 0) return hipSuccess;
+  if ((bytes | stride | (uintptr_t)src | (uintptr_t)dst) & 3) return hipErrorInvalidValue;
+  const uint64_t words = bytes / 4;
+  hipLaunchKernelGGL(k_replicate, dim3(blocks_for(words, 256), (unsigned)rows), dim3(256), 0, s,
+                     (const uint32_t*)src, words, (uint32_t*)dst, (uint64_t)(stride / 4));
+  return hipGetLastError();
+}
+
 hipError_t launch_refit_gather(int dtype, const uint32_t* order, const uint32_t* skey, uint32_t off, uint32_t n,
                                const void* x, const void* y, const void* z, const ProblemParams& P, int depth,
                                void* px, void* py, void* pz, uint32_t* status, hipStream_t s) {
