@@ -98,6 +98,10 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
     add("bmoments", "alu", bmoment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("base_moments", "alu", base_moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("solve", "alu", solve_flops_per_node(L), "TFLOP/s", PEAK_TFLOPS["fp64"])
+    # the pyramid's upper levels: factors made ahead of the level loop (units:
+    # cells), then per level only the two triangular solves (units: nodes)
+    add("factor_ahead", "alu", L ** 3 / 3.0, "TFLOP/s", PEAK_TFLOPS["fp64"])
+    add("solve_ahead", "alu", 2.0 * L * L, "TFLOP/s", PEAK_TFLOPS["fp64"])
     if path == "mixed":
         # every node is refined; on the float64 path only the nodes the
         # condition estimate flags are, a count the host does not see, so the

@@ -57,10 +57,11 @@ struct ProfRecord {
 const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce", "solve", "refine_sweep",
                               "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval", "compose",
                               "bmoments", "base_moments", "pyramid", "refit_gather", "refit_moments",
-                              "refit_factor", "refit_bmoments", "refit_solve", "refit_residual"};
+                              "refit_factor", "refit_bmoments", "refit_solve", "refit_residual", "factor_ahead",
+                              "solve_ahead"};
 enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
        KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_BMOM, KN_BASEM, KN_PYR, KN_XGATHER, KN_XMOM, KN_XFACTOR,
-       KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_COUNT };
+       KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_UPFAC, KN_FSOLVE, KN_COUNT };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof_pending;
@@ -190,6 +191,8 @@ struct Workspace {
   // frames, chunk counts, entries, chunk offsets and chunk partials; the
   // B-only partials of the levels it covers
   DevBuf pyr, pyr_tab, pyr_begin, pyr_count, pyr_geo, pyr_nchk, pyr_dst, pyr_off, pyr_part, part_m2;
+  // factors of the pyramid's upper levels made ahead of the level loop
+  DevBuf fac_up, up_flags;
   uint32_t* host_counters = nullptr;
   // host-visible, fine-grained words the topology kernel writes the next
   // level's counters and a sequence number into (host view and device view)
@@ -560,6 +563,30 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     break;
   }
   if (npyr == 0) ptab.clear();
+  // Factors of the pyramid's upper levels (above each problem's finest), made
+  // in one launch before the level loop: per problem the levels 0 .. ku-1,
+  // ku <= kp, as many as fit a bound on their storage.  Their pyramid
+  // entries are listed after the table; word 3 of a problem's entry gives its
+  // first slot and ku.
+  uint32_t up_cells = 0, up_off = 0;
+  const size_t fd_bytes = 8 * factor_doubles(F->p);
+  if (npyr > 0) {
+    int ku_max = kp_max;
+    auto cells_for = [&](int ku) {
+      uint64_t c = 0;
+      for (int k = 0; k < K; ++k) c += level_first(std::min((int)kp[k], ku));
+      return c;
+    };
+    while (ku_max > 0 && cells_for(ku_max) * fd_bytes > (256ull << 20)) --ku_max;
+    up_off = (uint32_t)ptab.size();
+    for (int k = 0; k < K && ku_max > 0; ++k) {
+      const uint32_t ku = (uint32_t)std::min((int)kp[k], ku_max);
+      if (ku == 0) continue;
+      ptab[PYR_TAB_WORDS * k + 3] = up_cells | (ku << 28);
+      for (uint32_t e = 0; e < level_first((int)ku); ++e) ptab.push_back(ptab[PYR_TAB_WORDS * k] + e);
+      up_cells += level_first((int)ku);
+    }
+  }
   const uint32_t* pyr_dev = nullptr;
   if (npyr > 0) {
     W.pyr_tab.reserve(4ull * ptab.size());
@@ -572,6 +599,10 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     W.pyr_dst.reserve(4ull * base_cells);
     W.pyr_off.reserve(4ull * (base_cells + 1));
     W.pyr_part.reserve(8ull * NMB * pyr_chunk_bound);
+    if (up_cells) {
+      W.fac_up.reserve(fd_bytes * up_cells);
+      W.up_flags.reserve(4ull * up_cells);
+    }
   }
 
   // small per-fit tables go through pinned staging: parameters, pointers,
@@ -675,6 +706,12 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       for (int d = kp_max - 1; d >= 0; --d)
         HIPCHK(launch_pyr_up(F->p, W.pyr.as<double>(), pyr_dev, pyr_dev + list_off[d], list_n[d], d, s));
     }
+    if (up_cells) {
+      ProfScope ps(KN_UPFAC, up_cells, s);
+      HIPCHK(hipMemsetAsync(W.up_flags.p, 0, 4ull * up_cells, s));
+      HIPCHK(launch_factor_cells(F->p, W.pyr.as<double>(), pyr_dev + up_off, up_cells, F->refine > 0 ? 1 : 0,
+                                 W.fac_up.as<double>(), W.up_flags.as<uint32_t>(), s));
+    }
   }
 
   // node capacity: at depth d at most min(K 8^d, N / L) nodes
@@ -745,6 +782,8 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     // path applies them where the conditioning estimate asks for them
     a.refine = F->refine == 0 ? 0 : (F->path == FMT_PATH_MIXED ? 2 : 1);
     a.pyr_tab = npyr > 0 ? pyr_dev : nullptr;
+    a.fac_up = up_cells ? W.fac_up.as<double>() : nullptr;
+    a.up_flags = up_cells ? W.up_flags.as<uint32_t>() : nullptr;
 
     const bool multi = nchunks > nnodes;   // some node spans several chunks
     if (lvl_pyr) {
@@ -761,13 +800,23 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       if (lvl_pts) HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), (uint32_t)gpd, s));
       if (lvl_pyr) HIPCHK(launch_chunk_reduce(a, W.part_m2.as<double>(), (uint32_t)rbd, s));
     }
+    // nodes whose factor was made ahead (problems with ku > d) and the others
+    uint32_t n_ahead_probs = 0;
+    for (int k = 0; k < K && up_cells; ++k)
+      if ((ptab[PYR_TAB_WORDS * k + 3] >> 28) > (uint32_t)d) ++n_ahead_probs;
     {
-      ProfScope ps(KN_SOLVE, nnodes, s);
       double* fac = F->refine > 0 ? W.fac.as<double>() : nullptr;
-      if (use_moments)
-        HIPCHK(launch_solve_moments(F->p, a, W.partial.as<double>(), W.part_m2.as<double>(), W.pyr.as<double>(),
-                                    fac, s));
-      else HIPCHK(launch_solve(F->p, a, W.partial.as<double>(), fac, s));
+      if (n_ahead_probs > 0) {
+        ProfScope ps(KN_FSOLVE, nnodes, s);
+        HIPCHK(launch_solve_ahead(F->p, a, W.part_m2.as<double>(), fac, s));
+      }
+      if (n_ahead_probs < (uint32_t)K) {
+        ProfScope ps(KN_SOLVE, nnodes, s);
+        if (use_moments)
+          HIPCHK(launch_solve_moments(F->p, a, W.partial.as<double>(), W.part_m2.as<double>(), W.pyr.as<double>(),
+                                      fac, s));
+        else HIPCHK(launch_solve(F->p, a, W.partial.as<double>(), fac, s));
+      }
     }
     for (int it = 0; it < F->refine; ++it) {
       {

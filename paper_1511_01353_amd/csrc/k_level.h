@@ -33,13 +33,20 @@ struct LevelArgs {
   // chunks per field); nfields <= 1 is one field
   uint32_t nfields = 1;
   uint64_t rstride = 0, cstride = 0;
+  // factors made ahead of the level loop for the pyramid's upper levels
+  // (k_factor_cells) and their flags; the pyramid table's word 3 holds, per
+  // problem, the first slot (low 28 bits) and the number of levels covered
+  // (high 4 bits).  Null when none were made.
+  const double* fac_up = nullptr;
+  const uint32_t* up_flags = nullptr;
 };
 
 // Grid rows of a launch over the fields of a LevelArgs.
 inline unsigned field_rows(const LevelArgs& a) { return a.nfields > 1 ? a.nfields : 1u; }
 
 // Moment pyramid tables (k_pyramid.hip).  The per-problem words: first
-// pyramid entry, depth kp (0: none), first flat finest cell, unused.
+// pyramid entry, depth kp (0: none), first flat finest cell, and the factors
+// made ahead of the level loop (first slot | levels << 28; 0: none).
 constexpr int PYR_TAB_WORDS = 4;
 struct PyrTab {
   const uint32_t* tab;      // PYR_TAB_WORDS per problem
@@ -124,6 +131,15 @@ hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, 
 // (factor_doubles(p) per node of the level), with the condition estimate
 // (a.refine == 1) and the rank flags.  No coefficients are written.
 hipError_t launch_factor_moments(int p, const LevelArgs& a, const double* part_m, double* fac, hipStream_t s);
+// Factors of n pyramid entries list[0..n) (M from the pyramid), made before
+// the level loop: slot g gets the factor of entry list[g] (factor_doubles(p)
+// doubles) and the flags of its condition estimate and deflation (up_flags
+// must hold zeros on entry).  refine as LevelArgs::refine.
+// The solve of the nodes whose factor was made ahead (a.fac_up; other nodes
+// are left to launch_solve_moments, which skips these).
+hipError_t launch_solve_ahead(int p, const LevelArgs& a, const double* part_b, double* fac, hipStream_t s);
+hipError_t launch_factor_cells(int p, const double* pyr, const uint32_t* list, uint32_t n, int refine,
+                               double* fac_up, uint32_t* up_flags, hipStream_t s);
 // F = G^-1 Lambda^T r on every node from the mode-2 partials (chunks summed
 // beforehand) and the factors of launch_factor_moments.
 hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s);

@@ -303,17 +303,25 @@ __device__ __forceinline__ double probe_entry(int i, int which, int L) {
   return ((h >> 7) & 1u ? 1.0 : -1.0) * rsqrt((double)L);
 }
 
-// With SOLVE false only the factor is made (no right-hand side): it is
-// always stored, and b, z may be null.
+// Doubles of one kept factor: [blocked L and D | D | D^-1 | scales].
+template <int L>
+__host__ __device__ constexpr size_t factor_words() {
+  return (size_t)BlockShape<L>::WORDS + 3 * (size_t)L;
+}
+
+// refine: 0 none, 1 where the estimate asks (flags the node), 2 every node.
+// coef: the node's coefficient row; flag: its flag word; fout: where the
+// factor goes (null: nowhere).  With SOLVE false only the factor is made (no
+// right-hand side; b, z and coef may be null) and it is always stored.
 template <int L, bool SOLVE = true>
 __device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dv, double* iv,
-                                                   const double* sc, double (*xv)[L], double (*yv)[L],
-                                                   const LevelArgs& a, uint32_t k, uint32_t node, double* fac) {
+                                                   const double* sc, double (*xv)[L], double (*yv)[L], int refine,
+                                                   double* coef, uint32_t* flag, double* fout) {
   using S = BlockShape<L>;
   __shared__ int need_factor;   // the refinement sweeps will apply to this node
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const bool estimate = a.refine == 1;
-  if (tid == 0) need_factor = !SOLVE || a.refine == 2;
+  const bool estimate = refine == 1;
+  if (tid == 0) need_factor = !SOLVE || refine == 2;
   if (estimate)
     for (int e = tid; e < 2 * L; e += 256) xv[e / L][e % L] = probe_entry(e % L, e / L, L);
   ldl_blocked<L>(A, dv, iv);
@@ -328,7 +336,7 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
   __syncthreads();
   bool deflated = false;
   for (int i = tid; i < L; i += 256) {
-    if constexpr (SOLVE) a.nt.coef[(size_t)node * L + i] = sc[i] * z[i];
+    if constexpr (SOLVE) coef[i] = sc[i] * z[i];
     if (iv[i] == 0.0) deflated = true;
   }
   if (estimate && (w == 1 || w == 2)) {
@@ -337,20 +345,20 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off);
     if (lane == 0 && (double)L * sqrt(ss) > REFINE_KAPPA) {
-      atomicOr(a.nt.flags + node, FLAG_REFINE);
+      atomicOr(flag, FLAG_REFINE);
       need_factor = 1;
     }
   }
-  if (a.refine == 2) {
-    if (tid == 0) atomicOr(a.nt.flags + node, FLAG_REFINE);
+  if (refine == 2) {
+    if (tid == 0) atomicOr(flag, FLAG_REFINE);
   } else if (estimate && deflated) {
-    atomicOr(a.nt.flags + node, FLAG_REFINE);
+    atomicOr(flag, FLAG_REFINE);
     need_factor = 1;
   }
   __syncthreads();
   // the factor is kept only for the nodes the refinement sweeps will visit
-  if (fac && need_factor) {
-    double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
+  if (fout && need_factor) {
+    double* fo = fout;
     for (int e = tid; e < S::WORDS; e += 256) fo[e] = A[e];
     for (int i = tid; i < L; i += 256) {
       fo[S::WORDS + i] = dv[i];
@@ -358,7 +366,7 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
       fo[S::WORDS + 2 * L + i] = sc[i];
     }
   }
-  if (deflated) atomicOr(a.nt.flags + node, FLAG_DEFLATED);
+  if (deflated) atomicOr(flag, FLAG_DEFLATED);
 }
 
 // Fill the blocked matrix in storage order: thread t writes word t of every
@@ -418,7 +426,8 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   __syncthreads();
   assemble_blocked<L>(A, [&](int i, int q) { return (i <= q ? gram(i, q) : gram(q, i)) * sc[i] * sc[q]; });
   __syncthreads();
-  factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a, k, node, fac);
+  factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a.refine, a.nt.coef + (size_t)node * L, a.nt.flags + node,
+                        fac ? fac + (size_t)k * factor_words<L>() : nullptr);
 }
 
 // Equilibrated normal equations from power moments in LDS: mom[0 .. NM) the
@@ -507,6 +516,7 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   const uint32_t node = a.node0 + k;
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   const uint32_t* pt = a.pyr_tab ? a.pyr_tab + PYR_TAB_WORDS * a.nt.problem[node] : nullptr;
+  if (pt && a.fac_up && (pt[3] >> 28) > (uint32_t)a.level) return;   // factored ahead: k_solve_ahead
   if (pt && pyramid_covers(pt[1], a.level)) {
     // M from the pyramid cell, B from the node's B-only partial; all loads
     // issued before the first store
@@ -530,7 +540,53 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   }
   assemble_moments<P>(A, mom, mom + NM, b, sc, wv, ex);
   __syncthreads();
-  factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a, k, node, fac);
+  factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a.refine, a.nt.coef + (size_t)node * L, a.nt.flags + node,
+                        fac ? fac + (size_t)k * factor_words<L>() : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// K6 for the nodes whose factor was made ahead of the level loop
+// (k_factor_cells): B from the node's mode-2 partial, scaled as the
+// assembly scales it, and the two triangular solves with the kept factor;
+// the factor's flags go to the node, and the factor itself to the level's
+// refinement slot where the estimate asked for refinement.  Other nodes exit.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256) k_solve_ahead(LevelArgs a, const double* __restrict__ part_b,
+                                                     double* __restrict__ fac) {
+  constexpr int L = basis_size(P);
+  constexpr size_t FW = factor_words<L>();
+  constexpr Basis<P> B{};
+  using S = BlockShape<L>;
+  __shared__ double A[S::WORDS + 16];   // + the zero row
+  __shared__ double b[L], z[L], iv[S::LP], sc[L];
+  const int tid = threadIdx.x;
+  const uint32_t k = blockIdx.x;
+  const uint32_t node = a.node0 + k;
+  const uint32_t* pt = a.pyr_tab + PYR_TAB_WORDS * a.nt.problem[node];
+  if (!((pt[3] >> 28) > (uint32_t)a.level)) return;   // whole workgroup: factored in this level's k_solve_m
+  const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
+  const uint32_t slot = (pt[3] & 0x0FFFFFFFu) + level_first(a.level) + a.nt.prefix[node];
+  const double* fo = a.fac_up + (size_t)slot * FW;
+  const double* bs = part_b + (size_t)c0 * L;
+  copy_to_lds<256, S::WORDS>(A, fo, tid);
+  if (tid < 16) A[S::WORDS + tid] = 0.0;
+  for (int i = tid; i < L; i += 256) {
+    iv[i] = fo[S::WORDS + L + i];
+    sc[i] = fo[S::WORDS + 2 * L + i];
+    b[i] = bs[i] * sc[i] * B.inv_fact[i];   // as assemble_moments scales it
+  }
+  __syncthreads();
+  if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
+  __syncthreads();
+  for (int i = tid; i < L; i += 256) a.nt.coef[(size_t)node * L + i] = sc[i] * z[i];
+  const uint32_t fl = a.up_flags[slot];
+  if (tid == 0 && fl) atomicOr(a.nt.flags + node, fl);
+  // keep the factor where the refinement looks for it
+  if (fac && (fl & FLAG_REFINE)) {
+    double* fk = fac + (size_t)k * FW;
+    for (size_t e = tid; e < FW; e += 256) fk[e] = fo[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -557,7 +613,36 @@ __global__ void __launch_bounds__(256) k_factor_m(LevelArgs a, const double* __r
   copy_to_lds<256, NM>(mom, part_m + (size_t)a.chunk_off[k] * NM, tid);
   assemble_moments<P>(A, mom, nullptr, nullptr, sc, wv, ex);
   __syncthreads();
-  factor_solve_store<L, false>(A, nullptr, nullptr, dv, iv, sc, xv, yv, a, k, node, fac);
+  factor_solve_store<L, false>(A, nullptr, nullptr, dv, iv, sc, xv, yv, a.refine, nullptr, a.nt.flags + node,
+                               fac + (size_t)k * factor_words<L>());
+}
+
+// ---------------------------------------------------------------------------
+// Factors made ahead of the level loop: one workgroup per listed pyramid
+// entry (a cell of a level above the pyramid's finest), its M taken from
+// the pyramid, the factor and the flags of its condition estimate stored in
+// slot g.  The level's solve then only applies them (k_solve_m).
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256) k_factor_cells(const double* __restrict__ pyr,
+                                                      const uint32_t* __restrict__ list, int refine,
+                                                      double* __restrict__ fac_up, uint32_t* __restrict__ up_flags) {
+  constexpr int L = basis_size(P);
+  constexpr int NM = basis_size(2 * P);
+  using S = BlockShape<L>;
+  __shared__ double A[S::WORDS + 16];   // + the zero row
+  __shared__ double mom[NM > 4 * L ? NM : 4 * L];
+  __shared__ double dv[S::LP], iv[S::LP], sc[L], wv[L];
+  __shared__ int ex[L][3];
+  double(*xv)[L] = reinterpret_cast<double(*)[L]>(mom);
+  double(*yv)[L] = reinterpret_cast<double(*)[L]>(mom + 2 * L);
+  const int tid = threadIdx.x;
+  const uint32_t g = blockIdx.x;
+  copy_to_lds<256, NM>(mom, pyr + (size_t)list[g] * NM, tid);
+  assemble_moments<P>(A, mom, nullptr, nullptr, sc, wv, ex);
+  __syncthreads();
+  factor_solve_store<L, false>(A, nullptr, nullptr, dv, iv, sc, xv, yv, refine, nullptr, up_flags + g,
+                               fac_up + (size_t)g * factor_words<L>());
 }
 
 // ---------------------------------------------------------------------------
@@ -966,6 +1051,28 @@ static hipError_t factor_m_impl(const LevelArgs& a, const double* part_m, double
 }
 hipError_t launch_factor_moments(int p, const LevelArgs& a, const double* part_m, double* fac, hipStream_t s) {
   FMT_DISPATCH_P(p, factor_m_impl, a, part_m, fac, s);
+}
+
+template <int P>
+static hipError_t ahead_impl(const LevelArgs& a, const double* part_b, double* fac, hipStream_t s) {
+  if (a.nnodes == 0 || !a.fac_up || !a.pyr_tab) return hipSuccess;
+  hipLaunchKernelGGL(k_solve_ahead<P>, dim3(a.nnodes), dim3(256), 0, s, a, part_b, fac);
+  return hipGetLastError();
+}
+hipError_t launch_solve_ahead(int p, const LevelArgs& a, const double* part_b, double* fac, hipStream_t s) {
+  FMT_DISPATCH_P(p, ahead_impl, a, part_b, fac, s);
+}
+
+template <int P>
+static hipError_t fcells_impl(const double* pyr, const uint32_t* list, uint32_t n, int refine, double* fac_up,
+                              uint32_t* up_flags, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_factor_cells<P>, dim3(n), dim3(256), 0, s, pyr, list, refine, fac_up, up_flags);
+  return hipGetLastError();
+}
+hipError_t launch_factor_cells(int p, const double* pyr, const uint32_t* list, uint32_t n, int refine,
+                               double* fac_up, uint32_t* up_flags, hipStream_t s) {
+  FMT_DISPATCH_P(p, fcells_impl, pyr, list, n, refine, fac_up, up_flags, s);
 }
 
 template <int P>
