@@ -790,6 +790,32 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
         (double)(redc[0][tid - 8] + redc[1][tid - 8] + redc[2][tid - 8] + redc[3][tid - 8]);
 }
 
+// Exclusive prefix sum of one value per thread over a 1024-thread workgroup:
+// inclusive scans inside each wave (shuffles), then the wave totals from LDS.
+// Returns the thread's exclusive prefix and sets total; wsum holds 16 words.
+// Every thread must call it (two barriers inside).
+__device__ __forceinline__ uint32_t scan_1024(uint32_t x, uint32_t* wsum, uint32_t& total) {
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint32_t v = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)v, o);
+    if (lane >= (uint32_t)o) v += y;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  uint32_t base = 0, all = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < 16; ++q) {
+    const uint32_t t = wsum[q];
+    base += q < w ? t : 0u;
+    all += t;
+  }
+  __syncthreads();   // wsum may be reused after this
+  total = all;
+  return base + v - x;
+}
+
 // ---------------------------------------------------------------------------
 // Child activation (Alg. 1): octant o of a node at depth d becomes a node iff
 // d + 1 <= D, n_o >= calL (tested first) and sqrt(sum r^2 / n_o) > tol.
@@ -894,25 +920,17 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
                                                uint32_t* __restrict__ next_chunk_off,
                                                uint32_t* __restrict__ counters, uint32_t* __restrict__ hostc,
                                                uint32_t seq) {
-  __shared__ uint32_t s[1024];
+  __shared__ uint32_t wsum[16];
   const uint32_t tid = threadIdx.x;
   const uint32_t m = a.nnodes;
   const uint32_t seg = (m + 1023u) / 1024u;
   const uint32_t b = min(m, tid * seg), e = min(m, b + seg);
   uint32_t sum = 0;
   for (uint32_t i = b; i < e; ++i) sum += nact[i];
-  s[tid] = sum;
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    uint32_t v = tid >= off ? s[tid - off] : 0u;
-    __syncthreads();
-    s[tid] += v;
-    __syncthreads();
-  }
-  const uint32_t total = s[1023];
+  uint32_t total;
   // each node's first child index (exclusive prefix of the active counts),
   // in place of its count
-  uint32_t run = s[tid] - sum;
+  uint32_t run = scan_1024(sum, wsum, total);
   for (uint32_t i = b; i < e; ++i) {
     const uint32_t v = nact[i];
     nact[i] = run;
@@ -947,45 +965,31 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     pts += cn;
   }
   __syncthreads();
-  // total points of the next level (fixed-order integer sum)
-  s[tid] = pts;
-  __syncthreads();
-  for (uint32_t off = 512; off >= 1; off >>= 1) {
-    if (tid < off) s[tid] += s[tid + off];
-    __syncthreads();
-  }
-  const uint32_t next_points = s[0];
-  __syncthreads();
+  // total points of the next level (integer sum: exact in any order)
+  uint32_t next_points;
+  (void)scan_1024(pts, wsum, next_points);
   // exclusive scan of the children's chunk counts
   const uint32_t seg2 = (total + 1023u) / 1024u;
   const uint32_t b2 = min(total, tid * seg2), e2 = min(total, b2 + seg2);
   uint32_t sum2 = 0;
   for (uint32_t i = b2; i < e2; ++i) sum2 += next_chunk_off[i];
-  __syncthreads();
-  s[tid] = sum2;
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    uint32_t v = tid >= off ? s[tid - off] : 0u;
-    __syncthreads();
-    s[tid] += v;
-    __syncthreads();
-  }
-  uint32_t run2 = s[tid] - sum2;
+  uint32_t nchunks_next;
+  uint32_t run2 = scan_1024(sum2, wsum, nchunks_next);
   for (uint32_t i = b2; i < e2; ++i) {
     const uint32_t v = next_chunk_off[i];
     next_chunk_off[i] = run2;
     run2 += v;
   }
   if (tid == 1023) {
-    next_chunk_off[total] = s[1023];
+    next_chunk_off[total] = nchunks_next;
     counters[0] = total;
-    counters[1] = s[1023];
+    counters[1] = nchunks_next;
     counters[2] = next_points;
     if (hostc) {
       // the same counters into host-visible (fine-grained) memory, then the
       // sequence number with a system-scope release: the host waits on it
       hostc[0] = total;
-      hostc[1] = s[1023];
+      hostc[1] = nchunks_next;
       hostc[2] = next_points;
       __hip_atomic_store(hostc + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
