@@ -131,13 +131,13 @@ hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, 
 // (factor_doubles(p) per node of the level), with the condition estimate
 // (a.refine == 1) and the rank flags.  No coefficients are written.
 hipError_t launch_factor_moments(int p, const LevelArgs& a, const double* part_m, double* fac, hipStream_t s);
+// The solve of the nodes whose factor was made ahead (a.fac_up; other nodes
+// are left to launch_solve_moments, which skips these).
+hipError_t launch_solve_ahead(int p, const LevelArgs& a, const double* part_b, double* fac, hipStream_t s);
 // Factors of n pyramid entries list[0..n) (M from the pyramid), made before
 // the level loop: slot g gets the factor of entry list[g] (factor_doubles(p)
 // doubles) and the flags of its condition estimate and deflation (up_flags
 // must hold zeros on entry).  refine as LevelArgs::refine.
-// The solve of the nodes whose factor was made ahead (a.fac_up; other nodes
-// are left to launch_solve_moments, which skips these).
-hipError_t launch_solve_ahead(int p, const LevelArgs& a, const double* part_b, double* fac, hipStream_t s);
 hipError_t launch_factor_cells(int p, const double* pyr, const uint32_t* list, uint32_t n, int refine,
                                double* fac_up, uint32_t* up_flags, hipStream_t s);
 // F = G^-1 Lambda^T r on every node from the mode-2 partials (chunks summed
