@@ -252,6 +252,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 17)
     ap.add_argument("--refit-fields", type=int, default=8,
                     help="value fields of the fixed-topology refit leg (0: skip it)")
+    ap.add_argument("--refit-only", action="store_true",
+                    help="run only the refit leg and print its object (for profiling it alone)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device to device (a plain copy kernel of known size "
                          "against which hardware byte counters are scaled)")
@@ -280,6 +282,11 @@ def main():
     QX, QY, QZ = dev(pr.qx), dev(pr.qy), dev(pr.qz)
     out = torch.empty(args.nq, dtype=torch.float64, device="cuda")
     L = (pr.p + 1) * (pr.p + 2) * (pr.p + 3) // 6
+    if args.refit_only:
+        opts = fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth, refine_steps=args.fp64_refine)
+        print(json.dumps({"refit": refit_leg(fmt, opts, X, Y, Z, pr, max(1, args.refit_fields), args.steps,
+                                             args.warmup)}))
+        return
     paths = [args.path] if args.no_compare else [args.path] + [p for p in ("fp64", "mixed") if p != args.path]
     results = {}
     for path in paths:
