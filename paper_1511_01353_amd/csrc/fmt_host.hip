@@ -186,13 +186,16 @@ struct DevBuf {
 struct Workspace {
   // px, py, pz, pf: key-ordered inputs (payload set A); px2 .. pf2: set B
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
-  DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status, params, ptrs;
-  // moment pyramid: entries, tables, the finest cells' point ranges,
-  // frames, chunk counts, entries, chunk offsets and chunk partials; the
-  // B-only partials of the levels it covers
-  DevBuf pyr, pyr_tab, pyr_begin, pyr_count, pyr_geo, pyr_nchk, pyr_dst, pyr_off, pyr_part, part_m2;
+  DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status;
+  // a fit's small tables (parameters, pointers, pyramid table, level-0 chunk
+  // offsets, status word, flags of the factors made ahead), filled by one copy
+  DevBuf small;
+  // moment pyramid: entries, the finest cells' point ranges (begin, then
+  // count), frames, chunk counts, entries, chunk offsets and chunk partials;
+  // the B-only partials of the levels it covers
+  DevBuf pyr, pyr_begin, pyr_geo, pyr_nchk, pyr_dst, pyr_off, pyr_part, part_m2;
   // factors of the pyramid's upper levels made ahead of the level loop
-  DevBuf fac_up, up_flags;
+  DevBuf fac_up;
   uint32_t* host_counters = nullptr;
   // host-visible, fine-grained words the topology kernel writes the next
   // level's counters and a sequence number into (host view and device view)
@@ -500,9 +503,6 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   W.vals_alt.reserve(4ull * N);
   W.sort_scratch.reserve(4 * radix_sort_scratch_words(N));
   for (DevBuf* b : {&W.px, &W.py, &W.pz, &W.pf, &W.px2, &W.py2, &W.pz2, &W.pf2}) b->reserve(esz * N);
-  W.params.reserve(sizeof(ProblemParams) * K);
-  W.ptrs.reserve(sizeof(PtrSet) * K);
-  W.status.reserve(64);
   W.counters.reserve(64);
 
   // Moment pyramid of each problem (float64 power-moment path): its depth
@@ -587,39 +587,41 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       up_cells += level_first((int)ku);
     }
   }
-  const uint32_t* pyr_dev = nullptr;
   if (npyr > 0) {
-    W.pyr_tab.reserve(4ull * ptab.size());
-    pyr_dev = W.pyr_tab.as<uint32_t>();
     W.pyr.reserve(8ull * NMB * pyr_cells);
-    W.pyr_begin.reserve(4ull * base_cells);
-    W.pyr_count.reserve(4ull * base_cells);
+    W.pyr_begin.reserve(8ull * base_cells);   // begin, then count
     W.pyr_geo.reserve(48ull * base_cells);
     W.pyr_nchk.reserve(4ull * base_cells);
     W.pyr_dst.reserve(4ull * base_cells);
     W.pyr_off.reserve(4ull * (base_cells + 1));
     W.pyr_part.reserve(8ull * NMB * pyr_chunk_bound);
-    if (up_cells) {
-      W.fac_up.reserve(fd_bytes * up_cells);
-      W.up_flags.reserve(4ull * up_cells);
-    }
+    if (up_cells) W.fac_up.reserve(fd_bytes * up_cells);
   }
 
-  // small per-fit tables go through pinned staging: parameters, pointers,
-  // the pyramid table, then the level-0 chunk offsets
+  // The small per-fit tables go to the device in one copy from pinned
+  // staging: parameters, pointers, the pyramid table, the level-0 chunk
+  // offsets, and zeros for the status word and the ahead factors' flags.
+  std::vector<uint32_t> off0(K + 1, 0);
+  for (int k = 0; k < K; ++k) off0[k + 1] = off0[k] + (uint32_t)((in[k].n + CHUNK - 1) / CHUNK);
+  auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t prm_b = sizeof(ProblemParams) * K, ptr_b = sizeof(PtrSet) * K, off_b = 4ull * (K + 1);
   const size_t tab_b = 4ull * ptab.size();
-  char* stg = W.staging(prm_b + ptr_b + tab_b + off_b);
+  const size_t o_ptr = al256(prm_b), o_tab = o_ptr + al256(ptr_b), o_off = o_tab + al256(tab_b);
+  const size_t o_st = o_off + al256(off_b), o_up = o_st + 256, n_small = o_up + al256(4ull * up_cells);
+  W.small.reserve(n_small);
+  char* stg = W.staging(n_small);
   std::memcpy(stg, prm.data(), prm_b);
-  std::memcpy(stg + prm_b, ptrs.data(), ptr_b);
-  HIPCHK(hipMemcpyAsync(W.params.p, stg, prm_b, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(W.ptrs.p, stg + prm_b, ptr_b, hipMemcpyHostToDevice, s));
-  if (tab_b) {
-    std::memcpy(stg + prm_b + ptr_b, ptab.data(), tab_b);
-    HIPCHK(hipMemcpyAsync(W.pyr_tab.p, stg + prm_b + ptr_b, tab_b, hipMemcpyHostToDevice, s));
-  }
-  HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
-  const ProblemParams* d_prm = W.params.as<ProblemParams>();
+  std::memcpy(stg + o_ptr, ptrs.data(), ptr_b);
+  if (tab_b) std::memcpy(stg + o_tab, ptab.data(), tab_b);
+  std::memcpy(stg + o_off, off0.data(), off_b);
+  std::memset(stg + o_st, 0, n_small - o_st);
+  HIPCHK(hipMemcpyAsync(W.small.p, stg, n_small, hipMemcpyHostToDevice, s));
+  char* sm = W.small.as<char>();
+  const ProblemParams* d_prm = reinterpret_cast<const ProblemParams*>(sm);
+  const PtrSet* d_ptrs = reinterpret_cast<const PtrSet*>(sm + o_ptr);
+  const uint32_t* pyr_dev = npyr > 0 ? reinterpret_cast<const uint32_t*>(sm + o_tab) : nullptr;
+  uint32_t* d_status = reinterpret_cast<uint32_t*>(sm + o_st);
+  uint32_t* d_upflags = reinterpret_cast<uint32_t*>(sm + o_up);
 
   // K1 keys, K2 sort with the inputs as payload (K3: the sort itself leaves
   // them in key order).  With an odd number of sort passes the keys start in
@@ -636,7 +638,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   if (K > 1) cat = PtrSet{W.px.p, W.py.p, W.pz.p, W.pf.p};
   {
     ProfScope ps(KN_KEYGEN, N, s);
-    HIPCHK(launch_keygen(dtype, W.ptrs.as<PtrSet>(), d_prm, K, F->D, N, k_in, W.status.as<uint32_t>(), cat, s));
+    HIPCHK(launch_keygen(dtype, d_ptrs, d_prm, K, F->D, N, k_in, d_status, cat, s));
   }
   bool in_alt = false;
   {
@@ -672,10 +674,9 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     PyrTab pt{pyr_dev, cst, cst + npyr + 1, (uint32_t)npyr};
     {
       ProfScope ps(KN_PYR, nbc, s);
-      HIPCHK(hipMemsetAsync(W.pyr_begin.p, 0, 4ull * nbc, s));
-      HIPCHK(hipMemsetAsync(W.pyr_count.p, 0, 4ull * nbc, s));
+      HIPCHK(hipMemsetAsync(W.pyr_begin.p, 0, 8ull * nbc, s));   // begin and count
       HIPCHK(launch_pyr_cells(F->skey.as<uint32_t>(), N, F->D, K, d_prm, pt, nbc, W.pyr_begin.as<uint32_t>(),
-                              W.pyr_count.as<uint32_t>(), W.pyr_geo.as<double>(), W.pyr_nchk.as<uint32_t>(),
+                              W.pyr_begin.as<uint32_t>() + nbc, W.pyr_geo.as<double>(), W.pyr_nchk.as<uint32_t>(),
                               W.pyr_dst.as<uint32_t>(), s));
       HIPCHK(launch_pyr_scan(W.pyr_nchk.as<uint32_t>(), nbc, W.pyr_off.as<uint32_t>(), s));
     }
@@ -684,7 +685,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       ProfScope ps(KN_BASEM, N, s);
       LevelArgs c{};
       c.nt.begin = W.pyr_begin.as<uint32_t>();
-      c.nt.count = W.pyr_count.as<uint32_t>();
+      c.nt.count = W.pyr_begin.as<uint32_t>() + nbc;
       c.nt.geo = W.pyr_geo.as<double>();
       c.node0 = 0;
       c.nnodes = nbc;
@@ -708,9 +709,8 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     }
     if (up_cells) {
       ProfScope ps(KN_UPFAC, up_cells, s);
-      HIPCHK(hipMemsetAsync(W.up_flags.p, 0, 4ull * up_cells, s));
       HIPCHK(launch_factor_cells(F->p, W.pyr.as<double>(), pyr_dev + up_off, up_cells, F->refine > 0 ? 1 : 0,
-                                 W.fac_up.as<double>(), W.up_flags.as<uint32_t>(), s));
+                                 W.fac_up.as<double>(), d_upflags, s));
     }
   }
 
@@ -727,19 +727,15 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   NodeTable nt = tmp.table();
   HIPCHK(launch_roots(nt, d_prm, K, s));
 
-  // level 0 chunk offsets
-  std::vector<uint32_t> off0(K + 1, 0);
-  for (int k = 0; k < K; ++k) off0[k + 1] = off0[k] + (uint32_t)((in[k].n + CHUNK - 1) / CHUNK);
-  W.chunk_a.reserve(4ull * (K + 1));
-  std::memcpy(stg + prm_b + ptr_b + tab_b, off0.data(), off_b);
-  HIPCHK(hipMemcpyAsync(W.chunk_a.p, stg + prm_b + ptr_b + tab_b, off_b, hipMemcpyHostToDevice, s));
 
   uint32_t nnodes = (uint32_t)K, nchunks = off0[K], node0 = 0;
   uint32_t level_points = N;
   F->level_start.clear();
   F->level_count.clear();
-  DevBuf* cur_off = &W.chunk_a;
-  DevBuf* next_off = &W.chunk_b;
+  // chunk offsets: level 0's from the staged tables, then chunk_a and
+  // chunk_b in turn
+  const uint32_t* cur_off = reinterpret_cast<const uint32_t*>(sm + o_off);
+  DevBuf* next_off = &W.chunk_a;
   const size_t gpd = use_moments ? moment_partial_doubles(F->p) : gram_partial_doubles(F->p);
   const size_t fd = factor_doubles(F->p);
   const size_t rbd = moment_refine_doubles(F->p);
@@ -768,7 +764,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     a.nt = nt;
     a.node0 = node0;
     a.nnodes = nnodes;
-    a.chunk_off = cur_off->as<uint32_t>();
+    a.chunk_off = cur_off;
     a.nchunks = nchunks;
     a.px = W.px.p;
     a.py = W.py.p;
@@ -783,7 +779,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     a.refine = F->refine == 0 ? 0 : (F->path == FMT_PATH_MIXED ? 2 : 1);
     a.pyr_tab = npyr > 0 ? pyr_dev : nullptr;
     a.fac_up = up_cells ? W.fac_up.as<double>() : nullptr;
-    a.up_flags = up_cells ? W.up_flags.as<uint32_t>() : nullptr;
+    a.up_flags = up_cells ? d_upflags : nullptr;
 
     const bool multi = nchunks > nnodes;   // some node spans several chunks
     if (lvl_pyr) {
@@ -858,11 +854,12 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     nnodes = cnt[0];
     nchunks = cnt[1];
     level_points = cnt[2];
-    std::swap(cur_off, next_off);
+    cur_off = next_off->as<uint32_t>();
+    next_off = next_off == &W.chunk_a ? &W.chunk_b : &W.chunk_a;
   }
   F->nodes = node0;
   F->depth_present = (int)F->level_start.size() - 1;
-  HIPCHK(launch_check_coef(F->p, nt, F->nodes, W.status.as<uint32_t>(), s));
+  HIPCHK(launch_check_coef(F->p, nt, F->nodes, d_status, s));
 
   // hand the node table to the forest; copy it down to its exact size only
   // when the capacity bound would hold much more memory than the nodes need
@@ -882,7 +879,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     cp(F->nb_geo, tmp.nb_geo, 48ull * F->nodes);
     cp(F->nb_coef, tmp.nb_coef, 8ull * L * F->nodes);
   }
-  HIPCHK(hipMemcpyAsync(W.host_counters + 4, W.status.p, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(W.host_counters + 4, d_status, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   F->device_status = W.host_counters[4];
 
