@@ -663,7 +663,9 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   }
   {
     ProfScope ps(KN_GATHER, N, s);
-    HIPCHK(launch_widen(dtype, W.pf.p, N, F->resid.as<double>(), s));
+    // the pyramid's finest-cell ranges (begin, then count) are cleared here too
+    HIPCHK(launch_widen(dtype, W.pf.p, N, F->resid.as<double>(), npyr > 0 ? W.pyr_begin.as<uint32_t>() : nullptr,
+                        npyr > 0 ? 2 * (uint32_t)base_cells : 0u, s));
   }
 
   if (npyr > 0) {
@@ -674,7 +676,6 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     PyrTab pt{pyr_dev, cst, cst + npyr + 1, (uint32_t)npyr};
     {
       ProfScope ps(KN_PYR, nbc, s);
-      HIPCHK(hipMemsetAsync(W.pyr_begin.p, 0, 8ull * nbc, s));   // begin and count
       HIPCHK(launch_pyr_cells(F->skey.as<uint32_t>(), N, F->D, K, d_prm, pt, nbc, W.pyr_begin.as<uint32_t>(),
                               W.pyr_begin.as<uint32_t>() + nbc, W.pyr_geo.as<double>(), W.pyr_nchk.as<uint32_t>(),
                               W.pyr_dst.as<uint32_t>(), s));
@@ -780,6 +781,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     a.pyr_tab = npyr > 0 ? pyr_dev : nullptr;
     a.fac_up = up_cells ? W.fac_up.as<double>() : nullptr;
     a.up_flags = up_cells ? d_upflags : nullptr;
+    a.status = d_status;
 
     const bool multi = nchunks > nnodes;   // some node spans several chunks
     if (lvl_pyr) {
@@ -859,7 +861,6 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   }
   F->nodes = node0;
   F->depth_present = (int)F->level_start.size() - 1;
-  HIPCHK(launch_check_coef(F->p, nt, F->nodes, d_status, s));
 
   // hand the node table to the forest; copy it down to its exact size only
   // when the capacity bound would hold much more memory than the nodes need

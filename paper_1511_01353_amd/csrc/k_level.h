@@ -39,6 +39,9 @@ struct LevelArgs {
   // (high 4 bits).  Null when none were made.
   const double* fac_up = nullptr;
   const uint32_t* up_flags = nullptr;
+  // status word: the solves mark nodes whose coefficients are not all finite
+  // (FLAG_NONFINITE) and set bit 2 here; null: no check
+  uint32_t* status = nullptr;
 };
 
 // Grid rows of a launch over the fields of a LevelArgs.

@@ -56,6 +56,18 @@ __device__ __forceinline__ double pivot_recip(double d) {
   return fma(x, e, x);
 }
 
+// With a status word, a node's coefficients that are not all finite mark the
+// node (FLAG_NONFINITE) and the fit (status bit 2); `bad` is this thread's
+// finding for the coefficients it wrote.  Callers test with isfinite: the
+// test c - c == 0 on a product just computed may be contracted into a fused
+// multiply-add that returns the product's rounding error.
+__device__ __forceinline__ void mark_nonfinite(bool bad, uint32_t* flag, uint32_t* status) {
+  if (status && bad) {
+    atomicOr(flag, FLAG_NONFINITE);
+    atomicOr(status, 2u);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Right-looking blocked LDL^T factorisation of the unit-diagonal matrix A
 // (blocked storage, padding rows/columns set to the identity), in place, by
@@ -316,7 +328,8 @@ __host__ __device__ constexpr size_t factor_words() {
 template <int L, bool SOLVE = true>
 __device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dv, double* iv,
                                                    const double* sc, double (*xv)[L], double (*yv)[L], int refine,
-                                                   double* coef, uint32_t* flag, double* fout) {
+                                                   double* coef, uint32_t* flag, double* fout,
+                                                   uint32_t* status = nullptr) {
   using S = BlockShape<L>;
   __shared__ int need_factor;   // the refinement sweeps will apply to this node
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -334,11 +347,16 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
     tri_solve_wave<L>(A, iv, xv[w - 1], yv[w - 1]);
   }
   __syncthreads();
-  bool deflated = false;
+  bool deflated = false, bad = false;
   for (int i = tid; i < L; i += 256) {
-    if constexpr (SOLVE) coef[i] = sc[i] * z[i];
+    if constexpr (SOLVE) {
+      const double c = sc[i] * z[i];
+      coef[i] = c;
+      bad |= !__builtin_isfinite(c);
+    }
     if (iv[i] == 0.0) deflated = true;
   }
+  if constexpr (SOLVE) mark_nonfinite(bad, flag, status);
   if (estimate && (w == 1 || w == 2)) {
     double ss = 0.0;
     for (int i = lane; i < L; i += 64) ss += yv[w - 1][i] * yv[w - 1][i];
@@ -427,7 +445,7 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   assemble_blocked<L>(A, [&](int i, int q) { return (i <= q ? gram(i, q) : gram(q, i)) * sc[i] * sc[q]; });
   __syncthreads();
   factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a.refine, a.nt.coef + (size_t)node * L, a.nt.flags + node,
-                        fac ? fac + (size_t)k * factor_words<L>() : nullptr);
+                        fac ? fac + (size_t)k * factor_words<L>() : nullptr, a.status);
 }
 
 // Equilibrated normal equations from power moments in LDS: mom[0 .. NM) the
@@ -541,7 +559,7 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   assemble_moments<P>(A, mom, mom + NM, b, sc, wv, ex);
   __syncthreads();
   factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a.refine, a.nt.coef + (size_t)node * L, a.nt.flags + node,
-                        fac ? fac + (size_t)k * factor_words<L>() : nullptr);
+                        fac ? fac + (size_t)k * factor_words<L>() : nullptr, a.status);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,7 +597,13 @@ __global__ void __launch_bounds__(256) k_solve_ahead(LevelArgs a, const double* 
   __syncthreads();
   if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
   __syncthreads();
-  for (int i = tid; i < L; i += 256) a.nt.coef[(size_t)node * L + i] = sc[i] * z[i];
+  bool bad = false;
+  for (int i = tid; i < L; i += 256) {
+    const double c = sc[i] * z[i];
+    a.nt.coef[(size_t)node * L + i] = c;
+    bad |= !__builtin_isfinite(c);
+  }
+  mark_nonfinite(bad, a.nt.flags + node, a.status);
   const uint32_t fl = a.up_flags[slot];
   if (tid == 0 && fl) atomicOr(a.nt.flags + node, fl);
   // keep the factor where the refinement looks for it
@@ -702,7 +726,13 @@ __device__ __forceinline__ void solve_with_factor(const LevelArgs& a, const doub
   if (tid < 64) tri_solve_wave<L>(A, iv, b, z);
   __syncthreads();
   double* F = a.nt.coef + (size_t)blockIdx.y * a.cstride + (size_t)node * L;
-  for (int i = tid; i < L; i += 256) F[i] = FIRST ? sc[i] * z[i] : F[i] + sc[i] * z[i];
+  bool bad = false;
+  for (int i = tid; i < L; i += 256) {
+    const double c = FIRST ? sc[i] * z[i] : F[i] + sc[i] * z[i];
+    F[i] = c;
+    bad |= !__builtin_isfinite(c);
+  }
+  mark_nonfinite(bad, a.nt.flags + node, a.status);
 }
 
 template <int P>

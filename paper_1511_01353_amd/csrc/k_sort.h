@@ -46,8 +46,10 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32
 hipError_t radix_sort_payload(int dtype, int np, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                               uint32_t* vals_alt, const void* const* pin, void* const* pay, void* const* pay_alt,
                               uint32_t n, int bits, uint32_t* scratch, hipStream_t s, bool* result_in_alt);
-// r[i] = (double)f[i]
-hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, hipStream_t s);
+// r[i] = (double)f[i] for i < n, and zero[j] = 0 for j < nzero (a clear of
+// small tables folded into the same launch)
+hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, uint32_t* zero, uint32_t nzero,
+                        hipStream_t s);
 
 // The points of one problem of a fitted forest in its key order, for a
 // fixed-topology refit: px[i] = x[order[off + i] - off] (likewise y, z) for

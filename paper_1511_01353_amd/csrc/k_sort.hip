@@ -555,17 +555,21 @@ hipError_t radix_sort_payload(int dtype, int np, uint32_t* keys, uint32_t* vals,
 
 // residual start: the sorted values, widened to float64
 template <typename T>
-__global__ void __launch_bounds__(256) k_widen(const T* __restrict__ f, uint32_t n, double* __restrict__ r) {
+__global__ void __launch_bounds__(256) k_widen(const T* __restrict__ f, uint32_t n, double* __restrict__ r,
+                                               uint32_t* __restrict__ zero, uint32_t nzero) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) r[i] = (double)f[i];
+  for (uint32_t j = i; j < nzero; j += gridDim.x * blockDim.x) zero[j] = 0u;
 }
 
-hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, hipStream_t s) {
-  if (n == 0) return hipSuccess;
+hipError_t launch_widen(int dtype, const void* f, uint32_t n, double* r, uint32_t* zero, uint32_t nzero,
+                        hipStream_t s) {
+  if (n == 0 && nzero == 0) return hipSuccess;
+  const unsigned grid = blocks_for(n > nzero ? n : nzero, 256);
   if (dtype == FMT_F32)
-    hipLaunchKernelGGL(k_widen<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const float*)f, n, r);
+    hipLaunchKernelGGL(k_widen<float>, dim3(grid), dim3(256), 0, s, (const float*)f, n, r, zero, nzero);
   else
-    hipLaunchKernelGGL(k_widen<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const double*)f, n, r);
+    hipLaunchKernelGGL(k_widen<double>, dim3(grid), dim3(256), 0, s, (const double*)f, n, r, zero, nzero);
   return hipGetLastError();
 }
 
