@@ -260,6 +260,16 @@ def test_errors(fmt):
     with pytest.raises(fmt.FmtError) as e:
         fmt.fmt_fit(fmt.fmt_default_opts(p=2), dev(x2), dev(y), dev(z), dev(f))
     assert e.value.status == fmt.FMT_E_DOMAIN
+    # a non-finite value gives non-finite coefficients: NUMERIC on every path
+    pr = synthetic.small_problem(20000, 3, 5, tol=1e-8, depth=3, dtype=np.float64)
+    for bad in (np.nan, np.inf):
+        fb = pr.f.copy()
+        fb[777] = bad
+        for kw in (dict(), dict(gram=fmt.FMT_GRAM_MOMENTS_LEVEL), dict(path=fmt.FMT_PATH_MIXED)):
+            o = fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth, **kw)
+            with pytest.raises(fmt.FmtError) as e:
+                fmt.fmt_fit(o, dev(pr.x), dev(pr.y), dev(pr.z), dev(fb))
+            assert e.value.status == fmt.FMT_E_NUMERIC, (bad, kw)
 
 
 def test_deterministic(fmt):

@@ -159,6 +159,11 @@ def test_refit_errors(fmt):
     with pytest.raises(fmt.FmtError) as e:   # an imported tree holds no points
         fmt.fmt_refit(ti, dev(pr.x), dev(pr.y), dev(pr.z), dev(f))
     assert e.value.status == fmt.FMT_E_INVALID_ARG
+    fb = f.copy()
+    fb[0, 123] = np.nan
+    with pytest.raises(fmt.FmtError) as e:   # a non-finite value
+        fmt.fmt_refit(tr, dev(pr.x), dev(pr.y), dev(pr.z), dev(fb))
+    assert e.value.status == fmt.FMT_E_NUMERIC
     # the tree still refits after the failures
     (out,) = refit(fmt, tr, pr, f)
     same_topology(out, tr)
