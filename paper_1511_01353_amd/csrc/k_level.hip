@@ -675,13 +675,9 @@ __global__ void __launch_bounds__(256) k_factor_cells(const double* __restrict__
 // sums its node's chunks, takes delta = G^{-1} Lambda^T r' with the kept
 // factor and sets F += delta.
 // ---------------------------------------------------------------------------
-// The solve with a kept factor, shared by the refinement (FIRST false:
-// F += delta on the flagged nodes) and by the first solve of a right-hand
-// side against factors made beforehand (FIRST true: F = G^-1 Lambda^T r on
-// every node, chunk partials summed beforehand).
-template <int P, bool FIRST>
-__device__ __forceinline__ void solve_with_factor(const LevelArgs& a, const double* __restrict__ part_b,
-                                                  const double* __restrict__ fac) {
+template <int P>
+__global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double* __restrict__ part_b,
+                                                      const double* __restrict__ fac) {
   constexpr int L = basis_size(P);
   constexpr Basis<P> B{};
   using S = BlockShape<L>;
@@ -690,10 +686,10 @@ __device__ __forceinline__ void solve_with_factor(const LevelArgs& a, const doub
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
-  if (!FIRST && !(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: no refinement here
+  if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
   // with a.refine == 2 (every node refined) the chunk partials were summed
   // into the first chunk's slot beforehand; otherwise they are summed here
-  const uint32_t c0 = a.chunk_off[k], c1 = (FIRST || a.refine == 2) ? c0 + 1 : a.chunk_off[k + 1];
+  const uint32_t c0 = a.chunk_off[k], c1 = a.refine == 2 ? c0 + 1 : a.chunk_off[k + 1];
   part_b += (size_t)blockIdx.y * a.nchunks * L;   // the field's partials
   const double* fo = fac + (size_t)k * (S::WORDS + 3 * L);
   copy_to_lds<256, S::WORDS>(A, fo, tid);
@@ -728,23 +724,57 @@ __device__ __forceinline__ void solve_with_factor(const LevelArgs& a, const doub
   double* F = a.nt.coef + (size_t)blockIdx.y * a.cstride + (size_t)node * L;
   bool bad = false;
   for (int i = tid; i < L; i += 256) {
-    const double c = FIRST ? sc[i] * z[i] : F[i] + sc[i] * z[i];
+    const double c = F[i] + sc[i] * z[i];
     F[i] = c;
     bad |= !__builtin_isfinite(c);
   }
   mark_nonfinite(bad, a.nt.flags + node, a.status);
 }
 
-template <int P>
-__global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double* __restrict__ part_b,
-                                                      const double* __restrict__ fac) {
-  solve_with_factor<P, false>(a, part_b, fac);
-}
 
+// The first solve of every field against the kept factors: one workgroup
+// per node loads the node's factor into LDS once, and its four waves take
+// the fields in turn (each wave scales its field's B, runs the two
+// triangular solves on the shared factor and writes F).  The chunk partials
+// were summed beforehand.
 template <int P>
 __global__ void __launch_bounds__(256) k_factor_solve(LevelArgs a, const double* __restrict__ part_b,
                                                       const double* __restrict__ fac) {
-  solve_with_factor<P, true>(a, part_b, fac);
+  constexpr int L = basis_size(P);
+  constexpr Basis<P> B{};
+  using S = BlockShape<L>;
+  __shared__ double A[S::WORDS + 16];   // + the zero row
+  __shared__ double iv[L], sc[L];
+  __shared__ double bw[4][L], zw[4][L];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const uint32_t k = blockIdx.x;
+  const uint32_t node = a.node0 + k;
+  const uint32_t c0 = a.chunk_off[k];
+  const double* fo = fac + (size_t)k * factor_words<L>();
+  copy_to_lds<256, S::WORDS>(A, fo, tid);
+  if (tid < 16) A[S::WORDS + tid] = 0.0;
+  for (int i = tid; i < L; i += 256) {
+    iv[i] = fo[S::WORDS + L + i];
+    sc[i] = fo[S::WORDS + 2 * L + i];
+  }
+  __syncthreads();
+  const uint32_t nf = a.nfields > 1 ? a.nfields : 1u;
+  for (uint32_t j = (uint32_t)w; j < nf; j += 4) {
+    const double* bs = part_b + ((size_t)j * a.nchunks + c0) * L;
+    for (int i = lane; i < L; i += 64) bw[w][i] = bs[i] * B.inv_fact[i] * sc[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    tri_solve_wave<L>(A, iv, bw[w], zw[w]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double* F = a.nt.coef + (size_t)j * a.cstride + (size_t)node * L;
+    for (int i = lane; i < L; i += 64) F[i] = sc[i] * zw[w][i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1112,7 +1142,7 @@ hipError_t launch_factor_cells(int p, const double* pyr, const uint32_t* list, u
 template <int P>
 static hipError_t fsolve_impl(const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
   if (a.nnodes == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_factor_solve<P>, dim3(a.nnodes, field_rows(a)), dim3(256), 0, s, a, part_b, fac);
+  hipLaunchKernelGGL(k_factor_solve<P>, dim3(a.nnodes), dim3(256), 0, s, a, part_b, fac);
   return hipGetLastError();
 }
 hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
