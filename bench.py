@@ -150,7 +150,10 @@ def refit_rooflines(kern: dict, p: int, L: int, coord_bytes: int, steps: int):
         out[name] = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak,
                          avg_launch_ms=st["avg_launch_ms"], work_per_unit=per_unit,
                          units_per_step=st["units"] / steps, traffic=None)
-    # power moments M once per level (mode 3), the factor once per node
+    # power moments M: from the moment pyramid (one pass over the points) for
+    # the levels it covers, else once per level (mode 3); the factor once per
+    # node
+    add("base_moments", "alu", base_moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("refit_moments", "alu", base_moment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("refit_factor", "alu", L ** 3 / 3.0, "TFLOP/s", PEAK_TFLOPS["fp64"])
     # per field: B (mode 2), two triangular solves, the residual update

@@ -456,6 +456,70 @@ struct FitInput {
   int64_t n;
 };
 
+// Moment pyramid of a set of problems (the float64 power-moment path): the
+// finest cells' ranges, frames and chunks from the sorted keys, their power
+// moments M (mode 3, one pass over the points), and each pyramid's coarser
+// levels from the finer ones by exact frame shifts.  `tab` is the device
+// table (PYR_TAB_WORDS per problem | first finest cell of each pyramid, and
+// the total | its problem | at list_off[d] the list_n[d] problems with
+// kp > d).  W.pyr_begin (begin, then count, of the finest cells) must hold
+// zeros; the pyramid's buffers must be reserved.
+struct PyramidShape {
+  int K = 0, npyr = 0, kp_max = 0;
+  uint64_t base_cells = 0, pyr_cells = 0, chunk_bound = 0;
+  std::vector<uint32_t> list_off, list_n;
+};
+void build_pyramid(Workspace& W, int p, int D, int dtype, const PyramidShape& ps_, const uint32_t* tab,
+                   const ProblemParams* d_prm, const uint32_t* skey, uint32_t N, double* resid, hipStream_t s) {
+  const uint32_t nbc = (uint32_t)ps_.base_cells;
+  const uint32_t NMB = (uint32_t)moment_base_doubles(p);
+  const uint32_t* cst = tab + (size_t)PYR_TAB_WORDS * ps_.K;
+  PyrTab pt{tab, cst, cst + ps_.npyr + 1, (uint32_t)ps_.npyr};
+  {
+    ProfScope ps(KN_PYR, nbc, s);
+    HIPCHK(launch_pyr_cells(skey, N, D, ps_.K, d_prm, pt, nbc, W.pyr_begin.as<uint32_t>(),
+                            W.pyr_begin.as<uint32_t>() + nbc, W.pyr_geo.as<double>(), W.pyr_nchk.as<uint32_t>(),
+                            W.pyr_dst.as<uint32_t>(), s));
+    HIPCHK(launch_pyr_scan(W.pyr_nchk.as<uint32_t>(), nbc, W.pyr_off.as<uint32_t>(), s));
+  }
+  {
+    // the finest cells as a level of nodes (range, frame, chunks)
+    ProfScope ps(KN_BASEM, N, s);
+    LevelArgs c{};
+    c.nt.begin = W.pyr_begin.as<uint32_t>();
+    c.nt.count = W.pyr_begin.as<uint32_t>() + nbc;
+    c.nt.geo = W.pyr_geo.as<double>();
+    c.node0 = 0;
+    c.nnodes = nbc;
+    c.chunk_off = W.pyr_off.as<uint32_t>();
+    c.nchunks = (uint32_t)ps_.chunk_bound;
+    c.px = W.px.p;
+    c.py = W.py.p;
+    c.pz = W.pz.p;
+    c.r = resid;
+    c.skey = skey;
+    c.D = D;
+    HIPCHK(launch_moments(p, 3, dtype, c, W.pyr_part.as<double>(), s));
+  }
+  {
+    ProfScope ps(KN_PYR, (double)ps_.pyr_cells, s);
+    HIPCHK(launch_pyr_base(W.pyr_off.as<uint32_t>(), nbc, W.pyr_part.as<double>(), NMB, W.pyr_dst.as<uint32_t>(),
+                           W.pyr.as<double>(), s));
+    for (int d = ps_.kp_max - 1; d >= 0; --d)
+      HIPCHK(launch_pyr_up(p, W.pyr.as<double>(), tab, tab + ps_.list_off[d], ps_.list_n[d], d, s));
+  }
+}
+void reserve_pyramid(Workspace& W, int p, const PyramidShape& ps_) {
+  const uint64_t NMB = moment_base_doubles(p), nbc = ps_.base_cells;
+  W.pyr.reserve(8ull * NMB * ps_.pyr_cells);
+  W.pyr_begin.reserve(8ull * nbc);   // begin, then count
+  W.pyr_geo.reserve(48ull * nbc);
+  W.pyr_nchk.reserve(4ull * nbc);
+  W.pyr_dst.reserve(4ull * nbc);
+  W.pyr_off.reserve(4ull * (nbc + 1));
+  W.pyr_part.reserve(8ull * NMB * ps_.chunk_bound);
+}
+
 // One batched pass of Alg. 1 over `in.size()` problems sharing p, D, path
 // and refinement count.
 std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_fit_opts>& per,
@@ -587,14 +651,17 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       up_cells += level_first((int)ku);
     }
   }
+  PyramidShape pshape;
+  pshape.K = K;
+  pshape.npyr = npyr;
+  pshape.kp_max = kp_max;
+  pshape.base_cells = base_cells;
+  pshape.pyr_cells = pyr_cells;
+  pshape.chunk_bound = pyr_chunk_bound;
+  pshape.list_off = list_off;
+  pshape.list_n = list_n;
   if (npyr > 0) {
-    W.pyr.reserve(8ull * NMB * pyr_cells);
-    W.pyr_begin.reserve(8ull * base_cells);   // begin, then count
-    W.pyr_geo.reserve(48ull * base_cells);
-    W.pyr_nchk.reserve(4ull * base_cells);
-    W.pyr_dst.reserve(4ull * base_cells);
-    W.pyr_off.reserve(4ull * (base_cells + 1));
-    W.pyr_part.reserve(8ull * NMB * pyr_chunk_bound);
+    reserve_pyramid(W, F->p, pshape);
     if (up_cells) W.fac_up.reserve(fd_bytes * up_cells);
   }
 
@@ -671,43 +738,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   if (npyr > 0) {
     // finest cells of every pyramid: ranges, frames, chunks; their power
     // moments M; then each pyramid's coarser levels from the finer ones
-    const uint32_t nbc = (uint32_t)base_cells;
-    const uint32_t* cst = pyr_dev + (size_t)PYR_TAB_WORDS * K;
-    PyrTab pt{pyr_dev, cst, cst + npyr + 1, (uint32_t)npyr};
-    {
-      ProfScope ps(KN_PYR, nbc, s);
-      HIPCHK(launch_pyr_cells(F->skey.as<uint32_t>(), N, F->D, K, d_prm, pt, nbc, W.pyr_begin.as<uint32_t>(),
-                              W.pyr_begin.as<uint32_t>() + nbc, W.pyr_geo.as<double>(), W.pyr_nchk.as<uint32_t>(),
-                              W.pyr_dst.as<uint32_t>(), s));
-      HIPCHK(launch_pyr_scan(W.pyr_nchk.as<uint32_t>(), nbc, W.pyr_off.as<uint32_t>(), s));
-    }
-    {
-      // the finest cells as a level of nodes (range, frame, chunks)
-      ProfScope ps(KN_BASEM, N, s);
-      LevelArgs c{};
-      c.nt.begin = W.pyr_begin.as<uint32_t>();
-      c.nt.count = W.pyr_begin.as<uint32_t>() + nbc;
-      c.nt.geo = W.pyr_geo.as<double>();
-      c.node0 = 0;
-      c.nnodes = nbc;
-      c.chunk_off = W.pyr_off.as<uint32_t>();
-      c.nchunks = (uint32_t)pyr_chunk_bound;
-      c.px = W.px.p;
-      c.py = W.py.p;
-      c.pz = W.pz.p;
-      c.r = F->resid.as<double>();
-      c.skey = F->skey.as<uint32_t>();
-      c.D = F->D;
-      c.tol = tols[0];
-      HIPCHK(launch_moments(F->p, 3, dtype, c, W.pyr_part.as<double>(), s));
-    }
-    {
-      ProfScope ps(KN_PYR, (double)pyr_cells, s);
-      HIPCHK(launch_pyr_base(W.pyr_off.as<uint32_t>(), nbc, W.pyr_part.as<double>(), NMB, W.pyr_dst.as<uint32_t>(),
-                             W.pyr.as<double>(), s));
-      for (int d = kp_max - 1; d >= 0; --d)
-        HIPCHK(launch_pyr_up(F->p, W.pyr.as<double>(), pyr_dev, pyr_dev + list_off[d], list_n[d], d, s));
-    }
+    build_pyramid(W, F->p, F->D, dtype, pshape, pyr_dev, d_prm, F->skey.as<uint32_t>(), N, F->resid.as<double>(), s);
     if (up_cells) {
       ProfScope ps(KN_UPFAC, up_cells, s);
       HIPCHK(launch_factor_cells(F->p, W.pyr.as<double>(), pyr_dev + up_off, up_cells, F->refine > 0 ? 1 : 0,
@@ -1087,19 +1118,63 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
   }
   F0.level_points = lpts;
 
+  // The power moments of the levels a moment pyramid covers come from one
+  // built as the fit builds it (depth kp from the point count), and every
+  // node of those levels is factored in one launch before the level loop;
+  // deeper levels form M and factor per level.  All factors stay for the
+  // loop when they fit a bound (else everything goes per level).
+  int kp = 0;
+  while (kp < std::min(S.D, 5) && (uint64_t)N >= ((uint64_t)L << (3 * (kp + 1)))) ++kp;
+  const size_t fw = factor_doubles(p);
+  const uint32_t NMB = (uint32_t)moment_base_doubles(p);
+  PyramidShape pshape;
+  uint32_t m_pyr = 0;   // nodes at levels <= kp (the first ones: level order)
+  for (size_t d = 0; d < nlev && (int)d <= kp; ++d) m_pyr += F0.level_count[d];
+  if (kp > 0) {
+    pshape.K = 1;
+    pshape.npyr = 1;
+    pshape.kp_max = kp;
+    pshape.base_cells = 1ull << (3 * kp);
+    pshape.pyr_cells = level_first(kp + 1);
+    pshape.chunk_bound = N / CHUNK + pshape.base_cells;
+    for (int d = 0; d < kp; ++d) {
+      pshape.list_off.push_back((uint32_t)(PYR_TAB_WORDS + 3 + d));
+      pshape.list_n.push_back(1u);
+    }
+  }
+  const bool whole = kp > 0 && 8ull * fw * M <= (1ull << 30) &&
+                     8ull * NMB * (pshape.pyr_cells + pshape.chunk_bound) <= (2ull << 30);
+  // device tables in one staged copy: chunk offsets | pyramid table |
+  // pyramid entries of the nodes factored ahead | problem parameters
+  std::vector<uint32_t> tab;
+  if (whole) {
+    tab = {0u, (uint32_t)kp, 0u, 0u, 0u, (uint32_t)pshape.base_cells, 0u};
+    for (int d = 0; d < kp; ++d) tab.push_back(0u);
+  }
+  auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t o_tab = al256(4ull * choff.size()), o_list = o_tab + al256(4ull * tab.size());
+  const size_t o_prm = o_list + al256(4ull * (whole ? m_pyr : 0)), n_small = o_prm + sizeof(ProblemParams);
+
   Workspace& W = workspace_for(s);
   std::lock_guard<std::mutex> wlock(W.mu);
   const size_t esz = dtype == FMT_F32 ? 4 : 8;
-  const uint32_t NMB = (uint32_t)moment_base_doubles(p);
   for (DevBuf* b : {&W.px, &W.py, &W.pz}) b->reserve(esz * N);
   W.partial.reserve(8ull * NMB * max_chunks);
   W.part_b.reserve(8ull * L * max_chunks * (size_t)m);
-  W.fac.reserve(8ull * factor_doubles(p) * max_nodes);
-  W.chunk_a.reserve(4ull * choff.size());
+  W.fac.reserve(8ull * fw * (whole ? M : max_nodes));
+  W.small.reserve(n_small);
   W.status.reserve(64);
-  char* stg = W.staging(4ull * choff.size());
+  if (whole) reserve_pyramid(W, p, pshape);
+  char* stg = W.staging(n_small);
   std::memcpy(stg, choff.data(), 4ull * choff.size());
-  HIPCHK(hipMemcpyAsync(W.chunk_a.p, stg, 4ull * choff.size(), hipMemcpyHostToDevice, s));
+  if (whole) {
+    std::memcpy(stg + o_tab, tab.data(), 4ull * tab.size());
+    uint32_t* lst = reinterpret_cast<uint32_t*>(stg + o_list);
+    for (uint32_t j = 0; j < m_pyr; ++j) lst[j] = level_first((int)hl[j]) + hp[j];
+  }
+  std::memcpy(stg + o_prm, &prm, sizeof(ProblemParams));
+  HIPCHK(hipMemcpyAsync(W.small.p, stg, n_small, hipMemcpyHostToDevice, s));
+  const uint32_t* d_choff = W.small.as<uint32_t>();
   HIPCHK(hipMemsetAsync(W.status.p, 0, 64, s));
   {
     ProfScope ps(KN_XGATHER, (double)N * (1 + m), s);
@@ -1107,13 +1182,22 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
                                W.px.p, W.py.p, W.pz.p, W.status.as<uint32_t>(), s));
     HIPCHK(launch_gather_fields(dtype, S.order.as<uint32_t>(), off, N, f, m, N, F0.resid.as<double>(), PB / 8, s));
   }
+  if (whole) {
+    HIPCHK(hipMemsetAsync(W.pyr_begin.p, 0, 8ull * pshape.base_cells, s));   // begin and count
+    build_pyramid(W, p, S.D, dtype, pshape, reinterpret_cast<const uint32_t*>(W.small.as<char>() + o_tab),
+                  reinterpret_cast<const ProblemParams*>(W.small.as<char>() + o_prm), F0.skey.as<uint32_t>(), N,
+                  F0.resid.as<double>(), s);
+    ProfScope ps(KN_XFACTOR, m_pyr, s);
+    HIPCHK(launch_factor_cells(p, W.pyr.as<double>(), reinterpret_cast<const uint32_t*>(W.small.as<char>() + o_list),
+                               m_pyr, S.refine > 0 ? 1 : 0, W.fac.as<double>(), F0.nb_flags.as<uint32_t>(), s));
+  }
 
   for (size_t d = 0; d < nlev; ++d) {
     LevelArgs a{};
     a.nt = F0.table();
     a.node0 = F0.level_start[d];
     a.nnodes = F0.level_count[d];
-    a.chunk_off = W.chunk_a.as<uint32_t>() + cbase[d];
+    a.chunk_off = d_choff + cbase[d];
     a.nchunks = nchk[d];
     a.px = W.px.p;
     a.py = W.py.p;
@@ -1128,14 +1212,16 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     a.refine = S.refine > 0 ? 1 : 0;
     a.pyr_tab = nullptr;
     const bool multi = a.nchunks > a.nnodes;
-    {
-      ProfScope ps(KN_XMOM, lpts[d], s);
-      HIPCHK(launch_moments(p, 3, dtype, a, W.partial.as<double>(), s));
-      if (multi) HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), NMB, s));
-    }
-    {
+    // this level's factors (level-local node k at fac + k * fw)
+    double* fac = W.fac.as<double>() + (whole ? (size_t)a.node0 * fw : 0);
+    if (!whole || (int)d > kp) {
+      {
+        ProfScope ps(KN_XMOM, lpts[d], s);
+        HIPCHK(launch_moments(p, 3, dtype, a, W.partial.as<double>(), s));
+        if (multi) HIPCHK(launch_chunk_reduce(a, W.partial.as<double>(), NMB, s));
+      }
       ProfScope ps(KN_XFACTOR, a.nnodes, s);
-      HIPCHK(launch_factor_moments(p, a, W.partial.as<double>(), W.fac.as<double>(), s));
+      HIPCHK(launch_factor_moments(p, a, W.partial.as<double>(), fac, s));
     }
     // all fields in each launch (grid rows)
     a.nfields = (uint32_t)m;
@@ -1148,7 +1234,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     }
     {
       ProfScope ps(KN_XSOLVE, (double)a.nnodes * m, s);
-      HIPCHK(launch_factor_solve(p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
+      HIPCHK(launch_factor_solve(p, a, W.part_b.as<double>(), fac, s));
     }
     for (int it = 0; it < S.refine; ++it) {
       {
@@ -1156,7 +1242,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
         HIPCHK(launch_moments(p, 1, dtype, a, W.part_b.as<double>(), s));
       }
       ProfScope ps(KN_RSOLVE, (double)a.nnodes * m, s);
-      HIPCHK(launch_refine_solve(p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
+      HIPCHK(launch_refine_solve(p, a, W.part_b.as<double>(), fac, s));
     }
     {
       ProfScope ps(KN_XRESID, (double)lpts[d] * m, s);
