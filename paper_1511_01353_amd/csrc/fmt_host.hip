@@ -62,6 +62,7 @@ const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce",
 enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
        KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_BMOM, KN_BASEM, KN_PYR, KN_XGATHER, KN_XMOM, KN_XFACTOR,
        KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_UPFAC, KN_FSOLVE, KN_COUNT };
+static_assert(sizeof(kKernelNames) / sizeof(kKernelNames[0]) == KN_COUNT, "one name per kernel class");
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof_pending;
