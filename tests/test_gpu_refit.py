@@ -167,3 +167,39 @@ def test_refit_errors(fmt):
     # the tree still refits after the failures
     (out,) = refit(fmt, tr, pr, f)
     same_topology(out, tr)
+
+
+def test_refit_full_size_properties(fmt):
+    """The benchmark's workload (2^20 points, p = 6, 3 414 nodes), where the
+    oracle is too slow to refit: the refit of the fit's own values reproduces
+    the fit, and a new field's final residual is orthogonal to the basis of
+    sampled leaves (each leaf's residual is its own least-squares residual,
+    so Lambda^T r = 0 up to rounding)."""
+    pr = synthetic.config2(nq=1000)
+    print_case("refit-full", pr)
+    tr = run_fit(fmt, pr)
+    f2 = new_fields(pr, [77])[0]
+    own, new = refit(fmt, tr, pr, np.stack([pr.f, f2]))
+    nb = tr.export_nodes()
+    na, _ = same_topology(own, tr)
+    ok = (nb["flags"] & 1) == 0
+    scale = np.maximum(np.abs(nb["coeffs"][ok]), 1.0)
+    assert np.max(np.abs(na["coeffs"][ok] - nb["coeffs"][ok]) / scale) < 1e-7
+    assert oracle.rms(own.export_points()["residual"] - tr.export_points()["residual"]) <= 1e-11
+    nn, pn = same_topology(new, tr)
+    level = nn["level"].astype(np.int64)
+    prefix = nn["prefix"].astype(np.int64)
+    parents = {(int(l) - 1, int(q) >> 3) for l, q in zip(level, prefix) if l > 0}
+    leaves = [i for i in range(len(level)) if (int(level[i]), int(prefix[i])) not in parents]
+    rng = np.random.default_rng(5)
+    from oracle import fmt_oracle as fo
+    x, y, z = (np.asarray(a, np.float64) for a in (pr.x, pr.y, pr.z))
+    r = pn["residual"]
+    order = pn["order"].astype(np.int64)
+    for i in rng.choice(leaves, 16, replace=False):
+        idx = order[nn["begin"][i]:nn["begin"][i] + nn["count"][i]]
+        c, s = oracle.node_frame(int(level[i]), fo._prefix_cell(int(prefix[i]), int(level[i])), (0, 0, 0), (1, 1, 1))
+        lam = oracle.moments((x[idx] - c[0]) * s[0], (y[idx] - c[1]) * s[1], (z[idx] - c[2]) * s[2], pr.p)
+        g = lam.T @ r[idx]
+        bound = 1e-10 * np.linalg.norm(lam) * np.linalg.norm(f2[idx].astype(np.float64))
+        assert np.max(np.abs(g)) <= bound, (i, np.max(np.abs(g)), bound)
