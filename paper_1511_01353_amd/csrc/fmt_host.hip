@@ -220,22 +220,24 @@ struct Workspace {
   // Wait for the topology kernel's counters of sequence number seq: spin on
   // the host-visible word; every few thousand spins ask whether the stream
   // has drained (then the word must be there, else read the device copy).
-  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[3]) {
+  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[4]) {
     for (uint64_t it = 1;; ++it) {
       if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) {
         out[0] = __atomic_load_n(level_flag + 0, __ATOMIC_RELAXED);
         out[1] = __atomic_load_n(level_flag + 1, __ATOMIC_RELAXED);
         out[2] = __atomic_load_n(level_flag + 2, __ATOMIC_RELAXED);
+        out[3] = __atomic_load_n(level_flag + 4, __ATOMIC_RELAXED);
         return;
       }
       if ((it & 4095) == 0) {
         const hipError_t e = hipStreamQuery(s);
         if (e == hipSuccess) {
           if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) continue;
-          HIPCHK(hipMemcpy(host_counters, counters_dev, 12, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(host_counters, counters_dev, 20, hipMemcpyDeviceToHost));
           out[0] = host_counters[0];
           out[1] = host_counters[1];
           out[2] = host_counters[2];
+          out[3] = host_counters[4];
           return;
         }
         if (e != hipErrorNotReady) hip_check(e, "level wait");
@@ -521,6 +523,15 @@ void reserve_pyramid(Workspace& W, int p, const PyramidShape& ps_) {
   W.pyr_part.reserve(8ull * NMB * ps_.chunk_bound);
 }
 
+// The r-weighted moments of a level (same output layout either way): the
+// nodes with at least SMALL_NODE points in staged chunks of eight waves
+// (mode 2), the smaller ones with two waves per chunk reading the points in
+// place (mode 4); a launch only for a kind the level holds.
+void launch_bmoments(int p, int dtype, const LevelArgs& a, uint32_t small, double* part, hipStream_t s) {
+  if (small < a.nnodes) HIPCHK(launch_moments(p, 2, dtype, a, part, s));
+  if (small > 0) HIPCHK(launch_moments(p, 4, dtype, a, part, s));
+}
+
 // One batched pass of Alg. 1 over `in.size()` problems sharing p, D, path
 // and refinement count.
 std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_fit_opts>& per,
@@ -763,6 +774,8 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
 
   uint32_t nnodes = (uint32_t)K, nchunks = off0[K], node0 = 0;
   uint32_t level_points = N;
+  uint32_t nsmall = 0;   // nodes of the level with fewer than SMALL_NODE points
+  for (int k = 0; k < K; ++k) nsmall += in[k].n < (int64_t)SMALL_NODE ? 1u : 0u;
   F->level_start.clear();
   F->level_count.clear();
   // chunk offsets: level 0's from the staged tables, then chunk_a and
@@ -818,7 +831,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     const bool multi = nchunks > nnodes;   // some node spans several chunks
     if (lvl_pyr) {
       ProfScope ps(KN_BMOM, level_points, s);
-      HIPCHK(launch_moments(F->p, 2, dtype, a, W.part_m2.as<double>(), s));
+      launch_bmoments(F->p, dtype, a, nsmall, W.part_m2.as<double>(), s);
     }
     if (lvl_pts) {
       ProfScope ps(KN_GRAM, level_points, s);
@@ -881,13 +894,14 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
                          next_off->as<uint32_t>(), W.counters.as<uint32_t>(), W.level_flag_dev, seq, s));
     }
-    uint32_t cnt[3];
+    uint32_t cnt[4];
     W.counters_dev = W.counters.p;
     W.wait_level(seq, s, cnt);
     node0 = next0;
     nnodes = cnt[0];
     nchunks = cnt[1];
     level_points = cnt[2];
+    nsmall = cnt[3];
     cur_off = next_off->as<uint32_t>();
     next_off = next_off == &W.chunk_a ? &W.chunk_b : &W.chunk_a;
   }
@@ -1101,7 +1115,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
 
   // per level: first node, nodes, points and chunk offsets (concatenated)
   const size_t nlev = F0.level_start.size();
-  std::vector<uint32_t> choff, cbase(nlev), nchk(nlev), lpts(nlev);
+  std::vector<uint32_t> choff, cbase(nlev), nchk(nlev), lpts(nlev), lsmall(nlev, 0);
   uint32_t max_chunks = 1, max_nodes = 1;
   for (size_t d = 0; d < nlev; ++d) {
     cbase[d] = (uint32_t)choff.size();
@@ -1110,6 +1124,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
       choff.push_back(run);
       run += (hc[k] + CHUNK - 1) / CHUNK;
       pts += hc[k];
+      lsmall[d] += hc[k] < SMALL_NODE ? 1u : 0u;
     }
     choff.push_back(run);
     nchk[d] = run;
@@ -1230,7 +1245,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     a.cstride = NB / 8;
     {
       ProfScope ps(KN_XBMOM, (double)lpts[d] * m, s);
-      HIPCHK(launch_moments(p, 2, dtype, a, W.part_b.as<double>(), s));
+      launch_bmoments(p, dtype, a, lsmall[d], W.part_b.as<double>(), s);
       if (multi) HIPCHK(launch_chunk_reduce(a, W.part_b.as<double>(), L, s));
     }
     {

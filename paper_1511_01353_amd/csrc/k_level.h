@@ -44,6 +44,11 @@ struct LevelArgs {
   uint32_t* status = nullptr;
 };
 
+// Nodes with fewer points than this take the r-weighted moments in mode 4
+// (unstaged, two waves per chunk), the others in mode 2; the choice depends
+// on the node alone, so a problem gets the same bits in any batch.
+constexpr uint32_t SMALL_NODE = 1024;
+
 // Grid rows of a launch over the fields of a LevelArgs.
 inline unsigned field_rows(const LevelArgs& a) { return a.nfields > 1 ? a.nfields : 1u; }
 
@@ -97,7 +102,8 @@ hipError_t launch_node_geo(const NodeTable& nt, const ProblemParams* prm, uint32
 hipError_t launch_roots(const NodeTable& nt, const ProblemParams* prm, int nprob, hipStream_t s);
 hipError_t launch_gram(int p, int path, int dtype, const LevelArgs& a, double* partial, hipStream_t s);
 // Power moments of every chunk (mode 0: M, B, sum r^2; mode 1: B of
-// r - Lambda F; mode 2: B; mode 3: M).  The grid is a.nchunks workgroups,
+// r - Lambda F; mode 2: B of the nodes with at least SMALL_NODE points;
+// mode 3: M; mode 4: B as mode 2, unstaged, of the smaller nodes).  The grid is a.nchunks workgroups,
 // which may exceed chunk_off[nnodes] (the extra ones exit).  With
 // a.pyr_tab, mode 2 skips the nodes the pyramid does not cover and mode 0
 // those it covers.
@@ -149,9 +155,10 @@ hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, 
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s);
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
                            uint32_t* nact, hipStream_t s);
-// counters[0..2] = next level's nodes, chunks, points; with hostc (device view
-// of host-visible memory) they are also written there, followed by seq at
-// hostc[3] (system-scope release).
+// counters[0..2] = next level's nodes, chunks, points, counters[4] = its
+// nodes with fewer than SMALL_NODE points; with hostc (device view of
+// host-visible memory) they are also written there (same positions), and
+// the sequence number at hostc[3] last (system-scope release).
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
                        uint32_t seq, hipStream_t s);

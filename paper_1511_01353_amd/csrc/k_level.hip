@@ -998,7 +998,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
   }
   __syncthreads();
   // one thread per (node, octant): the octant's child, if active
-  uint32_t pts = 0;
+  uint32_t pts = 0, small = 0;
   for (uint32_t pr = tid; pr < 8u * m; pr += 1024u) {
     const uint32_t i = pr >> 3, o = pr & 7u;
     const uint32_t node = a.node0 + i;
@@ -1023,11 +1023,13 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
     next_chunk_off[crun] = (cn + CHUNK - 1) / CHUNK;
     pts += cn;
+    small += cn < (uint32_t)SMALL_NODE ? 1u : 0u;
   }
   __syncthreads();
   // total points of the next level (integer sum: exact in any order)
-  uint32_t next_points;
+  uint32_t next_points, next_small;
   (void)scan_1024(pts, wsum, next_points);
+  (void)scan_1024(small, wsum, next_small);
   // exclusive scan of the children's chunk counts
   const uint32_t seg2 = (total + 1023u) / 1024u;
   const uint32_t b2 = min(total, tid * seg2), e2 = min(total, b2 + seg2);
@@ -1045,12 +1047,14 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     counters[0] = total;
     counters[1] = nchunks_next;
     counters[2] = next_points;
+    counters[4] = next_small;
     if (hostc) {
       // the same counters into host-visible (fine-grained) memory, then the
       // sequence number with a system-scope release: the host waits on it
       hostc[0] = total;
       hostc[1] = nchunks_next;
       hostc[2] = next_points;
+      hostc[4] = next_small;
       __hip_atomic_store(hostc + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }

@@ -21,7 +21,10 @@
 // Modes: 0 = M, B and sum r^2 of a level's nodes; 1 = B of the refinement
 // residual r' = r - Lambda F; 2 = B only (the power moments M of the node come
 // from the moment pyramid); 3 = M only, over the cells of the pyramid's
-// finest level.
+// finest level; 4 = B only as mode 2 for the nodes with fewer than
+// SMALL_NODE points (mode 2 takes the others): two waves per chunk reading
+// their points straight from memory (no staging, so many more workgroups
+// share a compute unit).
 #include <utility>
 
 #include "k_level.h"
@@ -49,7 +52,7 @@ struct MomentPlan {
   static constexpr int CAP = 64;   // accumulators per lane budget
   // waves per workgroup: mode 3 runs over many small cells, where smaller
   // workgroups let more of them share a compute unit
-  static constexpr int WAVES = MODE == 3 ? 4 : 8;
+  static constexpr int WAVES = MODE == 3 ? 4 : (MODE == 4 ? 2 : 8);
   static constexpr int NW_MAX = HAS_M ? WAVES : 2;
   static constexpr int NG_MIN = (NOUT + CAP - 1) / CAP;
   static constexpr int NW = NG_MIN < NW_MAX ? (NG_MIN < 1 ? 1 : NG_MIN) : NW_MAX;
@@ -158,7 +161,8 @@ __device__ __forceinline__ void accumulate(std::index_sequence<T...>, const doub
 template <int MODE, typename TIN>
 struct Staged {
   static constexpr bool HAS_W = MODE != 3;
-  static constexpr size_t BYTES = (size_t)CHUNK * (3 * sizeof(TIN) + (HAS_W ? sizeof(double) : 0));
+  static constexpr bool IN_LDS = MODE != 4;   // mode 4 reads the points where they are
+  static constexpr size_t BYTES = IN_LDS ? (size_t)CHUNK * (3 * sizeof(TIN) + (HAS_W ? sizeof(double) : 0)) : 0;
   const TIN* x;
   const TIN* y;
   const TIN* z;
@@ -170,6 +174,7 @@ struct Staged {
     z = p + 2 * CHUNK;
     w = reinterpret_cast<const double*>(p + 3 * CHUNK);
   }
+  __device__ Staged(const TIN* gx, const TIN* gy, const TIN* gz, const double* gw) : x(gx), y(gy), z(gz), w(gw) {}
 };
 
 // One wave's share of a chunk: group G of the runs over slice `slice` of the
@@ -266,9 +271,16 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
   const double* geo = a.nt.geo + 6 * (size_t)node;
   const uint32_t fj = blockIdx.y;   // field of a multi-field launch
   const double* rin = a.r + (size_t)fj * a.rstride;
-  if constexpr (MODE == 0 || MODE == 2) {
-    // a level split between the pyramid's nodes (mode 2) and the others
-    if (a.pyr_tab && pyramid_covers(a.pyr_tab[PYR_TAB_WORDS * a.nt.problem[node] + 1], a.level) != (MODE == 2)) return;
+  if constexpr (MODE == 0 || MODE == 2 || MODE == 4) {
+    // a level split between the pyramid's nodes (modes 2, 4) and the others
+    if (a.pyr_tab && pyramid_covers(a.pyr_tab[PYR_TAB_WORDS * a.nt.problem[node] + 1], a.level) != (MODE != 0)) return;
+  }
+  // modes 2 and 4 split the nodes by size
+  if constexpr (MODE == 2) {
+    if (nc < SMALL_NODE) return;
+  }
+  if constexpr (MODE == 4) {
+    if (nc >= SMALL_NODE) return;
   }
   if constexpr (MODE == 1) {
     if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
@@ -315,7 +327,7 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
         }
       }
     }
-  } else {
+  } else if constexpr (ST::IN_LDS) {
     for (uint32_t i0 = threadIdx.x; i0 < n; i0 += NPT * NT) {
       TIN vx[NPT], vy[NPT], vz[NPT];
       double r[NPT];
@@ -340,7 +352,10 @@ __global__ void __launch_bounds__((MomentPlan<P, MODE>::NTHR)) k_moments(LevelAr
     }
   }
   __syncthreads();
-  const ST st(smem);
+  const ST st = [&] {
+    if constexpr (ST::IN_LDS) return ST(smem);
+    else return ST(gx, gy, gz, rin + start);
+  }();
   double* out = part + ((size_t)fj * a.nchunks + g) * MP::NOUT;
   const int w = threadIdx.x >> 6;
   const int grp = w % MP::NW, slice = w / MP::NW;
@@ -374,6 +389,7 @@ static hipError_t moments_impl(int mode, int dtype, const LevelArgs& a, double* 
     case 1: launch_mode<P, 1>(dtype, a, part, s); break;
     case 2: launch_mode<P, 2>(dtype, a, part, s); break;
     case 3: launch_mode<P, 3>(dtype, a, part, s); break;
+    case 4: launch_mode<P, 4>(dtype, a, part, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
