@@ -51,13 +51,6 @@ __device__ __forceinline__ void scaled_powers(T t, T (&pw)[P + 1]) {
   for (int k = 1; k <= P; ++k) pw[k] = pw[k - 1] * t * (T(1) / T(k));
 }
 
-// Value of monomial i at a point, from its three scaled-power tables.
-template <int P, int I, typename T>
-__device__ __forceinline__ T monomial(const T (&pu)[P + 1], const T (&pv)[P + 1], const T (&pw)[P + 1]) {
-  constexpr Basis<P> B{};
-  return pu[B.lx[I]] * pv[B.ly[I]] * pw[B.lz[I]];
-}
-
 // sum_i F[i] Lambda_i(u) with compile-time indices; F read through a pointer
 // (LDS or global).  Nested Horner form, w innermost:
 //   sum_l u^l/l! sum_m v^m/m! sum_n F_lmn w^n/n!,
@@ -128,90 +121,6 @@ __device__ __forceinline__ void poly_eval_multi(const FPtr F, const double (&u)[
   for (int q = 0; q < NPT; ++q) out[q] = f[q];
 }
 
-// poly_eval for NPT points at once with the per-point step tables t/(k+1)
-// formed first (as poly_eval does): each coefficient read feeds NPT
-// independent Horner chains.  Same operations per point as poly_eval.
-template <int P, int NPT, typename FPtr>
-__device__ __forceinline__ void poly_eval_n(const FPtr F, const double (&u)[NPT], const double (&v)[NPT],
-                                            const double (&w)[NPT], double (&out)[NPT]) {
-  double ud[NPT][P + 1], vd[NPT][P + 1], wd[NPT][P + 1];
-#pragma unroll
-  for (int q = 0; q < NPT; ++q)
-#pragma unroll
-    for (int k = 0; k <= P; ++k) {
-      ud[q][k] = u[q] * (1.0 / (double)(k + 1));
-      vd[q][k] = v[q] * (1.0 / (double)(k + 1));
-      wd[q][k] = w[q] * (1.0 / (double)(k + 1));
-    }
-  double f[NPT];
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) f[q] = 0.0;
-#pragma unroll
-  for (int l = P; l >= 0; --l) {
-    double g[NPT];
-#pragma unroll
-    for (int q = 0; q < NPT; ++q) g[q] = 0.0;
-#pragma unroll
-    for (int m = P - l; m >= 0; --m) {
-      double h[NPT];
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) h[q] = 0.0;
-#pragma unroll
-      for (int n = P - l - m; n >= 0; --n) {
-        const int k = l + m + n;
-        const int idx = k * (k + 1) * (k + 2) / 6 + (k - l) * (k - l + 1) / 2 + (k - l - m);
-        const double c = F[idx];
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) h[q] = c + h[q] * wd[q][n];
-      }
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) g[q] = h[q] + g[q] * vd[q][m];
-    }
-#pragma unroll
-    for (int q = 0; q < NPT; ++q) f[q] = g[q] + f[q] * ud[q][l];
-  }
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) out[q] = f[q];
-}
-
-// sum_i C[i] u^a v^b w^c for NPT points at once, with C the coefficients
-// already divided by a! b! c! (plain monomials, so a point needs only u, v,
-// w).  Every coefficient is read once and feeds NPT independent Horner
-// chains, so the reads may come from LDS through a volatile view without
-// serialising each chain on its loads.
-template <int P, int NPT, typename FPtr>
-__device__ __forceinline__ void poly_eval_plain_multi(const FPtr C, const double (&u)[NPT], const double (&v)[NPT],
-                                                      const double (&w)[NPT], double (&out)[NPT]) {
-  double f[NPT];
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) f[q] = 0.0;
-#pragma unroll
-  for (int l = P; l >= 0; --l) {
-    double g[NPT];
-#pragma unroll
-    for (int q = 0; q < NPT; ++q) g[q] = 0.0;
-#pragma unroll
-    for (int m = P - l; m >= 0; --m) {
-      double h[NPT];
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) h[q] = 0.0;
-#pragma unroll
-      for (int n = P - l - m; n >= 0; --n) {
-        const int k = l + m + n;
-        const int idx = k * (k + 1) * (k + 2) / 6 + (k - l) * (k - l + 1) / 2 + (k - l - m);
-        const double c = C[idx];
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) h[q] = fma(h[q], w[q], c);
-      }
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) g[q] = fma(g[q], v[q], h[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < NPT; ++q) f[q] = fma(f[q], u[q], g[q]);
-  }
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) out[q] = f[q];
-}
 
 // ---------------------------------------------------------------------------
 // Tunables
@@ -237,7 +146,7 @@ struct NodeTable {
   uint32_t* parent;      // parent node (self for a root)
   uint32_t* first_child; // first child node (valid if child_mask != 0)
   uint32_t* child_mask;  // bit o set if octant o is a node
-  uint32_t* flags;       // bit0: a pivot was deflated; bit1: non-finite coefficient
+  uint32_t* flags;       // FLAG_DEFLATED, FLAG_NONFINITE, FLAG_REFINE (below)
   double* geo;           // 6 per node: centre x,y,z then dilation 2/h x,y,z
   double* coef;          // L per node
 };
