@@ -1262,7 +1262,7 @@ std::vector<std::shared_ptr<Forest>> refit_forests(fmt_tree& t, const void* x, c
     }
     {
       ProfScope ps(KN_XRESID, (double)lpts[d] * m, s);
-      HIPCHK(launch_residual(p, dtype, a, nullptr, s));
+      HIPCHK(launch_residual_fields(p, dtype, a, s));
     }
   }
   // the rank and refinement flags belong to the node set: every field's tree

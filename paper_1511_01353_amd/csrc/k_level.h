@@ -153,6 +153,9 @@ hipError_t launch_factor_cells(int p, const double* pyr, const uint32_t* list, u
 // beforehand) and the factors of launch_factor_moments.
 hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s);
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s);
+// r <- r - Lambda F for every field of a multi-field LevelArgs (one launch,
+// the points read once per group of fields), without octant statistics.
+hipError_t launch_residual_fields(int p, int dtype, const LevelArgs& a, hipStream_t s);
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
                            uint32_t* nact, hipStream_t s);
 // counters[0..2] = next level's nodes, chunks, points, counters[4] = its

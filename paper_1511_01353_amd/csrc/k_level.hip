@@ -877,6 +877,48 @@ __device__ __forceinline__ uint32_t scan_1024(uint32_t x, uint32_t* wsum, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Residual update of every field of a multi-field launch (the fixed-topology
+// refit), without octant statistics: one workgroup per chunk reads the
+// chunk's points once per group of up to RF_GROUP fields and takes each
+// field's r <- r - Lambda F with that field's coefficients (the arithmetic of
+// k_residual, point by point).
+// ---------------------------------------------------------------------------
+constexpr int RF_GROUP = 8;
+
+template <int P, typename TIN>
+__global__ void __launch_bounds__(256) k_residual_fields(LevelArgs a) {
+  constexpr int L = basis_size(P);
+  __shared__ double Fs[RF_GROUP][L];
+  const int tid = threadIdx.x;
+  const uint32_t g = blockIdx.x;
+  const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
+  const uint32_t node = a.node0 + k;
+  const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
+  const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
+  const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
+  const double* geo = a.nt.geo + 6 * (size_t)node;
+  const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
+  const uint32_t nf = a.nfields > 1 ? a.nfields : 1u;
+  for (uint32_t f0 = 0; f0 < nf; f0 += RF_GROUP) {
+    const uint32_t ng = min((uint32_t)RF_GROUP, nf - f0);
+    __syncthreads();   // the previous group's coefficients are no longer read
+    for (uint32_t e = tid; e < ng * L; e += 256)
+      Fs[e / L][e % L] = a.nt.coef[(size_t)(f0 + e / L) * a.cstride + (size_t)node * L + e % L];
+    __syncthreads();
+    for (uint32_t i = start + tid; i < end; i += 256) {
+      double x, y, z;
+      load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
+      const double u = (x - cx) * sx, v = (y - cy) * sy, w = (z - cz) * sz;
+      for (uint32_t j = 0; j < ng; ++j) {
+        double* rr = a.r + (size_t)(f0 + j) * a.rstride;
+        const double val = poly_eval<P, double>(Fs[j], u, v, w);
+        rr[i] = rr[i] - val;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Child activation (Alg. 1): octant o of a node at depth d becomes a node iff
 // d + 1 <= D, n_o >= calL (tested first) and sqrt(sum r^2 / n_o) > tol.
 // One thread per node.  The octant counts come from the residual pass (exact
@@ -1163,6 +1205,17 @@ static hipError_t resid_impl(int dtype, const LevelArgs& a, double* part_ss, hip
 }
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {
   FMT_DISPATCH_P(p, resid_impl, dtype, a, part_ss, s);
+}
+
+template <int P>
+static hipError_t residf_impl(int dtype, const LevelArgs& a, hipStream_t s) {
+  if (a.nchunks == 0) return hipSuccess;
+  if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual_fields<P, float>), dim3(a.nchunks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_residual_fields<P, double>), dim3(a.nchunks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_residual_fields(int p, int dtype, const LevelArgs& a, hipStream_t s) {
+  FMT_DISPATCH_P(p, residf_impl, dtype, a, s);
 }
 
 template <int P>
