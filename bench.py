@@ -136,7 +136,7 @@ def kernel_rooflines(kern: dict, p: int, L: int, path: str, coord_bytes: int, st
     return out
 
 
-def refit_rooflines(kern: dict, p: int, L: int, coord_bytes: int, steps: int):
+def refit_rooflines(kern: dict, p: int, L: int, coord_bytes: int, steps: int, fields: int = 1):
     """Rooflines of the fixed-topology refit's kernel classes (same definition
     as kernel_rooflines: algorithmic work over summed launch durations)."""
     out = {}
@@ -159,7 +159,9 @@ def refit_rooflines(kern: dict, p: int, L: int, coord_bytes: int, steps: int):
     # per field: B (mode 2), two triangular solves, the residual update
     add("refit_bmoments", "alu", bmoment_flops_per_point(p), "TFLOP/s", PEAK_TFLOPS["fp64"])
     add("refit_solve", "alu", 2.0 * L * L, "TFLOP/s", PEAK_TFLOPS["fp64"])
-    add("refit_residual", "hbm", 3 * coord_bytes + 8 + 8 + 4, "GB/s", PEAK_HBM_GBS)
+    # residual: r read and written per field, the coordinates once per point
+    # for all the fields
+    add("refit_residual", "hbm", 8 + 8 + 3 * coord_bytes / max(fields, 1), "GB/s", PEAK_HBM_GBS)
     return out
 
 
@@ -204,7 +206,7 @@ def refit_leg(fmt, tree_opts, X, Y, Z, pr, m: int, steps: int, warmup: int):
         "fields": m, "n": pr.n, "nodes": nodes,
         "ms_p50": 1e3 * t50, "ms_p99": 1e3 * float(np.percentile(times, 99)),
         "field_pts_per_s": m * pr.n / t50,
-        "rooflines": refit_rooflines(kern, pr.p, L, pr.x.dtype.itemsize, steps),
+        "rooflines": refit_rooflines(kern, pr.p, L, pr.x.dtype.itemsize, steps, m),
         "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in st.items()}
                     for k, st in kern.items()},
     }

@@ -35,5 +35,7 @@ def test_refit_rooflines_from_launch_records():
     r = bench.refit_rooflines(kern, 6, 84, 4, 2)
     assert abs(r["refit_factor"]["achieved"] - 100 * 84 ** 3 / 3 / 2e-3 / 1e12) < 1e-12
     assert r["refit_factor"]["unit"] == "TFLOP/s" and r["refit_factor"]["peak"] == 78.6
-    assert abs(r["refit_residual"]["achieved"] - 2e6 * 32 / 1e-3 / 1e9) < 1e-9
+    assert abs(r["refit_residual"]["achieved"] - 2e6 * (16 + 12) / 1e-3 / 1e9) < 1e-9
+    r8 = bench.refit_rooflines(kern, 6, 84, 4, 2, 8)
+    assert abs(r8["refit_residual"]["achieved"] - 2e6 * (16 + 1.5) / 1e-3 / 1e9) < 1e-9
     assert r["refit_residual"]["bound"] == "hbm"
