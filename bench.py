@@ -268,7 +268,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus N with N > 1 is not supported", file=sys.stderr)
+        print("bench.py runs on one GPU; --gpus N with N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
