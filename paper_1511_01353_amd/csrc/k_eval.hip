@@ -137,11 +137,14 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
 // where the result is written.
 // Coefficient rows: a wave whose queries all reach one node reads the row
 // with wave-uniform (scalar) loads.  Otherwise the rows come through LDS in
-// four rounds of 16 queries: the 4 lanes of a quad load one query's row
-// together (each instruction reads 64 contiguous bytes per query, one cache
-// line, instead of one line per lane), and the query's own lane evaluates it.
+// two rounds of 32 queries, each round loaded as two batches of 16: the 4
+// lanes of a quad load one query's row together (each instruction reads 64
+// contiguous bytes, half of one 128-byte line, per query, instead of one
+// line per lane), and the query's own lane evaluates it.  One wave per
+// workgroup; a round's 32 rows take 21.5 KB of LDS at p = 6.
 // ---------------------------------------------------------------------------
-constexpr int EVAL_THREADS = 128;
+constexpr int EVAL_THREADS = 64;
+constexpr int EVAL_ROWS = 32;   // rows staged per round
 
 template <int P, typename TIN>
 __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double* __restrict__ cc,
@@ -151,10 +154,12 @@ __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double*
                                                        double* __restrict__ out) {
   constexpr int L = basis_size(P);
   constexpr int CS = ccoef_stride(L);
-  constexpr int WAVES = EVAL_THREADS / 64;
-  __shared__ __attribute__((aligned(16))) double rows[WAVES][16 * CS];
+  constexpr int UP = (L + 1) / 2;   // double pairs of a row that hold coefficients
+  constexpr int LS = 2 * UP;        // LDS row stride (doubles), 16-byte aligned rows
+  static_assert(EVAL_THREADS == 64, "one wave per workgroup");
+  __shared__ __attribute__((aligned(16))) double rows[EVAL_ROWS * LS];
   const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const bool valid = i0 < nq;
   const uint32_t i = valid ? i0 : nq - 1;   // tail lanes repeat the last query and do not store
   const uint32_t src = perm ? perm[i] : i;   // caller's position of query i
@@ -194,30 +199,35 @@ __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double*
     typedef const double __attribute__((address_space(4))) cdouble;
     val = poly_eval<P, double>((const cdouble*)(cc + (size_t)n0 * CS), u, v, ww);
   } else {
-    double* buf = rows[w];
+    constexpr int KS = (UP + 3) / 4;   // loads per lane per batch of 16 rows
     const int q4 = lane >> 2, part = lane & 3;
 #pragma unroll 1
-    for (int r = 0; r < 4; ++r) {
-      // the quad's query: lane 16 r + q4
-      const uint32_t nd = (uint32_t)__shfl((int)node, 16 * r + q4);
-      const double2* srow = reinterpret_cast<const double2*>(cc + (size_t)nd * CS);
-      double2* drow = reinterpret_cast<double2*>(buf + q4 * CS);
-      constexpr int PAIRS = CS / 2, STEPS = (PAIRS + 3) / 4;
-      double2 vals[STEPS];
+    for (int r = 0; r < 64 / EVAL_ROWS; ++r) {
+      double2 vals[2][KS];
 #pragma unroll
-      for (int k = 0; k < STEPS; ++k) {
-        const int pr = 4 * k + part;
-        vals[k] = pr < PAIRS ? srow[pr] : make_double2(0.0, 0.0);
+      for (int b = 0; b < 2; ++b) {
+        // the quad's query: lane EVAL_ROWS r + 16 b + q4, its row to LDS row 16 b + q4
+        const uint32_t nd = (uint32_t)__shfl((int)node, EVAL_ROWS * r + 16 * b + q4);
+        const double2* srow = reinterpret_cast<const double2*>(cc + (size_t)nd * CS);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int pr = 4 * k + part;
+          vals[b][k] = pr < UP ? srow[pr] : make_double2(0.0, 0.0);
+        }
       }
 #pragma unroll
-      for (int k = 0; k < STEPS; ++k) {
-        const int pr = 4 * k + part;
-        if (pr < PAIRS) drow[pr] = vals[k];
+      for (int b = 0; b < 2; ++b) {
+        double2* drow = reinterpret_cast<double2*>(rows + (16 * b + q4) * LS);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int pr = 4 * k + part;
+          if (pr < UP) drow[pr] = vals[b][k];
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if ((lane >> 4) == r) val = poly_eval<P, double>(buf + (lane & 15) * CS, u, v, ww);
+      if (lane / EVAL_ROWS == r) val = poly_eval<P, double>(rows + (lane % EVAL_ROWS) * LS, u, v, ww);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

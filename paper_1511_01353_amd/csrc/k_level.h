@@ -168,9 +168,11 @@ hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint3
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
 // Row stride (doubles) of the composite coefficient table: calL rounded up to
 // even, so that every row starts on a 16-byte boundary.
-__host__ __device__ constexpr int ccoef_stride(int L) { return L + (L & 1); }
+// Composite coefficient rows start on 128-byte boundaries (one L2 line), so
+// a row of calL = 84 doubles occupies exactly six lines.
+__host__ __device__ constexpr int ccoef_stride(int L) { return (L + 15) / 16 * 16; }
 // Composite coefficients (a node's chain of polynomials in its frame),
-// ccoef_stride(calL) doubles per node, of the nodes first .. first+count-1,
+// ccoef_stride(calL) doubles per node (the tail of a row is zero), of the nodes first .. first+count-1,
 // all of one level; the parents' rows must be in place.
 hipError_t launch_compose(int p, const NodeTable& nt, uint32_t first, uint32_t count, double* cc, hipStream_t s);
 // Cell table of one tree: 8^T entries, see EvalTree::cells.
