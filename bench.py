@@ -250,7 +250,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--nq", type=int, default=1 << 22)
     ap.add_argument("--sort-queries", type=int, default=-1)
-    ap.add_argument("--mixed-refine", type=int, default=3)
+    ap.add_argument("--mixed-refine", type=int, default=1)
     ap.add_argument("--fp64-refine", type=int, default=1)
     ap.add_argument("--no-compare", action="store_true", help="time only the headline path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
