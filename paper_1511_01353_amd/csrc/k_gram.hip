@@ -109,13 +109,20 @@ __device__ __forceinline__ void gram_body(const LevelArgs& a, TT* tile, uint32_t
     }
   }
 
+  // the next batch's point is loaded before this batch's products, so its
+  // memory latency overlaps the matrix-core work
+  double nx = 0, ny = 0, nz = 0, nr = 0;
+  if (start + lane < end) {
+    load_point<TIN>(a.px, a.py, a.pz, start + lane, nx, ny, nz);
+    nr = a.r[start + lane];
+  }
   for (uint32_t bs = start; bs < end; bs += S::PB) {
     const uint32_t pt = bs + lane;
     const bool valid = pt < end;
-    double x = 0, y = 0, z = 0, rv = 0;
-    if (valid) {
-      load_point<TIN>(a.px, a.py, a.pz, pt, x, y, z);
-      rv = a.r[pt];
+    const double x = nx, y = ny, z = nz, rv = valid ? nr : 0.0;
+    if (pt + S::PB < end) {
+      load_point<TIN>(a.px, a.py, a.pz, pt + S::PB, nx, ny, nz);
+      nr = a.r[pt + S::PB];
     }
     double u = valid ? (x - cx) * sx : 0.0;
     double v = valid ? (y - cy) * sy : 0.0;
@@ -170,41 +177,53 @@ __device__ __forceinline__ void gram_body(const LevelArgs& a, TT* tile, uint32_t
   }
 }
 
-// MIXED = false: float64 basis values and products.  MIXED = true: float32
+// Float64 path: float64 basis values and products.  Mixed path: float32
 // products, except for nodes with fewer than MIXED_WIDE_RATIO * calL points
 // (near-interpolating nodes whose Gram is too ill-conditioned for a float32
 // preconditioner), which take the float64 route.
 constexpr int MIXED_WIDE_RATIO = 4;
 
-template <int P, typename TIN, bool MIXED>
-__global__ void __launch_bounds__(256) k_gram(LevelArgs a, double* __restrict__ partial) {
+// ROUTE 0: every chunk, float64 products.  ROUTE 1 / 2 (mixed path): only
+// the chunks of nodes that take the float32 / float64 route; the two launches
+// cover the level between them, and each sizes its LDS tile and registers for
+// one element type.  Up to p = 6 the registers are held to 4 waves per SIMD
+// for the float32 route and 3 for the float64 routes, which their LDS tiles
+// allow: more waves in flight hide the batch loads and barriers behind other
+// waves' matrix-core work.  Larger bases keep the compiler's allocation
+// (held to 3 waves they would spill).
+template <int P, typename TIN, typename TT, int ROUTE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 6 ? (ROUTE == 1 ? 4 : 3) : 1)))
+k_gram(LevelArgs a, double* __restrict__ partial) {
   using S = GramShape<P>;
-  __shared__ double tile[S::LP * S::PS];
+  __shared__ TT tile[S::LP * S::PS];
   const uint32_t g = blockIdx.x;
   const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
   const uint32_t node = a.node0 + k;
   const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
+  if (ROUTE != 0 && (nc >= (uint32_t)(MIXED_WIDE_RATIO * S::L)) != (ROUTE == 1)) return;   // the other launch's chunk
   const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
   const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
   const double* geo = a.nt.geo + 6 * (size_t)node;
   double* out = partial + (size_t)g * S::NPAIR * 256;
-  if (MIXED && nc >= (uint32_t)(MIXED_WIDE_RATIO * S::L))
-    gram_body<P, TIN, float>(a, reinterpret_cast<float*>(tile), start, end, geo, out);
-  else
-    gram_body<P, TIN, double>(a, tile, start, end, geo, out);
+  gram_body<P, TIN, TT>(a, tile, start, end, geo, out);
+}
+
+template <int P, typename TIN>
+static void gram_launch(int path, const LevelArgs& a, double* partial, hipStream_t s) {
+  dim3 grid(a.nchunks), block(256);
+  if (path == FMT_PATH_MIXED) {
+    hipLaunchKernelGGL((k_gram<P, TIN, float, 1>), grid, block, 0, s, a, partial);
+    hipLaunchKernelGGL((k_gram<P, TIN, double, 2>), grid, block, 0, s, a, partial);
+  } else {
+    hipLaunchKernelGGL((k_gram<P, TIN, double, 0>), grid, block, 0, s, a, partial);
+  }
 }
 
 template <int P>
 static hipError_t gram_impl(int path, int dtype, const LevelArgs& a, double* partial, hipStream_t s) {
   if (a.nchunks == 0) return hipSuccess;
-  dim3 grid(a.nchunks), block(256);
-  if (path == FMT_PATH_MIXED) {
-    if (dtype == FMT_F32) hipLaunchKernelGGL((k_gram<P, float, true>), grid, block, 0, s, a, partial);
-    else hipLaunchKernelGGL((k_gram<P, double, true>), grid, block, 0, s, a, partial);
-  } else {
-    if (dtype == FMT_F32) hipLaunchKernelGGL((k_gram<P, float, false>), grid, block, 0, s, a, partial);
-    else hipLaunchKernelGGL((k_gram<P, double, false>), grid, block, 0, s, a, partial);
-  }
+  if (dtype == FMT_F32) gram_launch<P, float>(path, a, partial, s);
+  else gram_launch<P, double>(path, a, partial, s);
   return hipGetLastError();
 }
 
