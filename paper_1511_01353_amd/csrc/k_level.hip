@@ -811,18 +811,52 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
     ss[q] = 0.0;
     cn[q] = 0u;
   }
-  for (uint32_t i = start + tid; i < end; i += 256) {
-    double x, y, z;
-    load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
-    const double val = poly_eval<P, double>(Fs, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
-    const double rn = rr[i] - val;
-    rr[i] = rn;
-    const uint32_t o = (a.skey[i] >> shift) & 7u;
+  auto tally = [&](double rn, uint32_t key) {
+    const uint32_t o = (key >> shift) & 7u;
     const double r2 = rn * rn;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       ss[q] += (o == (uint32_t)q) ? r2 : 0.0;
       cn[q] += (o == (uint32_t)q) ? 1u : 0u;
+    }
+  };
+  if constexpr (P <= 6) {
+    // the next point's inputs are loaded before this point's polynomial, so
+    // their latency overlaps it (larger bases would lose occupancy)
+    TIN nx = 0, ny = 0, nz = 0;
+    double nr = 0.0;
+    uint32_t nk = 0;
+    if (start + tid < end) {
+      const uint32_t i0 = start + tid;
+      nx = ((const TIN*)a.px)[i0];
+      ny = ((const TIN*)a.py)[i0];
+      nz = ((const TIN*)a.pz)[i0];
+      nr = rr[i0];
+      nk = a.skey[i0];
+    }
+    for (uint32_t i = start + tid; i < end; i += 256) {
+      const double x = (double)nx, y = (double)ny, z = (double)nz, rold = nr;
+      const uint32_t key = nk;
+      if (i + 256 < end) {
+        nx = ((const TIN*)a.px)[i + 256];
+        ny = ((const TIN*)a.py)[i + 256];
+        nz = ((const TIN*)a.pz)[i + 256];
+        nr = rr[i + 256];
+        nk = a.skey[i + 256];
+      }
+      const double val = poly_eval<P, double>(Fs, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
+      const double rn = rold - val;
+      rr[i] = rn;
+      tally(rn, key);
+    }
+  } else {
+    for (uint32_t i = start + tid; i < end; i += 256) {
+      double x, y, z;
+      load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
+      const double val = poly_eval<P, double>(Fs, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
+      const double rn = rr[i] - val;
+      rr[i] = rn;
+      tally(rn, a.skey[i]);
     }
   }
   if (!stats) return;
