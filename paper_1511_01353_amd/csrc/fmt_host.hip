@@ -1395,8 +1395,7 @@ static void ensure_composed(Forest& F, int problem, hipStream_t s) {
     F.nb_ccoef.alloc(sizeof(double) * (size_t)ccoef_stride(F.L) * std::max<uint32_t>(F.nodes, 1));
     {
       ProfScope ps(KN_COMPOSE, F.nodes, s);
-      for (size_t d = 0; d < F.level_start.size(); ++d)
-        HIPCHK(launch_compose(F.p, F.table(), F.level_start[d], F.level_count[d], F.nb_ccoef.as<double>(), s));
+      HIPCHK(launch_compose(F.p, F.table(), 0, F.nodes, F.nb_ccoef.as<double>(), s));
     }
     hipEvent_t ev = nullptr;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));

@@ -17,9 +17,11 @@ namespace fmt {
 // re-expands as
 //   u_p^l / l! = sum_{k <= l} (u_c^k / k!) sigma^(l-k) / (2^l (l-k)!),
 // applied axis by axis: a node's composite is its parent's composite shifted
-// into its frame plus its own polynomial (a root's is its own).  One launch
-// per level, parents before children; one wave per node, four nodes per
-// workgroup.
+// into its frame plus its own polynomial (a root's is its own).  One wave per
+// node, four nodes per workgroup, all levels in one launch: each wave walks
+// its node's chain from the root down, shifting and adding level by level,
+// so no node waits for another's result (the same operations, in the same
+// order, as composing level by level).
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t first, uint32_t count,
@@ -29,28 +31,55 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t first, u
   constexpr Basis<P> B{};
   __shared__ double buf[4][2][L];
   __shared__ int ex[L][3];
+  __shared__ uint32_t chain[4][FMT_MAX_LEVELS];
+  __shared__ double invf[P + 1];   // 1 / m!
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   for (int i = tid; i < L; i += 256) {
     ex[i][0] = B.lx[i];
     ex[i][1] = B.ly[i];
     ex[i][2] = B.lz[i];
   }
+  if (tid <= P) {
+    double f = 1.0;
+    for (int m = 2; m <= tid; ++m) f *= (double)m;   // exact: m! < 2^53 for m <= 18
+    invf[tid] = 1.0 / f;
+  }
   __syncthreads();
   const uint32_t k = blockIdx.x * 4 + (uint32_t)w;
   if (k >= count) return;   // the whole wave leaves; no workgroup barrier follows
   const uint32_t v = first + k;
+  const int depth = (int)nt.level[v];
+  if (lane == 0) {
+    // chain[w][d] = the ancestor of v at level d (v itself at its level)
+    uint32_t u = v;
+    for (int d = depth; d >= 0; --d) {
+      chain[w][d] = u;
+      if (d > 0) u = nt.parent[u];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   double* cur = buf[w][0];
   double* nxt = buf[w][1];
-  const double* F = nt.coef + (size_t)v * L;
-  double own[(L + 63) / 64];
+  constexpr int QL = (L + 63) / 64;
+  double own[QL];
+  {
+    const double* F = nt.coef + (size_t)chain[w][0] * L;
 #pragma unroll
-  for (int q = 0; q < (L + 63) / 64; ++q) own[q] = lane + 64 * q < L ? F[lane + 64 * q] : 0.0;
-  if (nt.level[v] > 0) {
-    const uint32_t par = nt.parent[v];
-    const uint32_t o = nt.prefix[v] & 7u;
+    for (int q = 0; q < QL; ++q) own[q] = lane + 64 * q < L ? F[lane + 64 * q] : 0.0;
+  }
+  for (int d = 1; d <= depth; ++d) {
+    // own holds the composite of the level d-1 ancestor; shift it into the
+    // frame of the level d ancestor a and add a's own polynomial
+    const uint32_t a = chain[w][d];
+    const uint32_t o = nt.prefix[a] & 7u;
+    const double* F = nt.coef + (size_t)a * L;
 #pragma unroll
-    for (int q = 0; q < (L + 63) / 64; ++q)
-      if (lane + 64 * q < L) cur[lane + 64 * q] = cc[(size_t)par * CS + lane + 64 * q];
+    for (int q = 0; q < QL; ++q)
+      if (lane + 64 * q < L) cur[lane + 64 * q] = own[q];
+#pragma unroll
+    for (int q = 0; q < QL; ++q) own[q] = lane + 64 * q < L ? F[lane + 64 * q] : 0.0;
 #pragma unroll
     for (int axis = 0; axis < 3; ++axis) {
       const double sg = ((o >> (2 - axis)) & 1u) ? 1.0 : -1.0;
@@ -61,11 +90,14 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t first, u
         int xyz[3] = {ex[e][0], ex[e][1], ex[e][2]};
         const int kk = xyz[axis];
         const int top = P - (xyz[0] + xyz[1] + xyz[2] - kk);
-        double sum = 0.0, t = ldexp(1.0, -kk);
+        double sum = 0.0;
         for (int l = kk; l <= top; ++l) {
+          // sigma^(l-kk) / (2^l (l-kk)!): a table entry, an exact power of
+          // two and a sign (no division in the loop)
+          const int m = l - kk;
+          const double t = ldexp((sg < 0.0 && (m & 1)) ? -invf[m] : invf[m], -l);
           xyz[axis] = l;
           sum = fma(cur[graded(xyz[0], xyz[1], xyz[2])], t, sum);
-          t *= sg / (2.0 * (double)(l + 1 - kk));
         }
         nxt[e] = sum;
       }
@@ -77,8 +109,11 @@ __global__ void __launch_bounds__(256) k_compose(NodeTable nt, uint32_t first, u
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int q = 0; q < (L + 63) / 64; ++q)
+    for (int q = 0; q < QL; ++q)
       if (lane + 64 * q < L) own[q] += cur[lane + 64 * q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 #pragma unroll
   for (int q = 0; q < (CS + 63) / 64; ++q) {

@@ -172,8 +172,9 @@ hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32
 // a row of calL = 84 doubles occupies exactly six lines.
 __host__ __device__ constexpr int ccoef_stride(int L) { return (L + 15) / 16 * 16; }
 // Composite coefficients (a node's chain of polynomials in its frame),
-// ccoef_stride(calL) doubles per node (the tail of a row is zero), of the nodes first .. first+count-1,
-// all of one level; the parents' rows must be in place.
+// ccoef_stride(calL) doubles per node (the tail of a row is zero), of the
+// nodes first .. first+count-1 of any levels (each wave walks its node's
+// chain; no row depends on another).
 hipError_t launch_compose(int p, const NodeTable& nt, uint32_t first, uint32_t count, double* cc, hipStream_t s);
 // Cell table of one tree: 8^T entries, see EvalTree::cells.
 // Also writes the frame table lvl (LVL_DOUBLES) of the tree's problem.
