@@ -176,7 +176,7 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
 // lanes of a quad load one query's row together (each instruction reads 64
 // contiguous bytes, half of one 128-byte line, per query, instead of one
 // line per lane), and the query's own lane evaluates it.  One wave per
-// workgroup; a round's 32 rows take 21.5 KB of LDS at p = 6.
+// workgroup; a round's 32 rows take 22 KB of LDS at p = 6.
 // ---------------------------------------------------------------------------
 constexpr int EVAL_THREADS = 64;
 constexpr int EVAL_ROWS = 32;   // rows staged per round
@@ -190,7 +190,10 @@ __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double*
   constexpr int L = basis_size(P);
   constexpr int CS = ccoef_stride(L);
   constexpr int UP = (L + 1) / 2;   // double pairs of a row that hold coefficients
-  constexpr int LS = 2 * UP;        // LDS row stride (doubles), 16-byte aligned rows
+  // LDS row stride (doubles): rows 16-byte aligned, and LS = 2 mod 4 so that
+  // 16 lanes reading the same coefficient of 16 rows with 16-byte loads hit
+  // 16 distinct groups of four banks
+  constexpr int LS = 2 * UP + ((2 * UP) % 4 == 0 ? 2 : 0);
   static_assert(EVAL_THREADS == 64, "one wave per workgroup");
   __shared__ __attribute__((aligned(16))) double rows[EVAL_ROWS * LS];
   const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
