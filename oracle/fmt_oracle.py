@@ -35,7 +35,7 @@ What is computed (all arithmetic IEEE float64; float32 inputs promoted exactly):
   octant at depth d+1 is the three bits (x highest) of the cells at that depth.
   A point on a split plane goes to the upper octant; a point at x = hi goes to
   the last cell.
-* Fixed-topology transform (the operator I' of Section 3 with the node set
+* Fixed-topology transform (the operator I' of Section 2, eq. identityprime, with the node set
   held fixed): for new values f on the same points, Alg. 2 at every node of an
   existing tree, parents before children, each node fitting the residual its
   ancestors left; no octant test is taken, so the map f -> coefficients is

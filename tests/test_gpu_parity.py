@@ -61,11 +61,13 @@ def compare_topology(tr, ot):
 
 
 def chain_stats(ot, pr, qx, qy, qz):
-    """Per query, over the nodes of its root-to-leaf chain: the largest
-    statistical leverage h_q = ||R^-T Lambda(u_q)||^2 (R: the triangle of the
-    QR of the node's Vandermonde matrix, the oracle's Alg. 2 factor) and the
-    largest condition number of the column-equilibrated triangle.  Data
-    points have h <= 1; h measures how far a query is extrapolated."""
+    """Oracle-side statistics of each query's root-to-leaf chain of nodes:
+    the largest statistical leverage h_q = ||R^-T Lambda(u_q)||^2 (R: the
+    triangle of the QR of the node's Vandermonde matrix, Alg. 2's factor),
+    the largest condition number of the column-equilibrated triangle, and
+    whether the oracle flagged a node of the chain rank-deficient.  Data
+    points have h <= 1; h measures how far a query is extrapolated.  Nothing
+    here depends on the GPU's result."""
     from oracle import fmt_oracle as fo
     D = ot.max_depth
     keys = oracle.morton(oracle.quantise(qx, ot.lo[0], ot.hi[0], D), oracle.quantise(qy, ot.lo[1], ot.hi[1], D),
@@ -74,6 +76,7 @@ def chain_stats(ot, pr, qx, qy, qz):
     q = [np.asarray(a, np.float64) for a in (qx, qy, qz)]
     h = np.zeros(q[0].shape[0])
     kap = np.zeros(q[0].shape[0])
+    rank = np.zeros(q[0].shape[0], dtype=bool)
     for i in range(ot.nodes):
         d, pre = int(ot.level[i]), int(ot.prefix[i])
         sel = (keys >> (3 * (D - d))) == pre
@@ -86,34 +89,48 @@ def chain_stats(ot, pr, qx, qy, qz):
         sv = np.linalg.svd(R / np.linalg.norm(lam, axis=0)[None, :], compute_uv=False)
         kap[sel] = np.maximum(kap[sel], sv[0] / max(sv[-1], 1e-300))
         if ot.rank_deficient[i]:
-            h[sel] = np.inf
+            rank[sel] = True
             continue
         lq = oracle.moments((q[0][sel] - c[0]) * s[0], (q[1][sel] - c[1]) * s[1], (q[2][sel] - c[2]) * s[2], ot.p)
         w = np.linalg.solve(R.T, lq.T)
         h[sel] = np.maximum(h[sel], np.sum(w * w, axis=0))
-    return h, kap, keys
+    return h, kap, rank, keys
 
 
 H_MAX = 1e4      # queries extrapolated further than this are not determined by the data
 KAPPA_MAX = 1e8  # nor are queries under a node this ill-conditioned
 
 
-def compare_eval(ot, nodes, pr, got, want, bound, min_frac=0.5):
-    """Element-wise parity on the queries the data determine: on every node
-    of the chain no rank flag (either side), condition number <= KAPPA_MAX and
-    leverage <= H_MAX; the difference is scaled by max(1, sqrt(h)), the
+def compare_eval(ot, nodes, pr, got, want, bound, min_frac=0.5, stats=None):
+    """Element-wise parity on the queries the data determine, decided on the
+    oracle's side alone: on every node of the chain the oracle's QR is full
+    rank, its equilibrated condition number is <= KAPPA_MAX and the query's
+    leverage is <= H_MAX.  The difference is scaled by max(1, sqrt(h)), the
     sensitivity of a least-squares prediction to perturbations of the data.
-    Every other query must be finite."""
-    h, kap, keys = chain_stats(ot, pr, pr.qx, pr.qy, pr.qz)
+    Every other query must be finite.  Queries under a node the GPU deflated
+    are compared like any other (and reported apart)."""
+    h, kap, rank, keys = stats if stats is not None else chain_stats(ot, pr, pr.qx, pr.qy, pr.qz)
     D = ot.max_depth
-    for i in np.nonzero((nodes["flags"] & 1) != 0)[0]:
-        h[(keys >> (3 * (D - int(ot.level[i])))) == int(ot.prefix[i])] = np.inf
-    ok = (h <= H_MAX) & (kap <= KAPPA_MAX)
+    gpu_defl = np.zeros(keys.shape[0], dtype=bool)
+    defl_nodes = np.nonzero((nodes["flags"] & 1) != 0)[0]
+    for i in defl_nodes:
+        gpu_defl |= (keys >> (3 * (D - int(ot.level[i])))) == int(ot.prefix[i])
+    if defl_nodes.size:
+        print(f"GPU-deflated nodes: {defl_nodes.size}, of which the oracle's QR flags rank-deficient "
+              f"{int(ot.rank_deficient[defl_nodes].sum())}", flush=True)
+    by_rank = rank
+    by_kappa = ~rank & (kap > KAPPA_MAX)
+    by_h = ~rank & ~by_kappa & (h > H_MAX)
+    ok = ~(by_rank | by_kappa | by_h)
     assert np.all(np.isfinite(got))
-    assert ok.mean() >= min_frac, ok.mean()
-    scaled = (got[ok] - want[ok]) / np.maximum(1.0, np.sqrt(h[ok]))
-    err = oracle.rms(scaled)
-    print(f"eval parity on {ok.sum()} of {ok.size} determined queries: rms scaled diff {err:.3e}", flush=True)
+    scaled = (got - want) / np.maximum(1.0, np.sqrt(np.where(ok, h, 0.0)))
+    err = oracle.rms(scaled[ok])
+    err_defl = oracle.rms(scaled[ok & gpu_defl])
+    print(f"eval parity on {ok.sum()} of {ok.size} queries ({ok.mean():.3f}): rms scaled diff {err:.3e}; "
+          f"excluded: oracle rank flag {by_rank.sum()}, kappa > {KAPPA_MAX:g} {by_kappa.sum()}, "
+          f"h > {H_MAX:g} {by_h.sum()}; compared under GPU-deflated nodes {int((ok & gpu_defl).sum())} "
+          f"(rms {err_defl:.3e})", flush=True)
+    assert ok.mean() >= min_frac, (ok.mean(), min_frac)
     assert err <= bound, (err, bound, int((~ok).sum()))
     return err
 
@@ -150,7 +167,7 @@ def test_fp64_path_matches_oracle(fmt, n, p, depth, tol, seed, dtype):
     want = oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)
     for sort in (0, 1):
         got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz), sort_queries=sort).cpu().numpy()
-        compare_eval(ot, nodes, pr, got, want, FP64_RMS)
+        compare_eval(ot, nodes, pr, got, want, FP64_RMS, min_frac=0.95)
     tr.close()
 
 
@@ -163,14 +180,17 @@ def test_config1_workload(fmt):
     info = tr.info()
     assert info.nodes == 73 and info.depth == 2
     got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS)
+    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.95)
 
 
+@pytest.mark.parametrize("refine", [1, 3])
 @pytest.mark.parametrize("seed,p", [(21, 4), (22, 6), (23, 8)])
-def test_mixed_path_matches_oracle(fmt, seed, p):
+def test_mixed_path_matches_oracle(fmt, seed, p, refine):
+    """Mixed path at one refinement sweep (the benchmark's setting: one float64
+    refinement step per node) and at three."""
     pr = synthetic.small_problem(40000, p, seed, tol=1e-7, depth=4, dtype=np.float32, nq=4000)
-    print_case("mixed", pr)
-    tr = run_fit(fmt, pr, path=1, refine=3)
+    print_case(f"mixed refine={refine}", pr)
+    tr = run_fit(fmt, pr, path=1, refine=refine)
     ot = oracle_fit(pr)
     nodes, pts = compare_topology(tr, ot)
     ref = oracle.rms(pr.f.astype(np.float64))
@@ -178,7 +198,7 @@ def test_mixed_path_matches_oracle(fmt, seed, p):
     print(f"mixed fitted-value rms diff {err:.3e} = {err / ref:.3e} x rms(f)", flush=True)
     assert err <= MIXED_REL * ref
     got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), MIXED_REL * ref)
+    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), MIXED_REL * ref, min_frac=0.95)
 
 
 def test_clustered_points_on_faces(fmt):
@@ -190,7 +210,7 @@ def test_clustered_points_on_faces(fmt):
     nodes, pts = compare_topology(tr, ot)
     assert fitted_rms(pr, pts, ot) <= FP64_RMS
     got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.2)
+    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.85)
 
 
 def test_points_on_split_planes_and_faces(fmt):
@@ -309,7 +329,7 @@ def test_batch_equals_single_fits(fmt):
         qa = tb.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
         qs = ts.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
         np.testing.assert_array_equal(qa, qs)
-        compare_eval(ot, nodes, pr, qa, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.2)
+        compare_eval(ot, nodes, pr, qa, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.7)
 
 
 @pytest.mark.parametrize("n,p,depth,clustered,seed", [
@@ -364,4 +384,49 @@ def test_refinement_applies_where_conditioning_needs_it(fmt):
         tr.close()
     tr = run_fit(fmt, well, path=1, refine=3)
     assert np.all((tr.export_nodes()["flags"] & 4) != 0)
+    tr.close()
+
+
+@pytest.fixture(scope="module")
+def config2_oracle():
+    """The benchmark's workload (2^20 uniform float32 points, p = 6, D = 6,
+    tol 1e-8) built exactly as bench.py builds it, fitted by the oracle on the
+    host once for the tests below, with the oracle's evaluation and chain
+    statistics on a seeded sample of 2^16 of its 2^22 queries."""
+    import time
+    pr = synthetic.config2()
+    t0 = time.perf_counter()
+    ot = oracle_fit(pr)
+    print(f"[case] config2 oracle fit: {ot.nodes} nodes in {time.perf_counter() - t0:.0f} s", flush=True)
+    sel = np.sort(np.random.default_rng(2024).choice(pr.qx.shape[0], 1 << 16, replace=False))
+    want = oracle.evaluate(ot, pr.qx[sel], pr.qy[sel], pr.qz[sel])
+    stats = chain_stats(ot, pr, pr.qx[sel], pr.qy[sel], pr.qz[sel])
+    print(f"[case] config2 oracle eval + chain stats done at {time.perf_counter() - t0:.0f} s", flush=True)
+    return pr, ot, sel, want, stats
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("path", ["fp64", "mixed"])
+def test_config2_full_size_matches_oracle(fmt, config2_oracle, path):
+    """The benchmark's fit at its real size and in its launch configuration
+    (pyramid depth 4, thousands of small finest-level nodes; the mixed path
+    with the benchmark's single refinement sweep): topology bit-exact, fitted
+    values within 1e-10 RMS (float64) or 1e-6 of RMS(f) (mixed), and all 2^22
+    queries evaluated as the benchmark does, compared on the sample."""
+    import torch
+    pr, ot, sel, want, stats = config2_oracle
+    print_case(f"config2 full size {path}", pr)
+    tr = run_fit(fmt, pr, path=0 if path == "fp64" else 1, refine=1)
+    nodes, pts = compare_topology(tr, ot)
+    err = fitted_rms(pr, pts, ot)
+    ref = oracle.rms(pr.f.astype(np.float64))
+    bound = FP64_RMS if path == "fp64" else MIXED_REL * ref
+    print(f"fitted-value rms diff {err:.3e} (bound {bound:.1e})", flush=True)
+    assert err <= bound
+    out = torch.empty(pr.qx.shape[0], dtype=torch.float64, device="cuda")
+    tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz), out=out, sort_queries=-1)
+    got = out.cpu().numpy()[sel]
+    sub = synthetic.Problem(x=pr.x, y=pr.y, z=pr.z, f=pr.f, p=pr.p, tol=pr.tol, max_depth=pr.max_depth,
+                            qx=pr.qx[sel], qy=pr.qy[sel], qz=pr.qz[sel])
+    compare_eval(ot, nodes, sub, got, want, bound, min_frac=0.99, stats=stats)
     tr.close()

@@ -77,7 +77,7 @@ def test_refit_matches_oracle(fmt, n, p, depth, tol, seed, dtype, clustered):
         print(f"fitted values rms diff {err:.3e}", flush=True)
         assert err <= FP64_RMS
         got = out.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-        compare_eval(ow, nodes, pr, got, oracle.evaluate(ow, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.2)
+        compare_eval(ow, nodes, pr, got, oracle.evaluate(ow, pr.qx, pr.qy, pr.qz), FP64_RMS, min_frac=0.85)
         out.close()
     tr.close()
 

@@ -122,10 +122,11 @@ def test_batched_workload(fmt):
         worst = max(worst, check_eval_at_points(pr, tr, pts, rng, 512))
     print(f"eval at data points vs f - r: max diff {worst:.2e}", flush=True)
     # oracle parity on a sample: the smallest and the median problem of each
-    # degree.  Clustered points leave many small nodes ill-conditioned; the GPU
-    # drops near-dependent columns there (equilibrated pivot <= 1e-13) and
-    # flags the node, so fewer queries are determined by both fits than for
-    # uniform data (the comparison needs at least 2% of them).
+    # degree.  The queries come from the problem's mixture, so in the smallest
+    # problems many fall far outside their leaf's points (leverage above the
+    # bound) or under a node whose points are coplanar on a clipped face (the
+    # oracle's rank flag): measured coverage is 0.365 at least (problem 29:
+    # 1 017 points, p = 6), hence the floor of 0.3.
     for p in (4, 5, 6):
         ks = sorted([k for k, pr in enumerate(probs) if pr.p == p], key=lambda k: probs[k].n)
         for k in (ks[0], ks[len(ks) // 2]):
@@ -136,7 +137,7 @@ def test_batched_workload(fmt):
             assert fitted_rms(pr, pts, ot) <= FP64_RMS
             want = oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)
             got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
-            compare_eval(ot, nodes, pr, got, want, FP64_RMS, min_frac=0.02)
+            compare_eval(ot, nodes, pr, got, want, FP64_RMS, min_frac=0.3)
     for tr in trees:
         tr.close()
 
