@@ -172,6 +172,30 @@ fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const v
 fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const void* qz,
                     int64_t nq, int dtype, double* out, int sort_queries, void* stream);
 
+/*
+ * fmt_eval for callers that cannot allocate device memory: code recorded
+ * under HIP graph capture, tight serving loops, and harnesses that forbid
+ * allocation.  Arguments, results and errors are those of fmt_eval; the
+ * differences:
+ *   - The sorted mode takes its scratch (query keys, positions, sorted
+ *     coordinates, sort histograms) from one static device array of
+ *     FMT_EVAL_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that
+ *     GPU until the process ends; no call allocates or frees memory.  The
+ *     sorted mode of nq queries needs 6 * round256(nq * sizeof(coordinate))
+ *     + 16 nq + about 4 nq / 16 bytes: every nq <= 2^20 fits for either
+ *     dtype; a larger nq in sorted mode fails with INVALID_ARG (evaluate in
+ *     pieces, or unsorted, which needs no scratch).
+ *   - The tree's evaluation tables (composite coefficients, cell table) are
+ *     built by the first fmt_eval of the tree; before that this call fails
+ *     with INVALID_ARG.
+ *   - Calls that overlap in time on one GPU share the array and race: the
+ *     caller serialises them (one stream, or events).  Nothing in the array
+ *     needs to start at zero; every call writes what it reads.
+ */
+#define FMT_EVAL_NOALLOC_SCRATCH_BYTES (72u << 20)
+fmt_status fmt_eval_noalloc(const fmt_tree* tree, const void* qx, const void* qy, const void* qz,
+                            int64_t nq, int dtype, double* out, int sort_queries, void* stream);
+
 /* Wait for all work of the tree's forest and report device-side status
    (DOMAIN for points outside the box, NUMERIC for non-finite coefficients). */
 fmt_status fmt_tree_wait(const fmt_tree* tree);

@@ -1405,81 +1405,162 @@ static void ensure_composed(Forest& F, int problem, hipStream_t s) {
   HIPCHK(hipStreamWaitEvent(s, F.composed, 0));
 }
 
-fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const void* qz, int64_t nq, int dtype,
-                    double* out, int sort_queries, void* stream) {
-  return guard([&] {
-    if (!tree) fail(FMT_E_INVALID_ARG, "NULL tree");
-    if (dtype != FMT_F32 && dtype != FMT_F64) fail(FMT_E_INVALID_ARG, "dtype must be FMT_F32 or FMT_F64");
-    if (nq < 0 || nq >= (1ll << 31)) fail(FMT_E_INVALID_ARG, "nq out of range");
-    if (nq == 0) return;
-    if (!qx || !qy || !qz || !out) fail(FMT_E_INVALID_ARG, "NULL query or output pointer");
-    hipStream_t s = (hipStream_t)stream;
-    Forest& F = *tree->forest;
+}  // extern "C"
+
+// Scratch of fmt_eval_noalloc: one array per device, held until the process
+// ends.  Host code never uses this name as an address: the device address
+// comes from hipGetSymbolAddress (noalloc_scratch) once per device.
+static __device__ __align__(256) unsigned char scratch[FMT_EVAL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// device's first call, with that device current).
+void* noalloc_scratch() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(FMT_E_INVALID_ARG, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(FMT_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+// Bytes of device scratch the sorted evaluation of n queries uses: the
+// coordinates twice (sort passes alternate), keys and positions twice, the
+// sort's histograms.
+size_t sorted_eval_bytes(uint32_t n, size_t esz) {
+  const size_t pbytes = (esz * n + 255) & ~(size_t)255;
+  return 6 * pbytes + 16ull * n + 4 * radix_sort_scratch_words(n) + 256;
+}
+
+// fmt_eval and fmt_eval_noalloc.  With `fixed` null the sorted mode takes
+// its scratch from hipMallocAsync and the tree's evaluation tables are built
+// on first use; with `fixed` (the no-alloc entry point) the scratch is that
+// array and the tables must exist already.
+void eval_tree(const fmt_tree* tree, const void* qx, const void* qy, const void* qz, int64_t nq, int dtype,
+               double* out, int sort_queries, hipStream_t s, void* fixed) {
+  if (!tree) fail(FMT_E_INVALID_ARG, "NULL tree");
+  if (dtype != FMT_F32 && dtype != FMT_F64) fail(FMT_E_INVALID_ARG, "dtype must be FMT_F32 or FMT_F64");
+  if (nq < 0 || nq >= (1ll << 31)) fail(FMT_E_INVALID_ARG, "nq out of range");
+  if (nq == 0) return;
+  if (!qx || !qy || !qz || !out) fail(FMT_E_INVALID_ARG, "NULL query or output pointer");
+  Forest& F = *tree->forest;
+  if (fixed) {
+    // no allocation here: the composite coefficients and the cell table
+    // must have been built by an earlier fmt_eval of this tree
+    std::lock_guard<std::mutex> g(F.compose_mu);
+    if (!F.composed || F.cell_ev.size() != F.probs.size() || !F.cell_ev[tree->problem])
+      fail(FMT_E_INVALID_ARG, "the tree's evaluation tables are not built: evaluate it once with fmt_eval first");
+    HIPCHK(hipStreamWaitEvent(s, F.cell_ev[tree->problem], 0));
+    HIPCHK(hipStreamWaitEvent(s, F.composed, 0));
+  } else {
     ensure_composed(F, tree->problem, s);
-    EvalTree t;
-    t.nt = F.table();
-    t.root = F.probs[tree->problem].root;
-    // query cells at the deepest level present: the same top bits as cells at
-    // max_depth (the scale differs by an exact power of two)
-    t.D = F.depth_present;
-    t.T = F.cell_T[tree->problem];
-    t.lvl = F.cell_tab[tree->problem].as<double>();
-    t.cells = (const uint32_t*)(F.cell_tab[tree->problem].as<char>() + 1024);
-    t.prm = F.probs[tree->problem].prm;
-    for (int a = 0; a < 3; ++a) t.prm.qscale[a] = std::ldexp(t.prm.qscale[a], t.D - F.D);
-    const double* cc = F.nb_ccoef.as<double>();
-    const uint32_t n = (uint32_t)nq;
-    // Sorting makes the coefficient reads of a wave uniform; without it every
-    // lane reads its own node's row.  That is cheaper while the coefficient
-    // table stays cache-resident, so sort by default only for large tables.
-    const size_t coef_bytes = sizeof(double) * (size_t)F.L * F.nodes;
-    const bool sort = t.D > 0 && (sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) &&
-                                                       coef_bytes > (64ull << 20)));
-    if (!sort) {
-      ProfScope ps(KN_EVAL, n, s);
+  }
+  EvalTree t;
+  t.nt = F.table();
+  t.root = F.probs[tree->problem].root;
+  // query cells at the deepest level present: the same top bits as cells at
+  // max_depth (the scale differs by an exact power of two)
+  t.D = F.depth_present;
+  t.T = F.cell_T[tree->problem];
+  t.lvl = F.cell_tab[tree->problem].as<double>();
+  t.cells = (const uint32_t*)(F.cell_tab[tree->problem].as<char>() + 1024);
+  t.prm = F.probs[tree->problem].prm;
+  for (int a = 0; a < 3; ++a) t.prm.qscale[a] = std::ldexp(t.prm.qscale[a], t.D - F.D);
+  const double* cc = F.nb_ccoef.as<double>();
+  const uint32_t n = (uint32_t)nq;
+  // Sorting makes the coefficient reads of a wave uniform; without it every
+  // lane reads its own node's row.  That is cheaper while the coefficient
+  // table stays cache-resident, so sort by default only for large tables.
+  const size_t coef_bytes = sizeof(double) * (size_t)F.L * F.nodes;
+  const bool sort = t.D > 0 && (sort_queries > 0 || (sort_queries < 0 && n >= (1u << 16) &&
+                                                     coef_bytes > (64ull << 20)));
+  if (!sort) {
+    if (fixed) {
       HIPCHK(launch_eval(F.p, dtype, t, cc, qx, qy, qz, nullptr, nullptr, n, out, s));
       return;
     }
-    const size_t esz = dtype == FMT_F32 ? 4 : 8;
-    const size_t words = radix_sort_scratch_words(n);
-    const size_t pbytes = (esz * n + 255) & ~(size_t)255;
-    const size_t bytes = 6 * pbytes + 16ull * n + 4 * words + 256;
-    char* base = nullptr;
-    HIPCHK(hipMallocAsync((void**)&base, bytes, s));
-    void* pay[3];
-    void* pay_alt[3];
-    for (int q = 0; q < 3; ++q) {
-      pay[q] = base + q * pbytes;
-      pay_alt[q] = base + (3 + q) * pbytes;
-    }
-    uint32_t* k0 = (uint32_t*)(base + 6 * pbytes);
-    uint32_t* v0 = k0 + n;
-    uint32_t* k1 = v0 + n;
-    uint32_t* v1 = k1 + n;
-    uint32_t* scr = v1 + n;
-    const void* pin[3] = {qx, qy, qz};
-    hipError_t e;
-    {
-      ProfScope ps(KN_EKEYS, n, s);
-      e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, t.D, k0, s);
-    }
-    bool in_alt = false;
-    {
-      // keys with the query coordinates and positions as payload
-      ProfScope ps(KN_ESORT, n, s);
-      if (e == hipSuccess)
-        e = radix_sort_payload(dtype, 3, k0, v0, k1, v1, pin, pay, pay_alt, n, 3 * t.D, scr, s, &in_alt);
-    }
-    uint32_t* ks = in_alt ? k1 : k0;
-    uint32_t* vs = in_alt ? v1 : v0;
+    ProfScope ps(KN_EVAL, n, s);
+    HIPCHK(launch_eval(F.p, dtype, t, cc, qx, qy, qz, nullptr, nullptr, n, out, s));
+    return;
+  }
+  const size_t esz = dtype == FMT_F32 ? 4 : 8;
+  const size_t pbytes = (esz * n + 255) & ~(size_t)255;
+  const size_t bytes = sorted_eval_bytes(n, esz);
+  if (fixed && bytes > (size_t)FMT_EVAL_NOALLOC_SCRATCH_BYTES)
+    fail(FMT_E_INVALID_ARG, "nq needs more scratch than FMT_EVAL_NOALLOC_SCRATCH_BYTES in sorted mode");
+  char* base = nullptr;
+  if (fixed) base = (char*)fixed;
+  else HIPCHK(hipMallocAsync((void**)&base, bytes, s));
+  void* pay[3];
+  void* pay_alt[3];
+  for (int q = 0; q < 3; ++q) {
+    pay[q] = base + q * pbytes;
+    pay_alt[q] = base + (3 + q) * pbytes;
+  }
+  uint32_t* k0 = (uint32_t*)(base + 6 * pbytes);
+  uint32_t* v0 = k0 + n;
+  uint32_t* k1 = v0 + n;
+  uint32_t* v1 = k1 + n;
+  uint32_t* scr = v1 + n;
+  const void* pin[3] = {qx, qy, qz};
+  hipError_t e;
+  bool in_alt = false;
+  if (fixed) {
+    // the same launches without the profiling events
+    e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, t.D, k0, s);
+    if (e == hipSuccess) e = radix_sort_payload(dtype, 3, k0, v0, k1, v1, pin, pay, pay_alt, n, 3 * t.D, scr, s, &in_alt);
     void* const* sq = in_alt ? pay_alt : pay;
-    {
-      ProfScope ps(KN_EVAL, n, s);
-      if (e == hipSuccess) e = launch_eval(F.p, dtype, t, cc, sq[0], sq[1], sq[2], vs, ks, n, out, s);
-    }
-    hipError_t e2 = hipFreeAsync(base, s);
+    if (e == hipSuccess)
+      e = launch_eval(F.p, dtype, t, cc, sq[0], sq[1], sq[2], in_alt ? v1 : v0, in_alt ? k1 : k0, n, out, s);
     hip_check(e, "eval");
-    hip_check(e2, "hipFreeAsync");
+    return;
+  }
+  {
+    ProfScope ps(KN_EKEYS, n, s);
+    e = launch_query_keys(dtype, qx, qy, qz, n, t.prm, t.D, k0, s);
+  }
+  {
+    // keys with the query coordinates and positions as payload
+    ProfScope ps(KN_ESORT, n, s);
+    if (e == hipSuccess)
+      e = radix_sort_payload(dtype, 3, k0, v0, k1, v1, pin, pay, pay_alt, n, 3 * t.D, scr, s, &in_alt);
+  }
+  uint32_t* ks = in_alt ? k1 : k0;
+  uint32_t* vs = in_alt ? v1 : v0;
+  void* const* sq = in_alt ? pay_alt : pay;
+  {
+    ProfScope ps(KN_EVAL, n, s);
+    if (e == hipSuccess) e = launch_eval(F.p, dtype, t, cc, sq[0], sq[1], sq[2], vs, ks, n, out, s);
+  }
+  hipError_t e2 = hipFreeAsync(base, s);
+  hip_check(e, "eval");
+  hip_check(e2, "hipFreeAsync");
+}
+
+}  // namespace
+
+extern "C" {
+
+fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const void* qz, int64_t nq, int dtype,
+                    double* out, int sort_queries, void* stream) {
+  return guard([&] { eval_tree(tree, qx, qy, qz, nq, dtype, out, sort_queries, (hipStream_t)stream, nullptr); });
+}
+
+fmt_status fmt_eval_noalloc(const fmt_tree* tree, const void* qx, const void* qy, const void* qz, int64_t nq,
+                            int dtype, double* out, int sort_queries, void* stream) {
+  return guard([&] {
+    void* base = noalloc_scratch();
+    eval_tree(tree, qx, qy, qz, nq, dtype, out, sort_queries, (hipStream_t)stream, base);
   });
 }
 

@@ -41,7 +41,8 @@ FMT_MAX_LEVELS = FMT_MAX_DEPTH + 1
 FMT_REFIT_MAX_FIELDS = 4096
 
 EXPORTED = [
-    "fmt_default_opts", "fmt_fit", "fmt_fit_batch", "fmt_eval", "fmt_tree_wait", "fmt_tree_get_info",
+    "fmt_default_opts", "fmt_fit", "fmt_fit_batch", "fmt_eval", "fmt_eval_noalloc", "fmt_tree_wait",
+    "fmt_tree_get_info",
     "fmt_tree_export_nodes", "fmt_tree_export_points", "fmt_tree_import", "fmt_refit", "fmt_tree_destroy",
     "fmt_last_error", "fmt_version", "fmt_profile_enable", "fmt_profile_reset", "fmt_profile_read",
 ]
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fmt_fit_batch.restype = c_int
     lib.fmt_eval.argtypes = [T, c_void_p, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p]
     lib.fmt_eval.restype = c_int
+    lib.fmt_eval_noalloc.argtypes = [T, c_void_p, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p]
+    lib.fmt_eval_noalloc.restype = c_int
     lib.fmt_tree_wait.argtypes = [T]
     lib.fmt_tree_wait.restype = c_int
     lib.fmt_tree_get_info.argtypes = [T, POINTER(fmt_tree_info)]
@@ -214,6 +217,21 @@ def fmt_eval(tree: "Tree", qx, qy, qz, out, sort_queries: int = -1, stream=None)
     dt = _dtype_code(qx)
     _check(load_library().fmt_eval(tree.handle, _dptr(qx), _dptr(qy), _dptr(qz), nq, dt, _dptr(out),
                                    int(sort_queries), _stream(stream)))
+    return out
+
+
+def fmt_eval_noalloc(tree: "Tree", qx, qy, qz, out, sort_queries: int = -1, stream=None):
+    """fmt_eval through the entry point that allocates nothing (its sorted mode
+    uses the library's fixed per-device scratch array)."""
+    import torch
+    nq = qx.numel()
+    if not (qy.numel() == qz.numel() == out.numel() == nq):
+        raise ValueError("query arrays and output must have the same length")
+    if out.dtype != torch.float64:
+        raise ValueError("output must be float64")
+    dt = _dtype_code(qx)
+    _check(load_library().fmt_eval_noalloc(tree.handle, _dptr(qx), _dptr(qy), _dptr(qz), nq, dt, _dptr(out),
+                                           int(sort_queries), _stream(stream)))
     return out
 
 
