@@ -212,6 +212,149 @@ def refit_leg(fmt, tree_opts, X, Y, Z, pr, m: int, steps: int, warmup: int):
     }
 
 
+def _progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_leg(fmt, steps: int, warmup: int):
+    """Batched workload: 256 independent fits of uneven size (N log-uniform in
+    [1e3, 2e5], Gaussian-mixture points, p in {4, 5, 6}) in one fmt_fit_batch
+    call, each problem's 4 096 mixture queries evaluated; the mixed path (the
+    workload's float32 Gram + float64 solve) and the float64 path."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    probs = synthetic.config3()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    X = [dev(pr.x) for pr in probs]
+    Y = [dev(pr.y) for pr in probs]
+    Z = [dev(pr.z) for pr in probs]
+    Fv = [dev(pr.f) for pr in probs]
+    Q = [(dev(pr.qx), dev(pr.qy), dev(pr.qz)) for pr in probs]
+    outs = [torch.empty(pr.qx.shape[0], dtype=torch.float64, device="cuda") for pr in probs]
+    total = sum(pr.n for pr in probs)
+    nq = sum(pr.qx.shape[0] for pr in probs)
+    truth = np.concatenate([pr.qf_true for pr in probs])
+    res = {}
+    for path in ("mixed", "fp64"):
+        opts = [fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth, refine_steps=1,
+                                     path=fmt.FMT_PATH_MIXED if path == "mixed" else fmt.FMT_PATH_FP64)
+                for pr in probs]
+        for _ in range(max(1, warmup)):
+            for t in fmt.fmt_fit_batch(opts, X, Y, Z, Fv):
+                t.close()
+        torch.cuda.synchronize()
+        fit_t, eval_t = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            trees = fmt.fmt_fit_batch(opts, X, Y, Z, Fv)   # returns with every tree complete
+            t1 = time.perf_counter()
+            for tr, (qx, qy, qz), o in zip(trees, Q, outs):
+                tr.eval(qx, qy, qz, out=o)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            fit_t.append(t1 - t0)
+            eval_t.append(t2 - t1)
+            nodes = sum(int(t.info().nodes) for t in trees)
+            for t in trees:
+                t.close()
+        got = np.concatenate([o.cpu().numpy() for o in outs])
+        res[path] = {"fit_pts_per_s": total / statistics.median(fit_t),
+                     "fit_ms_p50": 1e3 * statistics.median(fit_t), "fit_ms_p99": 1e3 * float(np.percentile(fit_t, 99)),
+                     "eval_pts_per_s": nq / statistics.median(eval_t),
+                     "eval_ms_p50": 1e3 * statistics.median(eval_t), "nodes": nodes,
+                     "E_rms": float(np.sqrt(np.mean((got - truth) ** 2)))}
+        _progress(f"batched {path}: {res[path]['fit_ms_p50']:.2f} ms per batch")
+    return {"workload": "batched uneven problems: 256 fits in one fmt_fit_batch call, N log-uniform [1e3, 2e5] "
+                        "(float32 Gaussian-mixture points, 1-8 components), p in {4,5,6}, depth<=6, tol 1e-8; "
+                        "4096 mixture queries per problem",
+            "problems": len(probs), "points": total, "queries": nq,
+            "value": res["mixed"]["fit_pts_per_s"], "unit": "fit points/s (mixed path)",
+            "paths": res,
+            "E_rms_ratio_minus_1": res["mixed"]["E_rms"] / res["fp64"]["E_rms"] - 1.0}
+
+
+def served_leg():
+    """Served workload: continuous batching of a Poisson request stream (the
+    serve module), latency percentiles at 50% and 80% of the measured
+    saturation rate, device memory against the budget."""
+    from paper_1511_01353_amd.serve import serve_report
+    rep = serve_report(requests=120, budget_gb=16.0, streams=4, seed=4000, loads=(0.5, 0.8), fit_slots=2,
+                       progress=_progress)
+    rep["note"] = "request payloads are host arrays, so latencies include their host-to-device copies"
+    return rep
+
+
+def clustered_leg(fmt, steps: int, warmup: int):
+    """Large clustered workload: 2^26 float32 points from a 32-component
+    Gaussian mixture, p = 8, depth <= 10, tol 1e-8; 2^26 mixture queries
+    (sorted evaluation: the coefficient table is tens of MB); the mixed path
+    (the workload's float32 MFMA Gram + float64 solve + one refinement sweep)
+    and the float64 path; errors against the true function and, when the
+    stored oracle values are present, against the oracle on its sample."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    t0 = time.perf_counter()
+    pr = synthetic.config5()
+    _progress(f"clustered inputs in {time.perf_counter() - t0:.0f} s")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    X, Y, Z, Fv = dev(pr.x), dev(pr.y), dev(pr.z), dev(pr.f)
+    QX, QY, QZ = dev(pr.qx), dev(pr.qy), dev(pr.qz)
+    out = torch.empty(QX.numel(), dtype=torch.float64, device="cuda")
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "config5_oracle.npz")
+    if os.path.exists(gpath):
+        gold = np.load(gpath)
+    res = {}
+    for path in ("mixed", "fp64"):
+        opts = fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth, refine_steps=1,
+                                    path=fmt.FMT_PATH_MIXED if path == "mixed" else fmt.FMT_PATH_FP64)
+        for _ in range(max(1, warmup)):
+            t = fmt.fmt_fit(opts, X, Y, Z, Fv)
+            t.eval(QX, QY, QZ, out=out, sort_queries=1)
+            t.close()
+        torch.cuda.synchronize()
+        fit_t, eval_t = [], []
+        for k in range(steps):
+            t0 = time.perf_counter()
+            tree = fmt.fmt_fit(opts, X, Y, Z, Fv)
+            t1 = time.perf_counter()
+            tree.eval(QX, QY, QZ, out=out, sort_queries=1)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            fit_t.append(t1 - t0)
+            eval_t.append(t2 - t1)
+            if k + 1 < steps:
+                tree.close()
+        fq = out.cpu().numpy()
+        info = tree.info()
+        r = {"fit_pts_per_s": pr.n / statistics.median(fit_t), "fit_ms_p50": 1e3 * statistics.median(fit_t),
+             "eval_pts_per_s": QX.numel() / statistics.median(eval_t), "eval_ms_p50": 1e3 * statistics.median(eval_t),
+             "nodes": int(info.nodes), "depth": int(info.depth),
+             "E_rms": float(np.sqrt(np.mean((fq - pr.qf_true) ** 2))), "E_inf": float(np.max(np.abs(fq - pr.qf_true)))}
+        if gold is not None:
+            sel = gold["query_index"]
+            ok = (~gold["rank"]) & (gold["kappa"] <= 1e8) & (gold["h"] <= 1e4)
+            d = (fq[sel] - gold["want"]) / np.maximum(1.0, np.sqrt(np.where(ok, gold["h"], 0.0)))
+            pts = tree.export_points()
+            r["vs_oracle"] = {"queries_compared": int(ok.sum()), "of": int(sel.shape[0]),
+                              "eval_rms_scaled_diff": float(np.sqrt(np.mean(d[ok] ** 2))),
+                              "residual_rms_diff": float(np.sqrt(np.mean(
+                                  (pts["residual"][gold["point_index"]] - gold["residual"]) ** 2)))}
+        tree.close()
+        res[path] = r
+        _progress(f"clustered {path}: fit {r['fit_ms_p50']:.1f} ms, eval {r['eval_ms_p50']:.1f} ms")
+    return {"workload": "large clustered fit: N=2^26 float32 points from a 32-component Gaussian mixture, "
+                        "4 Gaussian bumps, p=8 (L=165), depth<=10, tol 1e-8; eval 2^26 mixture queries, sorted",
+            "value": res["mixed"]["fit_pts_per_s"], "unit": "fit points/s (mixed path)",
+            "paths": res, "E_rms_ratio_minus_1": res["mixed"]["E_rms"] / res["fp64"]["E_rms"] - 1.0,
+            "oracle_fit_seconds": float(gold["fit_seconds"]) if gold is not None else None,
+            "oracle_threads": int(gold["threads"]) if gold is not None else None}
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -254,7 +397,10 @@ def parse():
     ap.add_argument("--fp64-refine", type=int, default=1)
     ap.add_argument("--no-compare", action="store_true", help="time only the headline path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 17)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16,
+                    help="points of the benchmark workload the one-thread oracle baseline fits")
+    ap.add_argument("--configs", type=str, default="3,4,5",
+                    help="other workloads to run after the headline: 3 batched, 4 served, 5 large clustered")
     ap.add_argument("--refit-fields", type=int, default=8,
                     help="value fields of the fixed-topology refit leg (0: skip it)")
     ap.add_argument("--refit-only", action="store_true",
@@ -379,6 +525,15 @@ def main():
                                     refine_steps=args.mixed_refine if args.path == "mixed" else args.fp64_refine)
         refit = refit_leg(fmt, opts, X, Y, Z, pr, args.refit_fields, args.steps, args.warmup)
 
+    others = {}
+    want = {c.strip() for c in args.configs.split(",") if c.strip()}
+    if "3" in want:
+        others["cfg3"] = batched_leg(fmt, max(3, args.steps // 2), 1)
+    if "4" in want:
+        others["cfg4"] = served_leg()
+    if "5" in want:
+        others["cfg5"] = clustered_leg(fmt, 3, 1)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pr, args.cpu_sample)
@@ -413,6 +568,7 @@ def main():
                     for k, st in h["kernels"].items()},
         "mixed_vs_fp64": cmp,
         "refit": refit,
+        **others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
@@ -427,22 +583,45 @@ def main():
 
 
 def cpu_baseline(pr, sample: int):
-    """The FP64 oracle on the first `sample` points of the same workload (host cores)."""
+    """The FP64 oracle on the host cores: the whole benchmark workload on all
+    threads (the same tree as the GPU's), a sample of it on one thread, and
+    the small workload on one and on all threads."""
     import numpy as np
 
     import oracle
+    import synthetic
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
+        threadpool_limits = None
         threads = os.cpu_count() or 1
-    n = min(sample, pr.n)
-    t0 = time.perf_counter()
-    oracle.fit(pr.x[:n], pr.y[:n], pr.z[:n], pr.f[:n], pr.p, pr.tol, pr.max_depth)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "fit points/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {n} points of the same workload (p={pr.p}, depth<={pr.max_depth}, tol={pr.tol}); "
-                      f"{dt:.1f} s"}
+
+    def timed(p, n=None):
+        n = p.n if n is None else min(n, p.n)
+        t0 = time.perf_counter()
+        oracle.fit(p.x[:n], p.y[:n], p.z[:n], p.f[:n], p.p, p.tol, p.max_depth)
+        return n, time.perf_counter() - t0
+
+    n_all, dt_all = timed(pr)
+    _progress(f"cpu oracle, {n_all} points, {threads} threads: {dt_all:.1f} s")
+    small = synthetic.config1()
+    variants = []
+    n1, d1 = timed(small)
+    variants.append({"workload": "small: N=4096 uniform float64, p=4, depth 3 (73 nodes)", "threads": int(threads),
+                     "value": n1 / d1, "seconds": d1})
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, d1 = timed(small)
+            variants.append({"workload": "small: N=4096 uniform float64, p=4, depth 3 (73 nodes)", "threads": 1,
+                             "value": n1 / d1, "seconds": d1})
+            ns, ds = timed(pr, sample)
+            variants.append({"workload": f"benchmark workload, first {ns} points", "threads": 1,
+                             "value": ns / ds, "seconds": ds})
+    return {"value": n_all / dt_all, "unit": "fit points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"all {n_all} points of the benchmark workload (p={pr.p}, depth<={pr.max_depth}, "
+                      f"tol={pr.tol}; the same tree as the GPU fit); {dt_all:.1f} s",
+            "variants": variants}
 
 
 if __name__ == "__main__":

@@ -67,7 +67,10 @@ typedef enum {
   FMT_PATH_FP64 = 0,
   /* Gram of the monomials on float32 MFMA (float32 accumulation within a
      chunk of points, chunks summed in float64); float64 Cholesky; float64
-     refinement sweeps (residual, Lambda^T r) recover float64 accuracy */
+     refinement sweeps (residual, Lambda^T r) recover float64 accuracy.
+     Nodes whose float32 Gram is too ill-conditioned for that (estimated
+     condition number above 1e6, or a deflated pivot) are solved again from
+     float64 power moments */
   FMT_PATH_MIXED = 1
 } fmt_path;
 
@@ -217,7 +220,11 @@ fmt_status fmt_tree_get_info(const fmt_tree* tree, fmt_tree_info* info);
  *            bit 2 set if the node's coefficients went through the
  *            refinement sweep (always on the mixed path; on the float64 path
  *            only for nodes whose normal equations are ill-conditioned or
- *            deflated, see fmt_fit_opts.refine_steps)
+ *            deflated, see fmt_fit_opts.refine_steps);
+ *            bit 3 set (mixed path) if the node's float32 Gram was too
+ *            ill-conditioned (estimated condition number above 1e6, or a
+ *            deflated pivot) and its normal equations were formed again
+ *            from float64 power moments
  */
 fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t* prefix,
                                  uint32_t* begin, uint32_t* count, uint32_t* flags, double* coeffs);

@@ -154,6 +154,9 @@ struct NodeTable {
 constexpr uint32_t FLAG_DEFLATED = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
 constexpr uint32_t FLAG_REFINE = 4u;   // the refinement sweeps apply to this node
+// mixed path: the node's float32 Gram was too ill-conditioned to solve from,
+// so its normal equations were formed again from float64 moments
+constexpr uint32_t FLAG_REGRAM = 8u;
 
 // Per-problem parameters of one batched fit.
 struct ProblemParams {

@@ -58,10 +58,10 @@ const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce",
                               "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval", "compose",
                               "bmoments", "base_moments", "pyramid", "refit_gather", "refit_moments",
                               "refit_factor", "refit_bmoments", "refit_solve", "refit_residual", "factor_ahead",
-                              "solve_ahead"};
+                              "solve_ahead", "regram"};
 enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
        KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_BMOM, KN_BASEM, KN_PYR, KN_XGATHER, KN_XMOM, KN_XFACTOR,
-       KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_UPFAC, KN_FSOLVE, KN_COUNT };
+       KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_UPFAC, KN_FSOLVE, KN_REGRAM, KN_COUNT };
 static_assert(sizeof(kKernelNames) / sizeof(kKernelNames[0]) == KN_COUNT, "one name per kernel class");
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -188,6 +188,8 @@ struct Workspace {
   // px, py, pz, pf: key-ordered inputs (payload set A); px2 .. pf2: set B
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status;
+  // float64 moment partials of the mixed path's re-solved nodes
+  DevBuf part_rg;
   // a fit's small tables (parameters, pointers, pyramid table, level-0 chunk
   // offsets, status word, flags of the factors made ahead), filled by one copy
   DevBuf small;
@@ -827,6 +829,9 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     a.fac_up = up_cells ? W.fac_up.as<double>() : nullptr;
     a.up_flags = up_cells ? d_upflags : nullptr;
     a.status = d_status;
+    // the mixed path's float32 Gram: too ill-conditioned nodes go to a
+    // float64 re-solve
+    a.regram = F->path == FMT_PATH_MIXED ? 1u : 0u;
 
     const bool multi = nchunks > nnodes;   // some node spans several chunks
     if (lvl_pyr) {
@@ -859,6 +864,20 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
           HIPCHK(launch_solve_moments(F->p, a, W.partial.as<double>(), W.part_m2.as<double>(), W.pyr.as<double>(),
                                       fac, s));
         else HIPCHK(launch_solve(F->p, a, W.partial.as<double>(), fac, s));
+      }
+      if (a.regram) {
+        // nodes whose float32 Gram the solve refused (FLAG_REGRAM): float64
+        // power moments of their chunks, then the float64 solve; the other
+        // nodes' workgroups exit at once
+        ProfScope ps(KN_REGRAM, level_points, s);
+        const size_t mpd = moment_partial_doubles(F->p);
+        W.part_rg.reserve(8ull * mpd * nchunks);
+        LevelArgs r = a;
+        r.regram = 0;
+        r.only_flag = FLAG_REGRAM;
+        HIPCHK(launch_moments(F->p, 0, dtype, r, W.part_rg.as<double>(), s));
+        if (multi) HIPCHK(launch_chunk_reduce(r, W.part_rg.as<double>(), (uint32_t)mpd, s));
+        HIPCHK(launch_solve_moments(F->p, r, W.part_rg.as<double>(), nullptr, nullptr, fac, s));
       }
     }
     for (int it = 0; it < F->refine; ++it) {

@@ -42,6 +42,14 @@ struct LevelArgs {
   // status word: the solves mark nodes whose coefficients are not all finite
   // (FLAG_NONFINITE) and set bit 2 here; null: no check
   uint32_t* status = nullptr;
+  // nonzero: the Gram partials are float32 sums (the mixed path); k_solve
+  // flags FLAG_REGRAM on nodes whose condition estimate exceeds REGRAM_KAPPA
+  // or that deflate a pivot, and leaves their coefficients to the float64
+  // re-solve
+  uint32_t regram = 0;
+  // nonzero: k_moments (mode 0), k_chunk_reduce and k_solve_m take only the
+  // nodes whose flags hold one of these bits (the float64 re-solve)
+  uint32_t only_flag = 0;
 };
 
 // Nodes with fewer points than this take the r-weighted moments in mode 4

@@ -304,6 +304,11 @@ __device__ __forceinline__ void tri_solve_wave(const double* A, const double* iv
 // solve's fitted values are accurate to ~1e-13 relative, and one sweep is
 // applied above it.
 constexpr double REFINE_KAPPA = 1e6;
+// Mixed path: a float32 Gram carries entry errors of a few 1e-10 relative
+// (float32 sums over short runs of points, flushed to float64), so above
+// this estimated condition number its solve, even refined, misses the
+// float64 answer; such nodes are solved again from float64 moments.
+constexpr double REGRAM_KAPPA = 1e6;
 
 // Entry i of the fixed probe vector `which` (0 or 1): +-1/sqrt(L) with signs
 // from an integer hash, so the estimate is deterministic.
@@ -325,16 +330,24 @@ __host__ __device__ constexpr size_t factor_words() {
 // coef: the node's coefficient row; flag: its flag word; fout: where the
 // factor goes (null: nowhere).  With SOLVE false only the factor is made (no
 // right-hand side; b, z and coef may be null) and it is always stored.
+// With regram (float32 Gram partials): a node whose estimate exceeds
+// REGRAM_KAPPA or that deflates a pivot gets FLAG_REGRAM and nothing else
+// (no coefficients, flags or factor): the float64 re-solve takes it.
 template <int L, bool SOLVE = true>
 __device__ __forceinline__ void factor_solve_store(double* A, double* b, double* z, double* dv, double* iv,
                                                    const double* sc, double (*xv)[L], double (*yv)[L], int refine,
                                                    double* coef, uint32_t* flag, double* fout,
-                                                   uint32_t* status = nullptr) {
+                                                   uint32_t* status = nullptr, bool regram = false) {
   using S = BlockShape<L>;
   __shared__ int need_factor;   // the refinement sweeps will apply to this node
+  __shared__ int any_deflated, to_regram;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const bool estimate = refine == 1;
-  if (tid == 0) need_factor = !SOLVE || refine == 2;
+  const bool estimate = refine == 1 || regram;
+  if (tid == 0) {
+    need_factor = !SOLVE || refine == 2;
+    any_deflated = 0;
+    to_regram = 0;
+  }
   if (estimate)
     for (int e = tid; e < 2 * L; e += 256) xv[e / L][e % L] = probe_entry(e % L, e / L, L);
   ldl_blocked<L>(A, dv, iv);
@@ -347,30 +360,41 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
     tri_solve_wave<L>(A, iv, xv[w - 1], yv[w - 1]);
   }
   __syncthreads();
-  bool deflated = false, bad = false;
-  for (int i = tid; i < L; i += 256) {
-    if constexpr (SOLVE) {
-      const double c = sc[i] * z[i];
-      coef[i] = c;
-      bad |= !__builtin_isfinite(c);
-    }
+  bool deflated = false;
+  for (int i = tid; i < L; i += 256)
     if (iv[i] == 0.0) deflated = true;
-  }
-  if constexpr (SOLVE) mark_nonfinite(bad, flag, status);
+  if (deflated) any_deflated = 1;
   if (estimate && (w == 1 || w == 2)) {
     double ss = 0.0;
     for (int i = lane; i < L; i += 64) ss += yv[w - 1][i] * yv[w - 1][i];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) ss += __shfl_xor(ss, off);
-    if (lane == 0 && (double)L * sqrt(ss) > REFINE_KAPPA) {
+    const double kappa = (double)L * sqrt(ss);
+    if (lane == 0 && regram && !(kappa <= REGRAM_KAPPA)) to_regram = 1;
+    if (lane == 0 && refine == 1 && kappa > REFINE_KAPPA) {
       atomicOr(flag, FLAG_REFINE);
       need_factor = 1;
     }
   }
+  __syncthreads();
+  if (regram && (to_regram || any_deflated)) {
+    if (tid == 0) atomicOr(flag, FLAG_REGRAM);
+    return;   // uniform: the whole workgroup leaves the node to the float64 re-solve
+  }
+  if constexpr (SOLVE) {
+    bool bad = false;
+    for (int i = tid; i < L; i += 256) {
+      const double c = sc[i] * z[i];
+      coef[i] = c;
+      bad |= !__builtin_isfinite(c);
+    }
+    mark_nonfinite(bad, flag, status);
+  }
+  deflated = any_deflated != 0;
   if (refine == 2) {
     if (tid == 0) atomicOr(flag, FLAG_REFINE);
   } else if (estimate && deflated) {
-    atomicOr(flag, FLAG_REFINE);
+    if (tid == 0) atomicOr(flag, FLAG_REFINE);
     need_factor = 1;
   }
   __syncthreads();
@@ -384,7 +408,7 @@ __device__ __forceinline__ void factor_solve_store(double* A, double* b, double*
       fo[S::WORDS + 2 * L + i] = sc[i];
     }
   }
-  if (deflated) atomicOr(flag, FLAG_DEFLATED);
+  if (deflated && tid == 0) atomicOr(flag, FLAG_DEFLATED);
 }
 
 // Fill the blocked matrix in storage order: thread t writes word t of every
@@ -445,7 +469,7 @@ __global__ void __launch_bounds__(256) k_solve(LevelArgs a, const double* __rest
   assemble_blocked<L>(A, [&](int i, int q) { return (i <= q ? gram(i, q) : gram(q, i)) * sc[i] * sc[q]; });
   __syncthreads();
   factor_solve_store<L>(A, b, z, dv, iv, sc, xv, yv, a.refine, a.nt.coef + (size_t)node * L, a.nt.flags + node,
-                        fac ? fac + (size_t)k * factor_words<L>() : nullptr, a.status);
+                        fac ? fac + (size_t)k * factor_words<L>() : nullptr, a.status, a.regram != 0);
 }
 
 // Equilibrated normal equations from power moments in LDS: mom[0 .. NM) the
@@ -533,6 +557,7 @@ __global__ void __launch_bounds__(256) k_solve_m(LevelArgs a, const double* __re
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
+  if (a.only_flag && !(a.nt.flags[node] & a.only_flag)) return;   // whole workgroup: not this pass's node
   const uint32_t* pt = a.pyr_tab ? a.pyr_tab + PYR_TAB_WORDS * a.nt.problem[node] : nullptr;
   if (pt && a.fac_up && (pt[3] >> 28) > (uint32_t)a.level) return;   // factored ahead: k_solve_ahead
   if (pt && pyramid_covers(pt[1], a.level)) {
@@ -995,13 +1020,15 @@ __global__ void __launch_bounds__(256) k_children(LevelArgs a, const double* __r
 // Single-chunk nodes exit at once.
 __global__ void __launch_bounds__(1024) k_chunk_reduce(const uint32_t* __restrict__ chunk_off, uint32_t nnodes,
                                                        double* __restrict__ buf, uint32_t width, uint32_t eblocks,
-                                                       uint64_t fstride) {
+                                                       uint64_t fstride, const uint32_t* __restrict__ flags,
+                                                       uint32_t only_flag) {
   __shared__ double part[16][64];
   buf += (size_t)blockIdx.y * fstride;   // the field's partials
   const uint32_t k = blockIdx.x / eblocks;
   if (k >= nnodes) return;
   const uint32_t c0 = chunk_off[k], c1 = chunk_off[k + 1];
   if (c1 - c0 < 2) return;
+  if (only_flag && !(flags[k] & only_flag)) return;   // not this pass's node
   const uint32_t lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const uint32_t e = (blockIdx.x % eblocks) * 64 + lane;
   double acc[8];
@@ -1276,7 +1303,7 @@ hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, 
   if (a.nnodes == 0 || a.nchunks <= a.nnodes) return hipSuccess;
   const uint32_t eblocks = (width + 63) / 64;
   hipLaunchKernelGGL(k_chunk_reduce, dim3(a.nnodes * eblocks, field_rows(a)), dim3(1024), 0, s, a.chunk_off,
-                     a.nnodes, buf, width, eblocks, (uint64_t)a.nchunks * width);
+                     a.nnodes, buf, width, eblocks, (uint64_t)a.nchunks * width, a.nt.flags + a.node0, a.only_flag);
   return hipGetLastError();
 }
 

@@ -280,6 +280,9 @@ k_moments(LevelArgs a, double* __restrict__ part) {
     // a level split between the pyramid's nodes (modes 2, 4) and the others
     if (a.pyr_tab && pyramid_covers(a.pyr_tab[PYR_TAB_WORDS * a.nt.problem[node] + 1], a.level) != (MODE != 0)) return;
   }
+  if constexpr (MODE == 0) {
+    if (a.only_flag && !(a.nt.flags[node] & a.only_flag)) return;   // not this pass's node
+  }
   // modes 2 and 4 split the nodes by size
   if constexpr (MODE == 2) {
     if (nc < SMALL_NODE) return;

@@ -201,6 +201,49 @@ def test_mixed_path_matches_oracle(fmt, seed, p, refine):
     compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), MIXED_REL * ref, min_frac=0.95)
 
 
+@pytest.mark.parametrize("seed,p", [(24, 4), (25, 6), (26, 8)])
+def test_mixed_path_clustered_matches_oracle(fmt, seed, p):
+    """Mixed path on clustered points (many ill-conditioned nodes, points on
+    clipped faces) at the benchmark's single refinement sweep: nodes whose
+    float32 Gram is too ill-conditioned are re-solved from float64 moments
+    (flag bit 3), and every fitted value stays within 1e-6 of RMS(f)."""
+    pr = synthetic.small_problem(30000, p, seed, tol=1e-7, depth=5, dtype=np.float32, clustered=True, nq=4000)
+    print_case("mixed clustered", pr)
+    tr = run_fit(fmt, pr, path=1, refine=1)
+    ot = oracle_fit(pr)
+    nodes, pts = compare_topology(tr, ot)
+    regram = (nodes["flags"] & 8) != 0
+    print(f"re-solved from float64 moments: {int(regram.sum())} of {regram.size} nodes", flush=True)
+    ref = oracle.rms(pr.f.astype(np.float64))
+    err = fitted_rms(pr, pts, ot)
+    print(f"mixed fitted-value rms diff {err:.3e} = {err / ref:.3e} x rms(f)", flush=True)
+    assert err <= MIXED_REL * ref
+    got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
+    compare_eval(ot, nodes, pr, got, oracle.evaluate(ot, pr.qx, pr.qy, pr.qz), MIXED_REL * ref, min_frac=0.5)
+    tr.close()
+
+
+def test_mixed_batch_matches_oracle(fmt):
+    """Mixed path on batched mixture problems (the batched workload's path):
+    each problem's topology bit-exact and fitted values within 1e-6 of
+    RMS(f) of the oracle."""
+    probs = synthetic.config3(seed0=3000, count=8, nlo=2e3, nhi=6e4, nq=500)
+    opts = [fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth, path=1, refine_steps=1)
+            for pr in probs]
+    trees = fmt.fmt_fit_batch(opts, [dev(p.x) for p in probs], [dev(p.y) for p in probs],
+                              [dev(p.z) for p in probs], [dev(p.f) for p in probs])
+    for pr, tb in zip(probs, trees):
+        print_case("mixed batch member", pr)
+        ot = oracle_fit(pr)
+        nodes, pts = compare_topology(tb, ot)
+        ref = oracle.rms(pr.f.astype(np.float64))
+        err = fitted_rms(pr, pts, ot)
+        print(f"re-solved {int(((nodes['flags'] & 8) != 0).sum())} of {len(nodes['flags'])} nodes; "
+              f"fitted-value rms diff {err / ref:.3e} x rms(f)", flush=True)
+        assert err <= MIXED_REL * ref
+        tb.close()
+
+
 def test_clustered_points_on_faces(fmt):
     pr = synthetic.small_problem(30000, 4, 31, tol=1e-7, depth=5, dtype=np.float32, clustered=True, nq=3000)
     print_case("clustered", pr)

@@ -1,7 +1,8 @@
 """Continuous batching on the GPU: requests served with overlap give the
 same results as each request run alone (bitwise: a batched fit reduces
 every problem's nodes in the same chunk order as a single fit, and
-evaluation is deterministic)."""
+evaluation is deterministic); the device memory measured while serving stays
+under the budget; a sample of the served fits matches the oracle."""
 import numpy as np
 import pytest
 
@@ -31,6 +32,9 @@ def test_served_results_equal_alone(fmt):
     assert len(done) == len(reqs)
     assert all(r.error is None for r in done), [r.error for r in done if r.error]
     assert srv.peak <= srv.budget
+    # measured device memory (the device's used bytes less those in use
+    # before serving), sampled at every admission, against the budget
+    assert srv.peak_measured is not None and srv.peak_measured <= srv.budget
     st = srv.stats()
     print(st, flush=True)
     by = {r.rid: r for r in done}
@@ -46,6 +50,16 @@ def test_served_results_equal_alone(fmt):
         a, b = served.export_points(), t.export_points()
         np.testing.assert_array_equal(a["residual"], b["residual"])
         np.testing.assert_array_equal(served.export_nodes()["coeffs"], t.export_nodes()["coeffs"])
+    # the two smallest served fits against the oracle
+    import oracle
+    from test_gpu_parity import FP64_RMS, compare_topology
+    fits = sorted([r for r in reqs if r.kind == "fit"], key=lambda r: r.n)[:2]
+    for r in fits:
+        x, y, z, f = r.payload
+        print(f"[case] served fit {r.rid} against the oracle: n={r.n}", flush=True)
+        ot = oracle.fit(x, y, z, f, r.opts["p"], r.opts["tol"], r.opts["max_depth"])
+        _, pts = compare_topology(by[r.rid].result, ot)
+        assert oracle.rms(pts["residual"] - ot.residual) <= FP64_RMS
     for r in reqs:
         if r.kind != "eval":
             continue

@@ -27,6 +27,7 @@ class FakeExecutor:
         self.concurrent_evals = 0
         self.max_concurrent_evals = 0
         self.reads = []   # (tree, start, end) of every evaluation
+        self.fit_starts = []   # (start, end, slot) of every fit batch
 
     def fit_footprint(self, req):
         return 100 * req.n
@@ -41,8 +42,9 @@ class FakeExecutor:
         self.live_trees.discard(tree)
         self.released.append((tree, self.clock()))
 
-    def start_fit_batch(self, reqs):
+    def start_fit_batch(self, reqs, slot=0):
         end = self.clock() + sum(r.n for r in reqs) / self.fit_rate
+        self.fit_starts.append((self.clock(), end, slot))
         return {"kind": "fit", "end": end, "reqs": reqs}
 
     def start_eval(self, req, tree):
@@ -117,7 +119,7 @@ def test_fits_arriving_together_are_batched():
     reqs = [Request(rid=i, kind="fit", arrival=0.0, n=1000, opts={"p": 4}) for i in range(5)]
     batches = []
     orig = ex.start_fit_batch
-    ex.start_fit_batch = lambda rs: (batches.append(len(rs)), orig(rs))[1]
+    ex.start_fit_batch = lambda rs, slot=0: (batches.append(len(rs)), orig(rs, slot))[1]
     drive(srv, reqs, ex, clock)
     assert batches == [5]
 
@@ -178,3 +180,50 @@ def test_oversized_request_is_rejected_not_stalled():
     done = drive(srv, reqs, ex, clock)
     errs = {r.rid: r.error for r in done}
     assert errs[0] and errs[1] and errs[2] is None
+
+
+def max_overlap(spans):
+    ev = sorted([(a, 1) for a, b, _ in spans] + [(b, -1) for a, b, _ in spans], key=lambda t: (t[0], t[1]))
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+@pytest.mark.parametrize("slots", [1, 2])
+def test_fit_batches_in_flight_bounded_by_slots(slots):
+    """A fit arriving while a batch runs starts at once in a free fit slot
+    (on its own stream) when memory allows; with one slot it waits."""
+    clock = FakeClock()
+    ex = FakeExecutor(clock, fit_rate=1e6)
+    srv = Server(ex, budget_bytes=100_000_000, clock=clock, fit_slots=slots)
+    reqs = [Request(rid=0, kind="fit", arrival=0.0, n=20000, opts={"p": 4}),
+            Request(rid=1, kind="fit", arrival=0.001, n=20000, opts={"p": 4}),
+            Request(rid=2, kind="fit", arrival=0.002, n=20000, opts={"p": 4})]
+    drive(srv, reqs, ex, clock)
+    # with one slot the two later fits wait together and go as one batch
+    assert len(ex.fit_starts) == (3 if slots == 2 else 2)
+    assert max_overlap(ex.fit_starts) == slots
+    # concurrent batches never share a slot
+    for i, (a, b, s) in enumerate(ex.fit_starts):
+        for a2, b2, s2 in ex.fit_starts[i + 1:]:
+            if a2 < b and a < b2:
+                assert s != s2
+
+
+def test_workspace_counted_against_the_budget():
+    """The library's per-stream fit workspace (grow-only) is part of the
+    memory in use: a second slot's workspace is admitted only if it fits."""
+    clock = FakeClock()
+    ex = FakeExecutor(clock, fit_rate=1e6)
+    ex.workspace_bytes = lambda rs: 50 * sum(r.n for r in rs)
+    # one fit (footprint 100 n) plus its workspace (50 n) fits; two do not
+    n = 10000
+    srv = Server(ex, budget_bytes=int(1.6 * 150 * n), clock=clock, fit_slots=2)
+    reqs = [Request(rid=0, kind="fit", arrival=0.0, n=n, opts={"p": 4}),
+            Request(rid=1, kind="fit", arrival=0.001, n=n, opts={"p": 4})]
+    drive(srv, reqs, ex, clock)   # asserts used() <= budget at every tick
+    assert max_overlap(ex.fit_starts) == 1
+    assert all(r.error is None for r in srv.finished)
+    assert srv.peak <= srv.budget
