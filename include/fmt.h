@@ -43,7 +43,8 @@
 extern "C" {
 #endif
 
-#define FMT_MAX_P 8          /* largest supported total degree (calL = 165) */
+#define FMT_MAX_P 14         /* largest supported total degree (calL = 680); the
+                                supported orders are 0..8, 10, 12 and 14 */
 #define FMT_MAX_DEPTH 10     /* deepest supported level; keys use 3*D bits */
 #define FMT_MAX_LEVELS (FMT_MAX_DEPTH + 1)
 #define FMT_REFIT_MAX_FIELDS 4096   /* value fields one fmt_refit call takes */
@@ -91,7 +92,11 @@ typedef enum {
 } fmt_gram;
 
 typedef struct {
-  int p;               /* maximum total degree, 0..FMT_MAX_P */
+  int p;               /* maximum total degree: 0..8, 10, 12 or 14.  The
+                          large orders (calL = 286, 455, 680) take the float64
+                          path with per-level power moments and a tiled
+                          solve in device memory; they have no mixed path,
+                          MFMA Gram or fixed-topology refit */
   double tol;          /* tau: split tolerance on the octant RMS residual, >= 0 */
   int max_depth;       /* D, 0..FMT_MAX_DEPTH; the root is depth 0 */
   int path;            /* fmt_path */

@@ -13,7 +13,11 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
-SOURCES = ["k_sort.hip", "k_gram.hip", "k_moments.hip", "k_pyramid.hip", "k_level.hip", "k_eval.hip", "fmt_host.hip"]
+SOURCES = ["k_sort.hip", "k_gram.hip", "k_moments.hip", "k_pyramid.hip", "k_level.hip", "k_eval.hip", "k_wide.hip",
+           "fmt_host.hip"]
+# (source, extra flags, object): the moment kernels of each large order are
+# compiled in an object of their own, in parallel with the rest
+VARIANTS = [("k_moments.hip", [f"-DFMT_MOMENTS_WIDE_P={p}"], f"k_moments_p{p}.o") for p in (10, 12, 14)]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -31,8 +35,8 @@ def hipcc() -> str:
     return path
 
 
-def _compile(src: str, obj: str) -> str:
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(HERE, src), "-o", obj]
+def _compile(src: str, obj: str, extra=()) -> str:
+    cmd = [hipcc(), *FLAGS, *extra, "-c", os.path.join(HERE, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -42,9 +46,13 @@ def _compile(src: str, obj: str) -> str:
 def build(verbose: bool = False) -> str:
     out = os.path.join(PKG, LIB_NAME)
     with tempfile.TemporaryDirectory(prefix="fmt_build_") as tmp:
-        objs = [os.path.join(tmp, s.replace(".hip", ".o")) for s in SOURCES]
-        with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-            list(ex.map(_compile, SOURCES, objs))
+        jobs = [(s, os.path.join(tmp, s.replace(".hip", ".o")), []) for s in SOURCES]
+        jobs += [(s, os.path.join(tmp, o), f) for s, f, o in VARIANTS]
+        # the slowest objects first, so they overlap the rest
+        jobs.sort(key=lambda j: 0 if ("moments" in j[0] or "level" in j[0] or "eval" in j[0]) else 1)
+        objs = [j[1] for j in jobs]
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+            list(ex.map(lambda j: _compile(*j), jobs))
         tmp_lib = os.path.join(tmp, LIB_NAME)
         cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -432,7 +432,10 @@ int ceil_log2(int k) {
 }
 
 void validate_opts(const fmt_fit_opts& o) {
-  if (o.p < 0 || o.p > FMT_MAX_P) fail(FMT_E_INVALID_ARG, "p out of range 0..FMT_MAX_P");
+  if (o.p < 0 || o.p > FMT_MAX_P || (o.p > 8 && !wide_order(o.p)))
+    fail(FMT_E_INVALID_ARG, "p must be 0..8, 10, 12 or 14");
+  if (o.p > 8 && o.path != FMT_PATH_FP64) fail(FMT_E_INVALID_ARG, "the mixed path supports p <= 8");
+  if (o.p > 8 && o.gram == FMT_GRAM_MFMA) fail(FMT_E_INVALID_ARG, "the MFMA Gram supports p <= 8");
   if (o.max_depth < 0 || o.max_depth > FMT_MAX_DEPTH) fail(FMT_E_INVALID_ARG, "max_depth out of range 0..10");
   if (!(o.tol >= 0.0) || std::isinf(o.tol)) fail(FMT_E_INVALID_ARG, "tol must be finite and >= 0");
   if (o.path != FMT_PATH_FP64 && o.path != FMT_PATH_MIXED) fail(FMT_E_INVALID_ARG, "unknown path");
@@ -546,6 +549,10 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   F->dtype = dtype;
   F->refine = o.refine_steps;
   F->gram = o.path == FMT_PATH_MIXED ? FMT_GRAM_MFMA : o.gram;
+  // large bases: per-level moments (no pyramid: its frame shifts of moments
+  // up to degree 2p = 28 would cancel too many digits) and the tiled solve
+  const bool wide = wide_order(o.p);
+  if (wide) F->gram = FMT_GRAM_MOMENTS_LEVEL;
   F->nprob = (int)in.size();
   F->stream = s;
   HIPCHK(hipGetDevice(&F->device));
@@ -785,7 +792,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   const uint32_t* cur_off = reinterpret_cast<const uint32_t*>(sm + o_off);
   DevBuf* next_off = &W.chunk_a;
   const size_t gpd = use_moments ? moment_partial_doubles(F->p) : gram_partial_doubles(F->p);
-  const size_t fd = factor_doubles(F->p);
+  const size_t fd = wide ? wide_factor_doubles(F->p) : factor_doubles(F->p);
   const size_t rbd = moment_refine_doubles(F->p);
   for (int d = 0; d <= F->D && nnodes > 0; ++d) {
     F->level_start.push_back(node0);
@@ -798,6 +805,12 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     }
     if (lvl_pts) W.partial.reserve(8ull * gpd * nchunks);
     if (lvl_pyr) W.part_m2.reserve(8ull * rbd * nchunks);
+    if (wide) {
+      // every node's factor stays in device memory for the level
+      if (8ull * fd * nnodes > (32ull << 30))
+        fail(FMT_E_OOM, "a level of the large-basis fit needs more than 32 GiB of factors");
+      W.fac.reserve(8ull * fd * nnodes);
+    }
     if (F->refine > 0) {
       W.fac.reserve(8ull * fd * nnodes);
       W.part_b.reserve(8ull * rbd * nchunks);
@@ -858,7 +871,11 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
         ProfScope ps(KN_FSOLVE, nnodes, s);
         HIPCHK(launch_solve_ahead(F->p, a, W.part_m2.as<double>(), fac, s));
       }
-      if (n_ahead_probs < (uint32_t)K) {
+      if (wide) {
+        ProfScope ps(KN_SOLVE, nnodes, s);
+        HIPCHK(launch_wide_factor(F->p, a, W.partial.as<double>(), W.fac.as<double>(), s));
+        HIPCHK(launch_wide_solve(F->p, a, W.partial.as<double>(), W.fac.as<double>(), s));
+      } else if (n_ahead_probs < (uint32_t)K) {
         ProfScope ps(KN_SOLVE, nnodes, s);
         if (use_moments)
           HIPCHK(launch_solve_moments(F->p, a, W.partial.as<double>(), W.part_m2.as<double>(), W.pyr.as<double>(),
@@ -884,12 +901,15 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       {
         ProfScope ps(KN_RSWEEP, level_points, s);
         HIPCHK(launch_moments(F->p, 1, dtype, a, W.part_b.as<double>(), s));
-        // every node refined: sum the chunks in parallel first (the
-        // refinement solve otherwise sums its node's chunks itself)
-        if (multi && a.refine == 2) HIPCHK(launch_chunk_reduce(a, W.part_b.as<double>(), (uint32_t)rbd, s));
+        // every node refined, or the tiled solve (which reads the summed
+        // partial): sum the chunks in parallel first (the refinement solve
+        // otherwise sums its node's chunks itself)
+        if (multi && (a.refine == 2 || wide))
+          HIPCHK(launch_chunk_reduce(a, W.part_b.as<double>(), (uint32_t)rbd, s));
       }
       ProfScope ps(KN_RSOLVE, nnodes, s);
-      HIPCHK(launch_refine_solve(F->p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
+      if (wide) HIPCHK(launch_wide_refine_solve(F->p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
+      else HIPCHK(launch_refine_solve(F->p, a, W.part_b.as<double>(), W.fac.as<double>(), s));
     }
     {
       ProfScope ps(KN_RESID, level_points, s);
@@ -1736,6 +1756,7 @@ fmt_status fmt_refit(const fmt_tree* tree, const void* x, const void* y, const v
     ensure_tree_nodes(t);
     const ProblemInfo& P = t->forest->probs[t->problem];
     if (P.n == 0) fail(FMT_E_INVALID_ARG, "the tree holds no points (an imported tree)");
+    if (t->forest->p > 8) fail(FMT_E_INVALID_ARG, "the fixed-topology refit supports p <= 8");
     if (n != P.n) fail(FMT_E_INVALID_ARG, "n differs from the tree's point count");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));

@@ -179,7 +179,20 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
 // workgroup; a round's 32 rows take 22 KB of LDS at p = 6.
 // ---------------------------------------------------------------------------
 constexpr int EVAL_THREADS = 64;
-constexpr int EVAL_ROWS = 32;   // rows staged per round
+
+// Row staging of order P: lanes per row (each lane loads every G-th double
+// pair of the row) and rows per batch; small bases stage two batches of 16
+// rows per round (4 lanes a row), the large ones (p = 10..14, rows of up to
+// 5.4 KB) one batch of 8 rows (8 lanes a row), so a round stays within 48 KB
+// of LDS.
+template <int P>
+struct EvalStage {
+  static constexpr bool WIDE = P > 8;
+  static constexpr int G = WIDE ? 8 : 4;          // lanes per row
+  static constexpr int BATCH = 64 / G;            // rows per batch
+  static constexpr int NB = WIDE ? 1 : 2;         // batches per round
+  static constexpr int ROWS = BATCH * NB;         // rows per round
+};
 
 template <int P, typename TIN>
 __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double* __restrict__ cc,
@@ -194,6 +207,8 @@ __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double*
   // 16 lanes reading the same coefficient of 16 rows with 16-byte loads hit
   // 16 distinct groups of four banks
   constexpr int LS = 2 * UP + ((2 * UP) % 4 == 0 ? 2 : 0);
+  using ES = EvalStage<P>;
+  constexpr int EVAL_ROWS = ES::ROWS;
   static_assert(EVAL_THREADS == 64, "one wave per workgroup");
   __shared__ __attribute__((aligned(16))) double rows[EVAL_ROWS * LS];
   const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,28 +252,29 @@ __global__ void __launch_bounds__(EVAL_THREADS) k_eval(EvalTree t, const double*
     typedef const double __attribute__((address_space(4))) cdouble;
     val = poly_eval<P, double>((const cdouble*)(cc + (size_t)n0 * CS), u, v, ww);
   } else {
-    constexpr int KS = (UP + 3) / 4;   // loads per lane per batch of 16 rows
-    const int q4 = lane >> 2, part = lane & 3;
+    constexpr int G = ES::G, BATCH = ES::BATCH, NB = ES::NB;
+    constexpr int KS = (UP + G - 1) / G;   // loads per lane per batch
+    const int qg = lane / G, part = lane % G;
 #pragma unroll 1
     for (int r = 0; r < 64 / EVAL_ROWS; ++r) {
-      double2 vals[2][KS];
+      double2 vals[NB][KS];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        // the quad's query: lane EVAL_ROWS r + 16 b + q4, its row to LDS row 16 b + q4
-        const uint32_t nd = (uint32_t)__shfl((int)node, EVAL_ROWS * r + 16 * b + q4);
+      for (int b = 0; b < NB; ++b) {
+        // the group's query: lane EVAL_ROWS r + BATCH b + qg, its row to LDS row BATCH b + qg
+        const uint32_t nd = (uint32_t)__shfl((int)node, EVAL_ROWS * r + BATCH * b + qg);
         const double2* srow = reinterpret_cast<const double2*>(cc + (size_t)nd * CS);
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-          const int pr = 4 * k + part;
+          const int pr = G * k + part;
           vals[b][k] = pr < UP ? srow[pr] : make_double2(0.0, 0.0);
         }
       }
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        double2* drow = reinterpret_cast<double2*>(rows + (16 * b + q4) * LS);
+      for (int b = 0; b < NB; ++b) {
+        double2* drow = reinterpret_cast<double2*>(rows + (BATCH * b + qg) * LS);
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-          const int pr = 4 * k + part;
+          const int pr = G * k + part;
           if (pr < UP) drow[pr] = vals[b][k];
         }
       }
@@ -282,7 +298,7 @@ static hipError_t compose_impl(const NodeTable& nt, uint32_t first, uint32_t cou
 }
 
 hipError_t launch_compose(int p, const NodeTable& nt, uint32_t first, uint32_t count, double* cc, hipStream_t s) {
-  FMT_DISPATCH_P(p, compose_impl, nt, first, count, cc, s);
+  FMT_DISPATCH_P_ALL(p, compose_impl, nt, first, count, cc, s);
 }
 
 hipError_t launch_cell_table(const NodeTable& nt, uint32_t root, int T, const ProblemParams& prm, double* lvl,
@@ -311,7 +327,7 @@ static hipError_t eval_impl(int dtype, const EvalTree& t, const double* cc, cons
 hipError_t launch_eval(int p, int dtype, const EvalTree& t, const double* cc, const void* qx, const void* qy,
                        const void* qz, const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out,
                        hipStream_t s) {
-  FMT_DISPATCH_P(p, eval_impl, dtype, t, cc, qx, qy, qz, perm, skeys, nq, out, s);
+  FMT_DISPATCH_P_ALL(p, eval_impl, dtype, t, cc, qx, qy, qz, perm, skeys, nq, out, s);
 }
 
 }  // namespace fmt

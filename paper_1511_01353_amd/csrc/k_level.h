@@ -193,6 +193,27 @@ hipError_t launch_eval(int p, int dtype, const EvalTree& t, const double* cc, co
                        const void* qz, const uint32_t* perm, const uint32_t* skeys, uint32_t nq, double* out,
                        hipStream_t s);
 
+// Large bases (k_wide.hip): orders p = 10, 12, 14 (calL = 286, 455, 680),
+// whose normal equations do not fit a workgroup's LDS.  Per node of the level
+// a factor of wide_factor_doubles(p) doubles in device memory (fac + k *
+// that for level node k): the equilibrated matrix assembled from the node's
+// mode-0 partial (chunks summed beforehand) and factored by a blocked
+// Cholesky; then the solve writes F (with the condition estimate when
+// a.refine == 1, and the rank flags), and the refinement solve adds the
+// correction from the node's mode-1 partial (chunks summed beforehand).
+bool wide_order(int p);
+size_t wide_factor_doubles(int p);
+hipError_t launch_wide_factor(int p, const LevelArgs& a, const double* part_m, double* fac, hipStream_t s);
+hipError_t launch_wide_solve(int p, const LevelArgs& a, const double* part_m, const double* fac, hipStream_t s);
+hipError_t launch_wide_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac,
+                                    hipStream_t s);
+// The moment kernels (modes 0 and 1 only) of the large orders, each compiled
+// in a translation unit of its own (k_moments.hip built with
+// FMT_MOMENTS_WIDE_P defined); launch_moments dispatches to them.
+hipError_t launch_moments_p10(int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s);
+hipError_t launch_moments_p12(int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s);
+hipError_t launch_moments_p14(int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s);
+
 // Device helpers shared by the level kernels ---------------------------------
 
 // Node k of a level owning chunk g: the last k with chunk_off[k] <= g, so
@@ -268,7 +289,7 @@ __device__ __forceinline__ void load_point(const void* px, const void* py, const
 
 }  // namespace fmt
 
-// Instantiate F<P> for the runtime order p (0..FMT_MAX_P).
+// Instantiate F<P> for the runtime order p of the small bases (0..8).
 #define FMT_DISPATCH_P(p, F, ...)                  \
   switch (p) {                                      \
     case 0: return F<0>(__VA_ARGS__);               \
@@ -280,5 +301,25 @@ __device__ __forceinline__ void load_point(const void* px, const void* py, const
     case 6: return F<6>(__VA_ARGS__);               \
     case 7: return F<7>(__VA_ARGS__);               \
     case 8: return F<8>(__VA_ARGS__);               \
+    default: return hipErrorInvalidValue;           \
+  }
+
+// Instantiate F<P> for every supported order: the small bases 0..8 and the
+// large ones 10, 12, 14 (kernels whose work per point or node is a loop over
+// the basis, not a factorisation held in LDS).
+#define FMT_DISPATCH_P_ALL(p, F, ...)              \
+  switch (p) {                                      \
+    case 0: return F<0>(__VA_ARGS__);               \
+    case 1: return F<1>(__VA_ARGS__);               \
+    case 2: return F<2>(__VA_ARGS__);               \
+    case 3: return F<3>(__VA_ARGS__);               \
+    case 4: return F<4>(__VA_ARGS__);               \
+    case 5: return F<5>(__VA_ARGS__);               \
+    case 6: return F<6>(__VA_ARGS__);               \
+    case 7: return F<7>(__VA_ARGS__);               \
+    case 8: return F<8>(__VA_ARGS__);               \
+    case 10: return F<10>(__VA_ARGS__);             \
+    case 12: return F<12>(__VA_ARGS__);             \
+    case 14: return F<14>(__VA_ARGS__);             \
     default: return hipErrorInvalidValue;           \
   }

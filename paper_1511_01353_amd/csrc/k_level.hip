@@ -1265,7 +1265,7 @@ static hipError_t resid_impl(int dtype, const LevelArgs& a, double* part_ss, hip
   return hipGetLastError();
 }
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {
-  FMT_DISPATCH_P(p, resid_impl, dtype, a, part_ss, s);
+  FMT_DISPATCH_P_ALL(p, resid_impl, dtype, a, part_ss, s);
 }
 
 template <int P>
@@ -1288,7 +1288,7 @@ static hipError_t children_impl(const LevelArgs& a, const double* part_ss, uint3
 }
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
                            uint32_t* nact, hipStream_t s) {
-  FMT_DISPATCH_P(p, children_impl, a, part_ss, cbeg, ccnt, nact, s);
+  FMT_DISPATCH_P_ALL(p, children_impl, a, part_ss, cbeg, ccnt, nact, s);
 }
 
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
@@ -1325,7 +1325,7 @@ static hipError_t check_impl(const NodeTable& nt, uint32_t nnodes, uint32_t* sta
   return hipGetLastError();
 }
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s) {
-  FMT_DISPATCH_P(p, check_impl, nt, nnodes, status, s);
+  FMT_DISPATCH_P_ALL(p, check_impl, nt, nnodes, status, s);
 }
 
 }  // namespace fmt

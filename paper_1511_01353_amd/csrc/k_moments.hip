@@ -124,9 +124,11 @@ struct Plan {
   static constexpr MomentPlan<P, MODE> v{};
 };
 
+#ifndef FMT_MOMENTS_WIDE_P
 size_t moment_partial_doubles(int p) { return basis_size(2 * p) + basis_size(p) + 1; }
 size_t moment_refine_doubles(int p) { return basis_size(p); }
 size_t moment_base_doubles(int p) { return basis_size(2 * p); }
+#endif
 
 // Accumulate item I (compile-time) for one point: a run acc[s + c] += h w^c.
 template <int S, int NA, int P2, size_t... C>
@@ -392,19 +394,44 @@ static void launch_mode(int dtype, const LevelArgs& a, double* part, hipStream_t
 template <int P>
 static hipError_t moments_impl(int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s) {
   if (a.nchunks == 0) return hipSuccess;
-  switch (mode) {
-    case 0: launch_mode<P, 0>(dtype, a, part, s); break;
-    case 1: launch_mode<P, 1>(dtype, a, part, s); break;
-    case 2: launch_mode<P, 2>(dtype, a, part, s); break;
-    case 3: launch_mode<P, 3>(dtype, a, part, s); break;
-    case 4: launch_mode<P, 4>(dtype, a, part, s); break;
-    default: return hipErrorInvalidValue;
+  if constexpr (P > 8) {
+    // large bases: per-level moments (mode 0) and the refinement sweep (mode 1)
+    switch (mode) {
+      case 0: launch_mode<P, 0>(dtype, a, part, s); break;
+      case 1: launch_mode<P, 1>(dtype, a, part, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (mode) {
+      case 0: launch_mode<P, 0>(dtype, a, part, s); break;
+      case 1: launch_mode<P, 1>(dtype, a, part, s); break;
+      case 2: launch_mode<P, 2>(dtype, a, part, s); break;
+      case 3: launch_mode<P, 3>(dtype, a, part, s); break;
+      case 4: launch_mode<P, 4>(dtype, a, part, s); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
 
+#ifndef FMT_MOMENTS_WIDE_P
 hipError_t launch_moments(int p, int mode, int dtype, const LevelArgs& a, double* part, hipStream_t s) {
+  switch (p) {
+    case 10: return launch_moments_p10(mode, dtype, a, part, s);
+    case 12: return launch_moments_p12(mode, dtype, a, part, s);
+    case 14: return launch_moments_p14(mode, dtype, a, part, s);
+    default: break;
+  }
   FMT_DISPATCH_P(p, moments_impl, mode, dtype, a, part, s);
 }
+#else
+// this translation unit: the kernels of one large order only
+#define FMT_MOMENTS_CAT2(a, b) a##b
+#define FMT_MOMENTS_CAT(a, b) FMT_MOMENTS_CAT2(a, b)
+hipError_t FMT_MOMENTS_CAT(launch_moments_p, FMT_MOMENTS_WIDE_P)(int mode, int dtype, const LevelArgs& a,
+                                                                  double* part, hipStream_t s) {
+  return moments_impl<FMT_MOMENTS_WIDE_P>(mode, dtype, a, part, s);
+}
+#endif
 
 }  // namespace fmt

@@ -35,7 +35,7 @@ FMT_PATH_MIXED = 1
 FMT_GRAM_MOMENTS = 0
 FMT_GRAM_MFMA = 1
 FMT_GRAM_MOMENTS_LEVEL = 2
-FMT_MAX_P = 8
+FMT_MAX_P = 14
 FMT_MAX_DEPTH = 10
 FMT_MAX_LEVELS = FMT_MAX_DEPTH + 1
 FMT_REFIT_MAX_FIELDS = 4096

@@ -11,7 +11,9 @@ throughout: the errors of interest go well below float32 rounding.
   python -m paper_1511_01353_amd.scoping [--orders 4,8] [--taus 1e-6,1e-8,1e-10,1e-12]
                                           [--sizes 4,5,6,7] [--depth 10]
 
-Orders above FMT_MAX_P (8) are not supported by this implementation.
+The orders are 0..8, 10, 12 and 14 (the paper's experiments use 4, 8, 12;
+its unscoped single-node fits of Section 3 use 6, 10, 14, which is
+--depth 0 --taus 0).
 """
 import argparse
 import json
