@@ -80,7 +80,11 @@ def main(argv=None):
         for p in orders:
             pr = synthetic.scoping_problem(n, p, taus[0], args.seed + k, depth=args.depth)
             for tau in taus:
-                r = run_case(fmt, torch, pr, tau, args.depth)
+                try:
+                    r = run_case(fmt, torch, pr, tau, args.depth)
+                except fmt.FmtError as e:   # e.g. a level whose factors exceed the memory bound
+                    print(json.dumps({"p": p, "n": n, "tau": tau, "error": str(e)}), flush=True)
+                    continue
                 rows.append(r)
                 print(json.dumps(r), flush=True)
     best = min(rows, key=lambda r: r["E_rms"])
