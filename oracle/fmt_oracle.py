@@ -40,6 +40,16 @@ What is computed (all arithmetic IEEE float64; float32 inputs promoted exactly):
   existing tree, parents before children, each node fitting the residual its
   ancestors left; no octant test is taken, so the map f -> coefficients is
   linear.
+* Gaussian-RBF factorisation (Section 2, eq. fullyfactored): the kernel
+  phi(|x' - x|) = exp(-eps^2 |x' - x|^2) expanded in Taylor series and
+  truncated to the calL monomials of degree <= p on each side,
+  phi ~ Lambda(x) . E . T . E . Lambda(x')^T with E = diag(eps^|alpha|) and
+  T_ab = (-1)^|a| h_{a1+b1}(0) h_{a2+b2}(0) h_{a3+b3}(0), the h_n(0) being the
+  values at zero of the Hermite functions h_n(t) = exp(-t^2) H_n(t) that the
+  section defines (physicists' Hermite polynomials: H_n(0) = (-1)^(n/2)
+  n!/(n/2)! for even n, 0 for odd n).  The section's printed closed form
+  (-1)^(n/2) (n-1)!! is the probabilists' He_n(0), which expands
+  exp(-eps^2 |x' - x|^2 / 2) instead; both are available.
 * Evaluation (the practical form f'_q = Lambda'_q F_p of Section 2, summed over
   the tree as the residual decomposition implies): for a query, walk from the
   root down while the node holding the query's cell exists, adding each node's
@@ -58,6 +68,7 @@ __all__ = [
     "rank_stride", "basis_size", "exponents", "moments",
     "quantise", "morton", "node_frame", "mesh_to_moments",
     "Tree", "fit", "fit_fixed", "evaluate", "rms", "max_abs",
+    "hermite_at_zero", "rbf_T", "rbf_factored",
 ]
 
 EPS = np.finfo(np.float64).eps
@@ -362,6 +373,45 @@ def _prefix_cell(prefix: int, level: int) -> Tuple[int, int, int]:
         j = (j << 1) | ((t >> 1) & 1)
         k = (k << 1) | (t & 1)
     return i, j, k
+
+
+# ----------------------------------------------------------------------------
+# Gaussian-RBF factorisation (Section 2, eq. fullyfactored)
+# ----------------------------------------------------------------------------
+def hermite_at_zero(n: int, kind: str = "physicists") -> float:
+    """h_n(0): the Hermite function exp(-t^2) H_n(t) at t = 0 (physicists'),
+    or the probabilists' He_n(0) that the section prints."""
+    if n % 2:
+        return 0.0
+    sign = -1.0 if (n // 2) % 2 else 1.0
+    if kind == "physicists":
+        return sign * float(math.factorial(n) // math.factorial(n // 2))
+    if kind == "probabilists":
+        dfact = 1
+        for k in range(n - 1, 0, -2):
+            dfact *= k
+        return sign * float(dfact)
+    raise ValueError("kind must be 'physicists' or 'probabilists'")
+
+
+def rbf_T(p: int, kind: str = "physicists") -> np.ndarray:
+    """T_ab = (-1)^|a| h_{a1+b1}(0) h_{a2+b2}(0) h_{a3+b3}(0) over the graded basis."""
+    ex = exponents(p)
+    L = len(ex)
+    T = np.zeros((L, L))
+    for i, (a1, a2, a3) in enumerate(ex):
+        sg = -1.0 if (a1 + a2 + a3) % 2 else 1.0
+        for j, (b1, b2, b3) in enumerate(ex):
+            T[i, j] = sg * (hermite_at_zero(a1 + b1, kind) * hermite_at_zero(a2 + b2, kind)
+                            * hermite_at_zero(a3 + b3, kind))
+    return T
+
+
+def rbf_factored(x, y, z, xq, yq, zq, p: int, eps: float, kind: str = "physicists") -> np.ndarray:
+    """phi'_{q i} = Lambda(x_q) E T E Lambda(x_i)^T, shape (len(xq), len(x))."""
+    E = np.array([float(eps) ** (a + b + c) for (a, b, c) in exponents(p)])
+    C = E[:, None] * rbf_T(p, kind) * E[None, :]
+    return moments(xq, yq, zq, p) @ C @ moments(x, y, z, p).T
 
 
 def rms(a) -> float:

@@ -543,6 +543,64 @@ def test_fixed_topology_rejects_other_points():
 
 
 # ----------------------------------------------------------------------------
+# Gaussian-RBF factorisation (Section 2, eq. fullyfactored)
+# ----------------------------------------------------------------------------
+def pin_hermite_numbers():
+    # H_n(0) from the polynomials themselves: H_0 = 1, H_2 = 4t^2 - 2,
+    # H_4 = 16t^4 - 48t^2 + 12, H_6 = 64t^6 - 480t^4 + 720t^2 - 120 (textbook
+    # recurrence H_{n+1} = 2t H_n - 2n H_{n-1}); He likewise (He_{n+1} = t He_n - n He_{n-1})
+    H = {0: np.poly1d([1.0]), 1: np.poly1d([2.0, 0.0])}
+    He = {0: np.poly1d([1.0]), 1: np.poly1d([1.0, 0.0])}
+    t = np.poly1d([1.0, 0.0])
+    for n in range(1, 14):
+        H[n + 1] = 2 * t * H[n] - 2 * n * H[n - 1]
+        He[n + 1] = t * He[n] - n * He[n - 1]
+    for n in range(15):
+        assert oracle.hermite_at_zero(n) == H[n](0.0)
+        assert oracle.hermite_at_zero(n, "probabilists") == He[n](0.0)
+    assert [oracle.hermite_at_zero(n) for n in (0, 2, 4, 6)] == [1.0, -2.0, 12.0, -120.0]
+
+
+def pin_rbf_factored_converges_to_the_gaussian():
+    # the truncated factorisation against exp(-eps^2 |x - x'|^2) evaluated
+    # directly: the error falls with the order and reaches rounding level
+    rng = np.random.default_rng(71)
+    x, y, z = rng.uniform(-1, 1, (3, 40))
+    xq, yq, zq = rng.uniform(-1, 1, (3, 30))
+    d2 = (xq[:, None] - x[None, :]) ** 2 + (yq[:, None] - y[None, :]) ** 2 + (zq[:, None] - z[None, :]) ** 2
+    for kind, scale in (("physicists", 1.0), ("probabilists", 0.5)):
+        eps = 0.15
+        direct = np.exp(-scale * eps * eps * d2)
+        errs = [np.max(np.abs(oracle.rbf_factored(x, y, z, xq, yq, zq, p, eps, kind) - direct)) for p in (2, 6, 10, 14)]
+        assert errs[0] > errs[1] > errs[2], (kind, errs)
+        assert errs[3] < 1e-12, (kind, errs)
+
+
+def pin_rbf_T_structure():
+    T = oracle.rbf_T(6)
+    assert np.array_equal(T, T.T)              # symmetric: h_n(0) vanishes for odd n
+    assert T[0, 0] == 1.0
+    ex = oracle.exponents(6)
+    i = ex.index((2, 0, 0))
+    assert T[i, 0] == -2.0 and T[0, i] == -2.0   # H_2(0)
+    j = ex.index((1, 0, 0))
+    assert T[j, j] == -(-2.0)                    # (-1)^1 H_2(0) H_0 H_0
+    assert T[j, 0] == 0.0                        # H_1(0) = 0
+
+
+def test_hermite_numbers():
+    pin_hermite_numbers()
+
+
+def test_rbf_factored_converges_to_the_gaussian():
+    pin_rbf_factored_converges_to_the_gaussian()
+
+
+def test_rbf_T_structure():
+    pin_rbf_T_structure()
+
+
+# ----------------------------------------------------------------------------
 # mutation tests: a planted mistake in the oracle must fail a pin
 # ----------------------------------------------------------------------------
 def _mutant_moments_no_factorial(u, v, w, p):
@@ -580,6 +638,16 @@ def _mutant_drop_last_block(u, v, w, r, p, block=fo.QR_BLOCK_ROWS):
     return _orig_mtm(u[:keep], v[:keep], w[:keep], r[:keep], p, block)
 
 
+def _mutant_hermite_probabilists(n, kind="physicists"):
+    return _orig_hermite(n, "probabilists")
+
+
+def _mutant_rbf_T_no_sign(p, kind="physicists"):
+    ex = fo.exponents(p)
+    return np.abs(_orig_rbf_T(p, kind)) * np.array([[1.0 if (a + b + c) % 2 == 0 else 1.0 for _ in ex]
+                                                      for (a, b, c) in ex])
+
+
 def _mutant_fit_fixed_children_first(tree, x, y, z, f):
     rev = np.arange(tree.nodes)[::-1]
     t = fo.dataclasses.replace(tree, level=tree.level[rev], prefix=tree.prefix[rev], begin=tree.begin[rev],
@@ -591,6 +659,8 @@ def _mutant_fit_fixed_children_first(tree, x, y, z, f):
 _orig_frame = fo.node_frame
 _orig_mtm = fo.mesh_to_moments
 _orig_fit_fixed = fo.fit_fixed
+_orig_hermite = fo.hermite_at_zero
+_orig_rbf_T = fo.rbf_T
 
 MUTANTS = [
     ("moments", _mutant_moments_no_factorial),
@@ -601,12 +671,15 @@ MUTANTS = [
     ("residual_update", _mutant_residual_sign),
     ("mesh_to_moments", _mutant_drop_last_block),
     ("fit_fixed", _mutant_fit_fixed_children_first),
+    ("hermite_at_zero", _mutant_hermite_probabilists),
+    ("rbf_T", _mutant_rbf_T_no_sign),
 ]
 
 PINS = [pin_basis_sizes, pin_graded_order, pin_moments_exact, pin_morton_matches_geometric,
         pin_exact_rational_ls, pin_polynomial_reproduction, pin_resolution_of_identity,
         pin_projection_orthogonality, pin_monotone_residual, pin_mean_hierarchy,
-        pin_fixed_topology_reproduces_fit, pin_fixed_topology_polynomial, pin_fixed_topology_linear_and_orthogonal]
+        pin_fixed_topology_reproduces_fit, pin_fixed_topology_polynomial, pin_fixed_topology_linear_and_orthogonal,
+        pin_hermite_numbers, pin_rbf_factored_converges_to_the_gaussian, pin_rbf_T_structure]
 
 
 @pytest.mark.parametrize("name,mutant", MUTANTS, ids=[m[0] for m in MUTANTS])
