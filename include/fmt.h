@@ -204,6 +204,28 @@ fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const 
 fmt_status fmt_eval_noalloc(const fmt_tree* tree, const void* qx, const void* qy, const void* qz,
                             int64_t nq, int dtype, double* out, int sort_queries, void* stream);
 
+/*
+ * Gaussian-RBF factorisation (Section 2, eq. fullyfactored): the Gaussian
+ * kernel exp(-eps^2 |x_q - x_i|^2) expanded in Taylor series and truncated
+ * to the calL monomials of degree <= p on each side,
+ *   out[q n + i] = sum_{a,b} Lambda_a(x_q) eps^|a| T_ab eps^|b| Lambda_b(x_i),
+ *   T_ab = (-1)^|a| H_{a1+b1}(0) H_{a2+b2}(0) H_{a3+b3}(0),
+ * with Lambda_a(x) = x^a / a! in the points' own coordinates (no frame) and
+ * H_m(0) the physicists' Hermite numbers, the values at zero of the Hermite
+ * functions exp(-t^2) H_m(t) the section defines.  A check of the theory
+ * behind the method, off the fit / eval path.
+ *   p          : 0..14 (every order).
+ *   eps        : shape parameter, finite, >= 0.
+ *   x, y, z    : device arrays of n points (dtype); 0 <= n < 2^31.
+ *   xq, yq, zq : device arrays of nq query points (dtype); 0 <= nq < 2^22.
+ *   out        : device array of nq * n float64, row q for query q.
+ * Asynchronous on `stream` (scratch from the stream-ordered allocator).
+ * Errors: INVALID_ARG, OOM, DEVICE.
+ */
+fmt_status fmt_rbf_factored(int p, double eps, const void* x, const void* y, const void* z, int64_t n,
+                            const void* xq, const void* yq, const void* zq, int64_t nq, int dtype, double* out,
+                            void* stream);
+
 /* Wait for all work of the tree's forest and report device-side status
    (DOMAIN for points outside the box, NUMERIC for non-finite coefficients). */
 fmt_status fmt_tree_wait(const fmt_tree* tree);

@@ -58,10 +58,10 @@ const char* kKernelNames[] = {"keygen", "sort", "gather", "gram", "gram_reduce",
                               "refine_solve", "residual", "children", "emit", "eval_keys", "eval_sort", "eval", "compose",
                               "bmoments", "base_moments", "pyramid", "refit_gather", "refit_moments",
                               "refit_factor", "refit_bmoments", "refit_solve", "refit_residual", "factor_ahead",
-                              "solve_ahead", "regram"};
+                              "solve_ahead", "regram", "rbf_rows", "rbf_pairs"};
 enum { KN_KEYGEN, KN_SORT, KN_GATHER, KN_GRAM, KN_REDUCE, KN_SOLVE, KN_RSWEEP, KN_RSOLVE, KN_RESID, KN_CHILD,
        KN_EMIT, KN_EKEYS, KN_ESORT, KN_EVAL, KN_COMPOSE, KN_BMOM, KN_BASEM, KN_PYR, KN_XGATHER, KN_XMOM, KN_XFACTOR,
-       KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_UPFAC, KN_FSOLVE, KN_REGRAM, KN_COUNT };
+       KN_XBMOM, KN_XSOLVE, KN_XRESID, KN_UPFAC, KN_FSOLVE, KN_REGRAM, KN_RBF_ROWS, KN_RBF_PAIRS, KN_COUNT };
 static_assert(sizeof(kKernelNames) / sizeof(kKernelNames[0]) == KN_COUNT, "one name per kernel class");
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -1600,6 +1600,77 @@ fmt_status fmt_eval_noalloc(const fmt_tree* tree, const void* qx, const void* qy
   return guard([&] {
     void* base = noalloc_scratch();
     eval_tree(tree, qx, qy, qz, nq, dtype, out, sort_queries, (hipStream_t)stream, base);
+  });
+}
+
+fmt_status fmt_rbf_factored(int p, double eps, const void* x, const void* y, const void* z, int64_t n,
+                            const void* xq, const void* yq, const void* zq, int64_t nq, int dtype, double* out,
+                            void* stream) {
+  return guard([&] {
+    if (p < 0 || p > FMT_MAX_P) fail(FMT_E_INVALID_ARG, "p out of range 0..14");
+    if (!(eps >= 0.0) || std::isinf(eps)) fail(FMT_E_INVALID_ARG, "eps must be finite and >= 0");
+    if (dtype != FMT_F32 && dtype != FMT_F64) fail(FMT_E_INVALID_ARG, "dtype must be FMT_F32 or FMT_F64");
+    if (n < 0 || nq < 0 || n >= (1ll << 31) || nq >= (1ll << 22)) fail(FMT_E_INVALID_ARG, "n or nq out of range");
+    if (n == 0 || nq == 0) return;
+    if (!x || !y || !z || !xq || !yq || !zq || !out) fail(FMT_E_INVALID_ARG, "NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const int L = basis_size(p);
+    const uint32_t LS = (uint32_t)((L + 63) / 64 * 64);
+    // Hermite numbers H_m(0) of the physicists' polynomials, from their
+    // recurrence at t = 0: H_0 = 1, H_1 = 0, H_{m+1}(0) = -2 m H_{m-1}(0)
+    std::vector<double> h(2 * p + 1, 0.0);
+    h[0] = 1.0;
+    for (int m = 1; m + 1 <= 2 * p; ++m) h[m + 1] = -2.0 * m * h[m - 1];
+    // exponents in graded order, then C = E T E with
+    // T_ab = (-1)^|a| H_{a1+b1}(0) H_{a2+b2}(0) H_{a3+b3}(0), E = diag(eps^|a|)
+    std::vector<uint32_t> expo;
+    std::vector<int> ex[3];
+    for (int k = 0; k <= p; ++k)
+      for (int l = k; l >= 0; --l)
+        for (int m = k - l; m >= 0; --m) {
+          const int nn = k - l - m;
+          expo.push_back((uint32_t)l | ((uint32_t)m << 8) | ((uint32_t)nn << 16));
+          ex[0].push_back(l);
+          ex[1].push_back(m);
+          ex[2].push_back(nn);
+        }
+    std::vector<double> epow(2 * p + 1, 1.0);
+    for (int k = 1; k <= 2 * p; ++k) epow[k] = epow[k - 1] * eps;
+    const size_t c_bytes = 8ull * L * LS, e_bytes = 4ull * L;
+    const size_t b_bytes = 8ull * (size_t)n * LS;
+    std::vector<char> host(c_bytes + e_bytes, 0);
+    double* C = reinterpret_cast<double*>(host.data());
+    for (int a = 0; a < L; ++a) {
+      const int da = ex[0][a] + ex[1][a] + ex[2][a];
+      for (int b = 0; b < L; ++b) {
+        const int db = ex[0][b] + ex[1][b] + ex[2][b];
+        const double t = h[ex[0][a] + ex[0][b]] * h[ex[1][a] + ex[1][b]] * h[ex[2][a] + ex[2][b]];
+        C[(size_t)a * LS + b] = (da & 1 ? -t : t) * epow[da] * epow[db];
+      }
+    }
+    std::memcpy(host.data() + c_bytes, expo.data(), e_bytes);
+    // device layout: [C | exponents (padded to 256 bytes) | B]
+    const size_t e_pad = (e_bytes + 255) & ~(size_t)255;
+    char* base = nullptr;
+    HIPCHK(hipMallocAsync((void**)&base, c_bytes + e_pad + b_bytes, s));
+    double* dC = reinterpret_cast<double*>(base);
+    uint32_t* dE = reinterpret_cast<uint32_t*>(base + c_bytes);
+    double* dB = reinterpret_cast<double*>(base + c_bytes + e_pad);
+    hipError_t e = hipMemcpyAsync(base, host.data(), c_bytes + e_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host image goes out of scope
+    // B's padding columns are read (as zeros) by the second product
+    if (e == hipSuccess) e = hipMemsetAsync(dB, 0, b_bytes, s);
+    if (e == hipSuccess) {
+      ProfScope ps(KN_RBF_ROWS, (double)n, s);
+      e = launch_rbf_gemm(dtype, x, y, z, (uint32_t)n, dC, (uint32_t)L, LS, dE, L, p, dB, LS, s);
+    }
+    if (e == hipSuccess) {
+      ProfScope ps(KN_RBF_PAIRS, (double)n * (double)nq, s);
+      e = launch_rbf_gemm(dtype, xq, yq, zq, (uint32_t)nq, dB, (uint32_t)n, LS, dE, L, p, out, (uint64_t)n, s);
+    }
+    hipError_t e2 = hipFreeAsync(base, s);
+    hip_check(e, "rbf");
+    hip_check(e2, "hipFreeAsync");
   });
 }
 

@@ -207,6 +207,14 @@ hipError_t launch_wide_factor(int p, const LevelArgs& a, const double* part_m, d
 hipError_t launch_wide_solve(int p, const LevelArgs& a, const double* part_m, const double* fac, hipStream_t s);
 hipError_t launch_wide_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac,
                                     hipStream_t s);
+// Gaussian-RBF factorisation (k_rbf.hip): out[q * ostride + i] =
+// sum_{k < L} Lambda_k(x_q) R[i * LS + k] for q < nq (query points of dtype),
+// i < nr (rows R, LS doubles each, zero beyond L), on float64 MFMA; expo
+// holds the packed exponents (l | m << 8 | n << 16) of the L basis indices.
+// nq < 2^22.
+hipError_t launch_rbf_gemm(int dtype, const void* qx, const void* qy, const void* qz, uint32_t nq, const double* R,
+                           uint32_t nr, uint32_t LS, const uint32_t* expo, int L, int p, double* out,
+                           uint64_t ostride, hipStream_t s);
 // The moment kernels (modes 0 and 1 only) of the large orders, each compiled
 // in a translation unit of its own (k_moments.hip built with
 // FMT_MOMENTS_WIDE_P defined); launch_moments dispatches to them.

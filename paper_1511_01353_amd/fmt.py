@@ -45,6 +45,7 @@ EXPORTED = [
     "fmt_tree_get_info",
     "fmt_tree_export_nodes", "fmt_tree_export_points", "fmt_tree_import", "fmt_refit", "fmt_tree_destroy",
     "fmt_last_error", "fmt_version", "fmt_profile_enable", "fmt_profile_reset", "fmt_profile_read",
+    "fmt_rbf_factored",
 ]
 
 
@@ -93,6 +94,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fmt_eval.restype = c_int
     lib.fmt_eval_noalloc.argtypes = [T, c_void_p, c_void_p, c_void_p, c_int64, c_int, c_void_p, c_int, c_void_p]
     lib.fmt_eval_noalloc.restype = c_int
+    lib.fmt_rbf_factored.argtypes = [c_int, c_double, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                                     c_void_p, c_int64, c_int, c_void_p, c_void_p]
+    lib.fmt_rbf_factored.restype = c_int
     lib.fmt_tree_wait.argtypes = [T]
     lib.fmt_tree_wait.restype = c_int
     lib.fmt_tree_get_info.argtypes = [T, POINTER(fmt_tree_info)]
@@ -232,6 +236,25 @@ def fmt_eval_noalloc(tree: "Tree", qx, qy, qz, out, sort_queries: int = -1, stre
     dt = _dtype_code(qx)
     _check(load_library().fmt_eval_noalloc(tree.handle, _dptr(qx), _dptr(qy), _dptr(qz), nq, dt, _dptr(out),
                                            int(sort_queries), _stream(stream)))
+    return out
+
+
+def fmt_rbf_factored(p: int, eps: float, x, y, z, xq, yq, zq, out=None, stream=None):
+    """Truncated Gaussian-RBF factorisation between query points and points:
+    an (nq, n) float64 device tensor (out, if given, must be one)."""
+    import torch
+    n, nq = x.numel(), xq.numel()
+    if not (y.numel() == z.numel() == n and yq.numel() == zq.numel() == nq):
+        raise ValueError("coordinate arrays must have matching lengths")
+    dt = _dtype_code(x)
+    if not all(_dtype_code(t) == dt for t in (y, z, xq, yq, zq)):
+        raise ValueError("all coordinates must share one dtype")
+    if out is None:
+        out = torch.empty((nq, n), dtype=torch.float64, device=x.device)
+    if out.dtype != torch.float64 or out.numel() != nq * n:
+        raise ValueError("out must be a float64 tensor of nq * n entries")
+    _check(load_library().fmt_rbf_factored(int(p), float(eps), _dptr(x), _dptr(y), _dptr(z), n, _dptr(xq),
+                                           _dptr(yq), _dptr(zq), nq, dt, _dptr(out), _stream(stream)))
     return out
 
 
