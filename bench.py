@@ -355,6 +355,87 @@ def clustered_leg(fmt, steps: int, warmup: int):
             "oracle_threads": int(gold["threads"]) if gold is not None else None}
 
 
+def rbf_leg(fmt, steps: int):
+    """Gaussian-RBF factorisation check: 16384 query points against 16384
+    points in [-1, 1]^3 (float64), eps = 0.15, orders 6, 10 and 14; launch
+    times of the two MFMA products from HIP events; the largest deviation from
+    the directly evaluated Gaussian on a 256 x 256 corner of the block."""
+    import numpy as np
+    import torch
+    n = nq = 1 << 14
+    rng = np.random.default_rng(8000)
+    x = [torch.from_numpy(a).cuda() for a in rng.uniform(-1.0, 1.0, (3, n))]
+    q = [torch.from_numpy(a).cuda() for a in rng.uniform(-1.0, 1.0, (3, nq))]
+    out = torch.empty((nq, n), dtype=torch.float64, device="cuda")
+    eps = 0.15
+    res = {}
+    for p in (6, 10, 14):
+        L = basis_count(p)
+        fmt.fmt_rbf_factored(p, eps, *x, *q, out=out)
+        torch.cuda.synchronize()
+        fmt.fmt_profile_reset()
+        fmt.fmt_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fmt.fmt_rbf_factored(p, eps, *x, *q, out=out)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        fmt.fmt_profile_enable(False)
+        prof = fmt.fmt_profile_read()
+        pairs = prof.get("rbf_pairs", (0, 0.0, 0.0))
+        ms = pairs[1] / max(pairs[0], 1)
+        flops = 2.0 * n * nq * L
+        xs = [a[:256].cpu().numpy() for a in x]
+        qs = [a[:256].cpu().numpy() for a in q]
+        d2 = sum((qa[:, None] - xa[None, :]) ** 2 for qa, xa in zip(qs, xs))
+        dev = float(np.max(np.abs(out[:256, :256].cpu().numpy() - np.exp(-eps * eps * d2))))
+        res[f"p{p}"] = {"calL": L, "pairs_ms": ms, "wall_ms": 1e3 * wall,
+                        "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12,
+                                     "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                                     "frac": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"]},
+                        "max_dev_from_gaussian": dev}
+        _progress(f"rbf p={p}: {ms:.2f} ms, {res[f'p{p}']['roofline']['frac']:.3f} of the fp64 MFMA peak")
+    return {"workload": "Gaussian-RBF factorisation check: 16384 x 16384 float64 block, points and queries "
+                        "uniform in [-1,1]^3, eps 0.15, orders 6/10/14",
+            "work_per_unit": "2 calL flops per (query, point) pair", "paths": res}
+
+
+def wide_leg(fmt, steps: int):
+    """Large bases: the unscoped single-node fits of Section 3 (8^6 uniform
+    points of the Franke function, depth 0) at orders 10 and 14, and the
+    scoped order-12 fit of Section 4 at 8^7 points, tol 1e-10."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    res = {}
+    for name, n, p, tol, depth in (("unscoped_p10", 8 ** 6, 10, 0.0, 0), ("unscoped_p14", 8 ** 6, 14, 0.0, 0),
+                                   ("scoped_p12", 8 ** 7, 12, 1e-10, 10)):
+        pr = synthetic.scoping_problem(n, p, tol, 6300, depth=depth)
+        X = [dev(a) for a in (pr.x, pr.y, pr.z, pr.f)]
+        Q = [dev(a) for a in (pr.qx, pr.qy, pr.qz)]
+        o = fmt.fmt_default_opts(p=p, tol=tol, max_depth=depth)
+        fmt.fmt_fit(o, *X).close()
+        torch.cuda.synchronize()
+        ts = []
+        for k in range(steps):
+            t0 = time.perf_counter()
+            tr = fmt.fmt_fit(o, *X)
+            ts.append(time.perf_counter() - t0)
+            if k + 1 < steps:
+                tr.close()
+        got = tr.eval(*Q).cpu().numpy()
+        err = got - pr.qf_true
+        res[name] = {"n": n, "p": p, "calL": basis_count(p), "tol": tol, "nodes": int(tr.info().nodes),
+                     "fit_ms_p50": 1e3 * statistics.median(ts), "fit_pts_per_s": n / statistics.median(ts),
+                     "E_rms": float(np.sqrt(np.mean(err * err))), "E_inf": float(np.max(np.abs(err)))}
+        tr.close()
+        _progress(f"wide {name}: {res[name]['fit_ms_p50']:.1f} ms")
+    return {"workload": "large bases: unscoped 8^6-point Franke fits at p=10, 14; scoped 8^7-point fit at p=12, "
+                        "tol 1e-10 (float64 path)", "cases": res}
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -399,8 +480,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16,
                     help="points of the benchmark workload the one-thread oracle baseline fits")
-    ap.add_argument("--configs", type=str, default="3,4,5",
-                    help="other workloads to run after the headline: 3 batched, 4 served, 5 large clustered")
+    ap.add_argument("--configs", type=str, default="3,4,5,wide,rbf",
+                    help="other workloads to run after the headline: 3 batched, 4 served, 5 large clustered, "
+                         "wide (large bases), rbf (the Gaussian-RBF factorisation check)")
     ap.add_argument("--refit-fields", type=int, default=8,
                     help="value fields of the fixed-topology refit leg (0: skip it)")
     ap.add_argument("--refit-only", action="store_true",
@@ -533,6 +615,10 @@ def main():
         others["cfg4"] = served_leg()
     if "5" in want:
         others["cfg5"] = clustered_leg(fmt, 3, 1)
+    if "wide" in want:
+        others["large_bases"] = wide_leg(fmt, 3)
+    if "rbf" in want:
+        others["rbf_check"] = rbf_leg(fmt, 3)
 
     cpu = None
     if not args.no_cpu_baseline:
