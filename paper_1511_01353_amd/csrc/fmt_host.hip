@@ -12,6 +12,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fmt_common.h"
@@ -424,6 +425,22 @@ struct fmt_tree {
 namespace {
 
 const int kRefineMax = 8;
+
+// Streams on which the groups of one batched fit run concurrently: created
+// once per device (default priority, blocking like the caller's) and kept
+// until the process ends, with their workspaces.
+constexpr int kGroupStreams = 4;
+std::mutex g_group_mu;
+std::map<std::pair<int, int>, hipStream_t> g_group_streams;
+
+hipStream_t group_stream(int idx) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_group_mu);
+  hipStream_t& s = g_group_streams[{dev, idx}];
+  if (!s) HIPCHK(hipStreamCreate(&s));
+  return s;
+}
 
 int ceil_log2(int k) {
   int b = 0;
@@ -1378,20 +1395,63 @@ fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const v
       groups[std::make_tuple(opts[k].p, opts[k].path, opts[k].max_depth, opts[k].refine_steps, opts[k].tol,
                              opts[k].gram)]
           .push_back(k);
+    std::vector<const std::vector<int>*> glist;
+    for (auto& kv : groups) glist.push_back(&kv.second);
+    std::vector<std::shared_ptr<Forest>> forests(glist.size());
+    auto run_group = [&](size_t g, hipStream_t s) {
+      const std::vector<int>& ids = *glist[g];
+      std::vector<fmt_fit_opts> per;
+      std::vector<FitInput> in;
+      for (int k : ids) {
+        per.push_back(opts[k]);
+        in.push_back(FitInput{x[k], y[k], z[k], f[k], n[k]});
+      }
+      forests[g] = fit_group(per[0], per, in, dtype, s);
+    };
+    if (glist.size() == 1) {
+      run_group(0, (hipStream_t)stream);
+    } else {
+      // Groups (problems of different order, path, depth or tolerance) run
+      // concurrently: up to kGroupStreams host threads, each driving its
+      // groups' level loops on a stream of its own, so that their launches
+      // and level boundaries overlap on the device.  Those streams first
+      // wait for the caller's stream (the inputs); every group's fit ends
+      // with its stream drained, so the trees are complete on return.
+      const int nw = (int)std::min<size_t>(glist.size(), (size_t)kGroupStreams);
+      hipEvent_t ready = nullptr;
+      HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      hipError_t er = hipEventRecord(ready, (hipStream_t)stream);
+      std::vector<hipStream_t> ws(nw);
+      for (int w = 0; w < nw && er == hipSuccess; ++w) {
+        ws[w] = group_stream(w);
+        er = hipStreamWaitEvent(ws[w], ready, 0);
+      }
+      (void)hipEventDestroy(ready);
+      hip_check(er, "batch group streams");
+      int dev = 0;
+      HIPCHK(hipGetDevice(&dev));
+      std::vector<std::exception_ptr> errs(nw);
+      std::vector<std::thread> th;
+      for (int w = 0; w < nw; ++w)
+        th.emplace_back([&, w] {
+          try {
+            hip_check(hipSetDevice(dev), "hipSetDevice");   // a new thread starts on device 0
+            for (size_t g = (size_t)w; g < glist.size(); g += (size_t)nw) run_group(g, ws[w]);
+          } catch (...) {
+            errs[w] = std::current_exception();
+          }
+        });
+      for (auto& t : th) t.join();
+      for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+    }
     std::vector<fmt_tree*> made(count, nullptr);
     try {
-      for (auto& kv : groups) {
-        const std::vector<int>& ids = kv.second;
-        std::vector<fmt_fit_opts> per;
-        std::vector<FitInput> in;
-        for (int k : ids) {
-          per.push_back(opts[k]);
-          in.push_back(FitInput{x[k], y[k], z[k], f[k], n[k]});
-        }
-        auto F = fit_group(per[0], per, in, dtype, (hipStream_t)stream);
+      for (size_t g = 0; g < glist.size(); ++g) {
+        const std::vector<int>& ids = *glist[g];
         for (size_t j = 0; j < ids.size(); ++j) {
           fmt_tree* t = new fmt_tree();
-          t->forest = F;
+          t->forest = forests[g];
           t->problem = (int)j;
           made[ids[j]] = t;
         }
