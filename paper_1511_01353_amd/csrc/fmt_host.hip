@@ -189,6 +189,8 @@ struct Workspace {
   // px, py, pz, pf: key-ordered inputs (payload set A); px2 .. pf2: set B
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status;
+  // refinement corrections of a level's nodes (late refinement)
+  DevBuf delta;
   // float64 moment partials of the mixed path's re-solved nodes
   DevBuf part_rg;
   // a fit's small tables (parameters, pointers, pyramid table, level-0 chunk
@@ -223,24 +225,28 @@ struct Workspace {
   // Wait for the topology kernel's counters of sequence number seq: spin on
   // the host-visible word; every few thousand spins ask whether the stream
   // has drained (then the word must be there, else read the device copy).
-  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[4]) {
+  // out: next level's nodes, chunks, points, small nodes; this level's
+  // nodes flagged for refinement
+  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[5]) {
     for (uint64_t it = 1;; ++it) {
       if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) {
         out[0] = __atomic_load_n(level_flag + 0, __ATOMIC_RELAXED);
         out[1] = __atomic_load_n(level_flag + 1, __ATOMIC_RELAXED);
         out[2] = __atomic_load_n(level_flag + 2, __ATOMIC_RELAXED);
         out[3] = __atomic_load_n(level_flag + 4, __ATOMIC_RELAXED);
+        out[4] = __atomic_load_n(level_flag + 5, __ATOMIC_RELAXED);
         return;
       }
       if ((it & 4095) == 0) {
         const hipError_t e = hipStreamQuery(s);
         if (e == hipSuccess) {
           if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) continue;
-          HIPCHK(hipMemcpy(host_counters, counters_dev, 20, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(host_counters, counters_dev, 24, hipMemcpyDeviceToHost));
           out[0] = host_counters[0];
           out[1] = host_counters[1];
           out[2] = host_counters[2];
           out[3] = host_counters[4];
+          out[4] = host_counters[5];
           return;
         }
         if (e != hipErrorNotReady) hip_check(e, "level wait");
@@ -914,7 +920,36 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
         HIPCHK(launch_solve_moments(F->p, r, W.part_rg.as<double>(), nullptr, nullptr, fac, s));
       }
     }
-    for (int it = 0; it < F->refine; ++it) {
+    // The float64 small-basis path refines only the nodes its condition
+    // estimate flags, usually none: the refinement then runs after the
+    // residual update and the level's topology pass, which reports how many
+    // nodes are flagged, and only if there are any (late refinement: sweep
+    // of the updated residual, correction delta, r -= Lambda delta on the
+    // flagged nodes, topology again).  The mixed path (every node) and the
+    // large bases refine before the residual update.
+    const bool late_refine = a.refine == 1 && !wide;
+    auto refine_late = [&](void) {
+      W.delta.reserve(8ull * L * nnodes);
+      LevelArgs r = a;
+      r.sweep_current = 1;
+      r.delta = W.delta.as<double>();
+      for (int it = 0; it < F->refine; ++it) {
+        {
+          ProfScope ps(KN_RSWEEP, level_points, s);
+          HIPCHK(launch_moments(F->p, 1, dtype, r, W.part_b.as<double>(), s));
+        }
+        {
+          ProfScope ps(KN_RSOLVE, nnodes, s);
+          HIPCHK(launch_refine_solve(F->p, r, W.part_b.as<double>(), W.fac.as<double>(), s));
+        }
+        ProfScope ps(KN_RESID, level_points, s);
+        LevelArgs c = r;
+        c.only_flag = FLAG_REFINE;
+        HIPCHK(launch_residual(F->p, dtype, c, W.part_ss.as<double>(), s));
+        if (multi && d < F->D) HIPCHK(launch_chunk_reduce(c, W.part_ss.as<double>(), 16, s));
+      }
+    };
+    for (int it = 0; it < (late_refine ? 0 : F->refine); ++it) {
       {
         ProfScope ps(KN_RSWEEP, level_points, s);
         HIPCHK(launch_moments(F->p, 1, dtype, a, W.part_b.as<double>(), s));
@@ -935,24 +970,34 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     }
     F->level_points.push_back(level_points);
     if (d == F->D) {
+      if (late_refine && F->refine > 0) refine_late();   // no topology pass to report the flagged count
       node0 += nnodes;
       break;
     }
-    {
-      ProfScope ps(KN_CHILD, nnodes, s);
-      HIPCHK(launch_children(F->p, a, W.part_ss.as<double>(), W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(),
-                             W.nact.as<uint32_t>(), s));
-    }
     const uint32_t next0 = node0 + nnodes;
-    const uint32_t seq = ++W.level_seq;
-    {
-      ProfScope ps(KN_EMIT, nnodes, s);
-      HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
-                         next_off->as<uint32_t>(), W.counters.as<uint32_t>(), W.level_flag_dev, seq, s));
+    uint32_t cnt[5];
+    auto topology = [&](void) {
+      {
+        ProfScope ps(KN_CHILD, nnodes, s);
+        HIPCHK(launch_children(F->p, a, W.part_ss.as<double>(), W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(),
+                               W.nact.as<uint32_t>(), s));
+      }
+      const uint32_t seq = ++W.level_seq;
+      {
+        ProfScope ps(KN_EMIT, nnodes, s);
+        HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
+                           next_off->as<uint32_t>(), W.counters.as<uint32_t>(), W.level_flag_dev, seq, s));
+      }
+      W.counters_dev = W.counters.p;
+      W.wait_level(seq, s, cnt);
+    };
+    topology();
+    if (late_refine && F->refine > 0 && cnt[4] > 0) {
+      // flagged nodes: refine them and take the topology of the corrected
+      // residual
+      refine_late();
+      topology();
     }
-    uint32_t cnt[4];
-    W.counters_dev = W.counters.p;
-    W.wait_level(seq, s, cnt);
     node0 = next0;
     nnodes = cnt[0];
     nchunks = cnt[1];

@@ -47,9 +47,17 @@ struct LevelArgs {
   // or that deflate a pivot, and leaves their coefficients to the float64
   // re-solve
   uint32_t regram = 0;
-  // nonzero: k_moments (mode 0), k_chunk_reduce and k_solve_m take only the
-  // nodes whose flags hold one of these bits (the float64 re-solve)
+  // nonzero: k_moments (mode 0), k_chunk_reduce, k_solve_m and k_residual
+  // take only the nodes whose flags hold one of these bits (the float64
+  // re-solve; the refinement's correction pass)
   uint32_t only_flag = 0;
+  // refinement after the residual update: the sweep (mode 1) takes the
+  // residual as it stands (r already holds r - Lambda F) instead of
+  // subtracting Lambda F itself, and the refinement solve also writes its
+  // correction delta (calL per level node, at delta + k calL) so that a
+  // residual pass can subtract Lambda delta
+  uint32_t sweep_current = 0;
+  double* delta = nullptr;
 };
 
 // Nodes with fewer points than this take the r-weighted moments in mode 4
@@ -167,7 +175,8 @@ hipError_t launch_residual_fields(int p, int dtype, const LevelArgs& a, hipStrea
 hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uint32_t* cbeg, uint32_t* ccnt,
                            uint32_t* nact, hipStream_t s);
 // counters[0..2] = next level's nodes, chunks, points, counters[4] = its
-// nodes with fewer than SMALL_NODE points; with hostc (device view of
+// nodes with fewer than SMALL_NODE points, counters[5] = this level's nodes
+// flagged for refinement (FLAG_REFINE); with hostc (device view of
 // host-visible memory) they are also written there (same positions), and
 // the sequence number at hostc[3] last (system-scope release).
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,

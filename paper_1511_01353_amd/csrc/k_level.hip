@@ -749,8 +749,10 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   double* F = a.nt.coef + (size_t)blockIdx.y * a.cstride + (size_t)node * L;
   bool bad = false;
   for (int i = tid; i < L; i += 256) {
-    const double c = F[i] + sc[i] * z[i];
+    const double dl = sc[i] * z[i];
+    const double c = F[i] + dl;
     F[i] = c;
+    if (a.delta) a.delta[(size_t)k * L + i] = dl;
     bad |= !__builtin_isfinite(c);
   }
   mark_nonfinite(bad, a.nt.flags + node, a.status);
@@ -818,6 +820,7 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
   const uint32_t g = blockIdx.x;
   const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
   const uint32_t node = a.node0 + k;
+  if (a.only_flag && !(a.nt.flags[node] & a.only_flag)) return;   // whole workgroup: not this pass's node
   const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
   const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
   const uint32_t end = min(nb + nc, start + (uint32_t)CHUNK);
@@ -825,7 +828,10 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
   const double cx = geo[0], cy = geo[1], cz = geo[2], sx = geo[3], sy = geo[4], sz = geo[5];
   const uint32_t fj = blockIdx.y;   // field of a multi-field launch
   double* rr = a.r + (size_t)fj * a.rstride;
-  for (int i = tid; i < L; i += 256) Fs[i] = a.nt.coef[(size_t)fj * a.cstride + (size_t)node * L + i];
+  // the polynomial to subtract: the node's coefficients, or (correction
+  // pass) its refinement's delta
+  const double* Fsrc = a.delta ? a.delta + (size_t)k * L : a.nt.coef + (size_t)fj * a.cstride + (size_t)node * L;
+  for (int i = tid; i < L; i += 256) Fs[i] = Fsrc[i];
   __syncthreads();
   const bool stats = a.level < a.D;
   const int shift = stats ? 3 * (a.D - a.level - 1) : 0;
@@ -1088,9 +1094,13 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
   const uint32_t m = a.nnodes;
   const uint32_t seg = (m + 1023u) / 1024u;
   const uint32_t b = min(m, tid * seg), e = min(m, b + seg);
-  uint32_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += nact[i];
-  uint32_t total;
+  uint32_t sum = 0, flagged = 0;
+  for (uint32_t i = b; i < e; ++i) {
+    sum += nact[i];
+    flagged += (a.nt.flags[a.node0 + i] & FLAG_REFINE) ? 1u : 0u;
+  }
+  uint32_t total, level_flagged;
+  (void)scan_1024(flagged, wsum, level_flagged);
   // each node's first child index (exclusive prefix of the active counts),
   // in place of its count
   uint32_t run = scan_1024(sum, wsum, total);
@@ -1151,6 +1161,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     counters[1] = nchunks_next;
     counters[2] = next_points;
     counters[4] = next_small;
+    counters[5] = level_flagged;
     if (hostc) {
       // the same counters into host-visible (fine-grained) memory, then the
       // sequence number with a system-scope release: the host waits on it
@@ -1158,6 +1169,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
       hostc[1] = nchunks_next;
       hostc[2] = next_points;
       hostc[4] = next_small;
+      hostc[5] = level_flagged;
       __hip_atomic_store(hostc + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }

@@ -325,7 +325,13 @@ k_moments(LevelArgs a, double* __restrict__ part) {
         v[q] = ((double)vy[q] - cy) * sy;
         w[q] = ((double)vz[q] - cz) * sz;
       }
-      poly_eval_multi<P, NPT>(F, u, v, w, val);
+      if (a.sweep_current) {
+        // the residual update already subtracted Lambda F
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) val[q] = 0.0;
+      } else {
+        poly_eval_multi<P, NPT>(F, u, v, w, val);
+      }
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
         const uint32_t i = i0 + q * NT;

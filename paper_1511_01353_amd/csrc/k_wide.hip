@@ -414,8 +414,10 @@ __global__ void __launch_bounds__(256) k_wide_refine_solve(LevelArgs a, const do
   double* F = a.nt.coef + (size_t)node * L;
   bool bad = false;
   for (int i = tid; i < L; i += 256) {
-    const double c = F[i] + fo[wscale(ws) + i] * y[0][i];
+    const double dl = fo[wscale(ws) + i] * y[0][i];
+    const double c = F[i] + dl;
     F[i] = c;
+    if (a.delta) a.delta[(size_t)k * L + i] = dl;
     bad |= !__builtin_isfinite(c);
   }
   flag_nonfinite(bad, a.nt.flags + node, a.status);
