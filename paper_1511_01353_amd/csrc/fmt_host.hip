@@ -1720,7 +1720,7 @@ fmt_status fmt_rbf_factored(int p, double eps, const void* x, const void* y, con
     if (!x || !y || !z || !xq || !yq || !zq || !out) fail(FMT_E_INVALID_ARG, "NULL pointer");
     hipStream_t s = (hipStream_t)stream;
     const int L = basis_size(p);
-    const uint32_t LS = (uint32_t)((L + 63) / 64 * 64);
+    const uint32_t LS = (uint32_t)((L + 31) / 32 * 32);
     // Hermite numbers H_m(0) of the physicists' polynomials, from their
     // recurrence at t = 0: H_0 = 1, H_1 = 0, H_{m+1}(0) = -2 m H_{m-1}(0)
     std::vector<double> h(2 * p + 1, 0.0);
@@ -1742,7 +1742,7 @@ fmt_status fmt_rbf_factored(int p, double eps, const void* x, const void* y, con
     std::vector<double> epow(2 * p + 1, 1.0);
     for (int k = 1; k <= 2 * p; ++k) epow[k] = epow[k - 1] * eps;
     const size_t c_bytes = 8ull * L * LS, e_bytes = 4ull * L;
-    const size_t b_bytes = 8ull * (size_t)n * LS;
+    const size_t b_bytes = 8ull * (size_t)n * LS, q_bytes = 8ull * (size_t)nq * LS;
     std::vector<char> host(c_bytes + e_bytes, 0);
     double* C = reinterpret_cast<double*>(host.data());
     for (int a = 0; a < L; ++a) {
@@ -1754,24 +1754,29 @@ fmt_status fmt_rbf_factored(int p, double eps, const void* x, const void* y, con
       }
     }
     std::memcpy(host.data() + c_bytes, expo.data(), e_bytes);
-    // device layout: [C | exponents (padded to 256 bytes) | B]
+    // device layout: [C | exponents (padded to 256 bytes) | B | basis of the
+    // points | basis of the queries]
     const size_t e_pad = (e_bytes + 255) & ~(size_t)255;
     char* base = nullptr;
-    HIPCHK(hipMallocAsync((void**)&base, c_bytes + e_pad + b_bytes, s));
+    HIPCHK(hipMallocAsync((void**)&base, c_bytes + e_pad + 2 * b_bytes + q_bytes, s));
     double* dC = reinterpret_cast<double*>(base);
     uint32_t* dE = reinterpret_cast<uint32_t*>(base + c_bytes);
     double* dB = reinterpret_cast<double*>(base + c_bytes + e_pad);
+    double* dAx = reinterpret_cast<double*>(base + c_bytes + e_pad + b_bytes);
+    double* dAq = reinterpret_cast<double*>(base + c_bytes + e_pad + 2 * b_bytes);
     hipError_t e = hipMemcpyAsync(base, host.data(), c_bytes + e_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host image goes out of scope
     // B's padding columns are read (as zeros) by the second product
     if (e == hipSuccess) e = hipMemsetAsync(dB, 0, b_bytes, s);
     if (e == hipSuccess) {
       ProfScope ps(KN_RBF_ROWS, (double)n, s);
-      e = launch_rbf_gemm(dtype, x, y, z, (uint32_t)n, dC, (uint32_t)L, LS, dE, L, p, dB, LS, s);
+      e = launch_rbf_basis(dtype, x, y, z, (uint32_t)n, dE, L, LS, dAx, s);
+      if (e == hipSuccess) e = launch_rbf_basis(dtype, xq, yq, zq, (uint32_t)nq, dE, L, LS, dAq, s);
+      if (e == hipSuccess) e = launch_rbf_gemm(dAx, (uint32_t)n, dC, (uint32_t)L, LS, dB, LS, s);
     }
     if (e == hipSuccess) {
       ProfScope ps(KN_RBF_PAIRS, (double)n * (double)nq, s);
-      e = launch_rbf_gemm(dtype, xq, yq, zq, (uint32_t)nq, dB, (uint32_t)n, LS, dE, L, p, out, (uint64_t)n, s);
+      e = launch_rbf_gemm(dAq, (uint32_t)nq, dB, (uint32_t)n, LS, out, (uint64_t)n, s);
     }
     hipError_t e2 = hipFreeAsync(base, s);
     hip_check(e, "rbf");

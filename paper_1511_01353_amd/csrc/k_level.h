@@ -216,13 +216,15 @@ hipError_t launch_wide_factor(int p, const LevelArgs& a, const double* part_m, d
 hipError_t launch_wide_solve(int p, const LevelArgs& a, const double* part_m, const double* fac, hipStream_t s);
 hipError_t launch_wide_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac,
                                     hipStream_t s);
-// Gaussian-RBF factorisation (k_rbf.hip): out[q * ostride + i] =
-// sum_{k < L} Lambda_k(x_q) R[i * LS + k] for q < nq (query points of dtype),
-// i < nr (rows R, LS doubles each, zero beyond L), on float64 MFMA; expo
-// holds the packed exponents (l | m << 8 | n << 16) of the L basis indices.
-// nq < 2^22.
-hipError_t launch_rbf_gemm(int dtype, const void* qx, const void* qy, const void* qz, uint32_t nq, const double* R,
-                           uint32_t nr, uint32_t LS, const uint32_t* expo, int L, int p, double* out,
+// Gaussian-RBF factorisation (k_rbf.hip).  Basis values of n points of
+// dtype, row-major with stride LS (a multiple of 32): A[j LS + k] =
+// Lambda_k(x_j) for k < L, zero beyond; expo holds the packed exponents
+// (l | m << 8 | n << 16) of the L basis indices.
+hipError_t launch_rbf_basis(int dtype, const void* x, const void* y, const void* z, uint32_t n, const uint32_t* expo,
+                            int L, uint32_t LS, double* A, hipStream_t s);
+// out[q * ostride + i] = sum_{k < LS} A[q LS + k] R[i LS + k] for q < nq
+// (< 2^23), i < nr, on float64 MFMA.
+hipError_t launch_rbf_gemm(const double* A, uint32_t nq, const double* R, uint32_t nr, uint32_t LS, double* out,
                            uint64_t ostride, hipStream_t s);
 // The moment kernels (modes 0 and 1 only) of the large orders, each compiled
 // in a translation unit of its own (k_moments.hip built with

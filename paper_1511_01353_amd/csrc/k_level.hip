@@ -810,12 +810,24 @@ __global__ void __launch_bounds__(256) k_factor_solve(LevelArgs a, const double*
 // reduced in a fixed order so that results do not depend on scheduling.
 // part_ss holds 16 doubles per chunk: 8 sums of r^2, then 8 counts (exact).
 // ---------------------------------------------------------------------------
+// Threads of a residual workgroup (one chunk of up to CHUNK points): 1024
+// up to p = 3 (sixteen waves in flight per chunk hide the load latency of
+// the few chunks of the top levels; the polynomial fits the registers of
+// four waves per SIMD), 256 above (more threads per workgroup would make the
+// compiler spill the polynomial's coefficients).
+template <int P>
+struct ResidualShape {
+  static constexpr int THREADS = P <= 3 ? 1024 : 256;
+  static constexpr int WAVES = THREADS / 64;
+};
+
 template <int P, typename TIN>
-__global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restrict__ part_ss) {
+__global__ void __launch_bounds__(ResidualShape<P>::THREADS) k_residual(LevelArgs a, double* __restrict__ part_ss) {
   constexpr int L = basis_size(P);
+  constexpr int NT = ResidualShape<P>::THREADS, NW = ResidualShape<P>::WAVES;
   __shared__ double Fs[L];
-  __shared__ double red[4][8];
-  __shared__ uint32_t redc[4][8];
+  __shared__ double red[NW][8];
+  __shared__ uint32_t redc[NW][8];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const uint32_t g = blockIdx.x;
   const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
@@ -831,7 +843,7 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
   // the polynomial to subtract: the node's coefficients, or (correction
   // pass) its refinement's delta
   const double* Fsrc = a.delta ? a.delta + (size_t)k * L : a.nt.coef + (size_t)fj * a.cstride + (size_t)node * L;
-  for (int i = tid; i < L; i += 256) Fs[i] = Fsrc[i];
+  for (int i = tid; i < L; i += NT) Fs[i] = Fsrc[i];
   __syncthreads();
   const bool stats = a.level < a.D;
   const int shift = stats ? 3 * (a.D - a.level - 1) : 0;
@@ -865,15 +877,15 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
       nr = rr[i0];
       nk = a.skey[i0];
     }
-    for (uint32_t i = start + tid; i < end; i += 256) {
+    for (uint32_t i = start + tid; i < end; i += NT) {
       const double x = (double)nx, y = (double)ny, z = (double)nz, rold = nr;
       const uint32_t key = nk;
-      if (i + 256 < end) {
-        nx = ((const TIN*)a.px)[i + 256];
-        ny = ((const TIN*)a.py)[i + 256];
-        nz = ((const TIN*)a.pz)[i + 256];
-        nr = rr[i + 256];
-        nk = a.skey[i + 256];
+      if (i + NT < end) {
+        nx = ((const TIN*)a.px)[i + NT];
+        ny = ((const TIN*)a.py)[i + NT];
+        nz = ((const TIN*)a.pz)[i + NT];
+        nr = rr[i + NT];
+        nk = a.skey[i + NT];
       }
       const double val = poly_eval<P, double>(Fs, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
       const double rn = rold - val;
@@ -881,7 +893,7 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
       tally(rn, key);
     }
   } else {
-    for (uint32_t i = start + tid; i < end; i += 256) {
+    for (uint32_t i = start + tid; i < end; i += NT) {
       double x, y, z;
       load_point<TIN>(a.px, a.py, a.pz, i, x, y, z);
       const double val = poly_eval<P, double>(Fs, (x - cx) * sx, (y - cy) * sy, (z - cz) * sz);
@@ -909,10 +921,18 @@ __global__ void __launch_bounds__(256) k_residual(LevelArgs a, double* __restric
   }
   __syncthreads();
   part_ss += (size_t)fj * a.nchunks * 16;
-  if (tid < 8) part_ss[(size_t)g * 16 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-  else if (tid < 16)
-    part_ss[(size_t)g * 16 + tid] =
-        (double)(redc[0][tid - 8] + redc[1][tid - 8] + redc[2][tid - 8] + redc[3][tid - 8]);
+  // the waves in order (a fixed summation order)
+  if (tid < 8) {
+    double t = red[0][tid];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) t += red[q][tid];
+    part_ss[(size_t)g * 16 + tid] = t;
+  } else if (tid < 16) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) c += redc[q][tid - 8];
+    part_ss[(size_t)g * 16 + tid] = (double)c;
+  }
 }
 
 // Exclusive prefix sum of one value per thread over a 1024-thread workgroup:
@@ -1272,8 +1292,9 @@ template <int P>
 static hipError_t resid_impl(int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {
   if (a.nchunks == 0) return hipSuccess;
   const dim3 grid(a.nchunks, field_rows(a));
-  if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float>), grid, dim3(256), 0, s, a, part_ss);
-  else hipLaunchKernelGGL((k_residual<P, double>), grid, dim3(256), 0, s, a, part_ss);
+  const dim3 block(ResidualShape<P>::THREADS);
+  if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float>), grid, block, 0, s, a, part_ss);
+  else hipLaunchKernelGGL((k_residual<P, double>), grid, block, 0, s, a, part_ss);
   return hipGetLastError();
 }
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {

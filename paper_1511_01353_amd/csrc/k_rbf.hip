@@ -4,112 +4,134 @@
 // Taylor series and truncated to the calL monomials of degree <= p on each
 // side, is a product of three dense factors:
 //   phi'_{q i} = Lambda(x_q) . C . Lambda(x_i)^T,  C = E T E,
-// with E = diag(eps^|alpha|) and T the matrix of Hermite numbers.  Both
-// products are dense contractions over the basis, so they run on float64
-// MFMA: first B = Lambda(X) C (one row of calL per point), then
-// phi' = Lambda(X_q) B^T, an nq x n block written row by row.  One kernel
-// does either product: out[q][i] = sum_k Lambda_k(x_q) R[i][k] for the rows R
-// (C's rows, or B's).
+// with E = diag(eps^|alpha|) and T the matrix of Hermite numbers.  The basis
+// values of both point sets are formed once (k_rbf_basis), then both
+// products are dense contractions over the basis on float64 MFMA: first
+// B = Lambda(X) C (one row of calL per point), then phi' = Lambda(X_q) B^T,
+// an nq x n block written row by row.  One kernel does either product:
+// out[q][i] = sum_k A[q][k] R[i][k] for row-major A and R.
 #include "k_level.h"
 
 namespace fmt {
 
 typedef double rbf_d4 __attribute__((ext_vector_type(4)));
 
-constexpr int RBF_TILE = 64;   // output tile edge (queries and rows)
-constexpr int RBF_K = 64;      // basis entries staged per round
+constexpr int RBF_TM = 128;    // output tile edge (rows of A and of R)
+constexpr int RBF_K = 32;      // basis entries per staged round
 constexpr int RBF_LD = RBF_K + 1;
+constexpr int RBF_LOADS = RBF_TM * RBF_K / 256;   // doubles of each operand a thread stages per round
 
-// out[q * ostride + i] = sum_{k < L} Lambda_k(x_q) R[i * LS + k] for q < nq,
-// i < nr.  Workgroup: a 64 x 64 tile of (q, i); its four waves take 32 x 32
-// quadrants as 2 x 2 blocks of 16 x 16 on MFMA (float64, k = 4 per step).
-// Per round the 64 queries' basis values for 64 entries of k (from their
-// scaled powers t^k / k!, held in LDS) and the 64 rows' matching entries are
-// staged in LDS.  expo: packed exponents l | m << 8 | n << 16 of each basis
-// index (graded order).  R must hold finite values (zeros) in its padding
-// columns L .. LS - 1.
+// Basis values, row-major with stride LS: A[j][k] = Lambda_k(x_j) for k < L,
+// 0 for L <= k < LS.  One thread per entry.
 template <typename TIN>
-__global__ void __launch_bounds__(256) k_rbf_gemm(const TIN* __restrict__ qx, const TIN* __restrict__ qy,
-                                                  const TIN* __restrict__ qz, uint32_t nq,
-                                                  const double* __restrict__ R, uint32_t nr, uint32_t LS,
-                                                  const uint32_t* __restrict__ expo, int L, int p,
-                                                  double* __restrict__ out, uint64_t ostride) {
-  __shared__ double pw[RBF_TILE][3][16];
-  __shared__ double lq[RBF_TILE][RBF_LD];
-  __shared__ double rt[RBF_TILE][RBF_LD];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const uint32_t i0 = blockIdx.x * RBF_TILE, q0 = blockIdx.y * RBF_TILE;
-  // scaled powers of the tile's queries: pw[r][axis][k] = t^k / k!
-  for (int e = tid; e < RBF_TILE * 3; e += 256) {
-    const int r = e / 3, ax = e % 3;
-    const uint32_t q = min(q0 + (uint32_t)r, nq - 1);
-    const double t = (double)(ax == 0 ? qx[q] : (ax == 1 ? qy[q] : qz[q]));
-    double v = 1.0;
-    pw[r][ax][0] = 1.0;
-    for (int k = 1; k <= p; ++k) {
-      v = v * t / (double)k;
-      pw[r][ax][k] = v;
-    }
+__global__ void __launch_bounds__(256) k_rbf_basis(const TIN* __restrict__ x, const TIN* __restrict__ y,
+                                                   const TIN* __restrict__ z, uint32_t n,
+                                                   const uint32_t* __restrict__ expo, int L, uint32_t LS,
+                                                   double* __restrict__ A) {
+  const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (uint64_t)n * LS) return;
+  const uint32_t j = (uint32_t)(e / LS), k = (uint32_t)(e % LS);
+  double v = 0.0;
+  if (k < (uint32_t)L) {
+    const uint32_t ex = expo[k];
+    const int l = (int)(ex & 255u), m = (int)((ex >> 8) & 255u), nn = (int)(ex >> 16);
+    const double t[3] = {(double)x[j], (double)y[j], (double)z[j]};
+    const int pw[3] = {l, m, nn};
+    v = 1.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+      for (int a = 1; a <= pw[ax]; ++a) v = v * t[ax] / (double)a;   // t^a / a!, as the basis defines it
   }
-  const int qr = w >> 1, qc = w & 1;   // this wave's quadrant (query half, row half)
-  rbf_d4 acc[2][2];
+  A[e] = v;
+}
+
+// out[q * ostride + i] = sum_{k < LS} A[q * LS + k] R[i * LS + k] for
+// q < nq, i < nr (A and R zero beyond the basis).  Workgroup: a 128 x 128
+// tile of (q, i); each of its four waves takes a 64 x 64 quadrant as 4 x 4
+// blocks of 16 x 16 on float64 MFMA (k = 4 per step).  Per round 32 entries of
+// k of the tile's 128 rows of A and of R are staged in LDS, and the next
+// round's are loaded into registers while the current round multiplies.
+__global__ void __launch_bounds__(256) k_rbf_gemm(const double* __restrict__ A, uint32_t nq,
+                                                  const double* __restrict__ R, uint32_t nr, uint32_t LS,
+                                                  double* __restrict__ out, uint64_t ostride) {
+  __shared__ double ta[RBF_TM][RBF_LD];
+  __shared__ double tr[RBF_TM][RBF_LD];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const uint32_t i0 = blockIdx.x * RBF_TM, q0 = blockIdx.y * RBF_TM;
+  const int qr = w >> 1, qc = w & 1;   // this wave's quadrant (rows of A, rows of R)
+  rbf_d4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = rbf_d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = rbf_d4{0.0, 0.0, 0.0, 0.0};
+  // staging map: entry e = tid + 256 u of the 128 x 32 slice -> row e / 32, column e % 32
+  double va[RBF_LOADS], vr[RBF_LOADS];
+  auto load = [&](uint32_t k0) {
+#pragma unroll
+    for (int u = 0; u < RBF_LOADS; ++u) {
+      const int e = tid + 256 * u, r = e / RBF_K, c = e % RBF_K;
+      const uint32_t q = q0 + (uint32_t)r, i = i0 + (uint32_t)r;
+      va[u] = q < nq ? A[(size_t)q * LS + k0 + c] : 0.0;
+      vr[u] = i < nr ? R[(size_t)i * LS + k0 + c] : 0.0;
+    }
+  };
+  load(0);
   for (uint32_t k0 = 0; k0 < LS; k0 += RBF_K) {
-    __syncthreads();   // the powers are written / the previous round's tiles are read
-    for (int e = tid; e < RBF_TILE * RBF_K; e += 256) {
-      const int r = e / RBF_K, c = e % RBF_K;
-      const uint32_t k = k0 + (uint32_t)c;
-      double v = 0.0;
-      if (k < (uint32_t)L) {
-        const uint32_t x = expo[k];
-        v = pw[r][0][x & 255u] * pw[r][1][(x >> 8) & 255u] * pw[r][2][x >> 16];
-      }
-      lq[r][c] = v;
-      const uint32_t i = i0 + (uint32_t)r;
-      rt[r][c] = i < nr ? R[(size_t)i * LS + k] : 0.0;
+    __syncthreads();   // the previous round's tiles are read
+#pragma unroll
+    for (int u = 0; u < RBF_LOADS; ++u) {
+      const int e = tid + 256 * u, r = e / RBF_K, c = e % RBF_K;
+      ta[r][c] = va[u];
+      tr[r][c] = vr[u];
     }
     __syncthreads();
-#pragma unroll 4
+    if (k0 + RBF_K < LS) load(k0 + RBF_K);   // in flight during this round's products
+#pragma unroll
     for (int kk = 0; kk < RBF_K; kk += 4) {
       const int kq = kk + (lane >> 4);
-      double av[2], bv[2];
+      double av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = lq[32 * qr + 16 * a + (lane & 15)][kq];
+      for (int a = 0; a < 4; ++a) av[a] = ta[64 * qr + 16 * a + (lane & 15)][kq];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = rt[32 * qc + 16 * b + (lane & 15)][kq];
+      for (int b = 0; b < 4; ++b) bv[b] = tr[64 * qc + 16 * b + (lane & 15)][kq];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
   }
   // accumulator element j of a lane: row 4 j + (lane >> 4), column lane & 15
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const uint32_t q = q0 + 32 * qr + 16 * a + 4 * j + (lane >> 4);
-        const uint32_t i = i0 + 32 * qc + 16 * b + (lane & 15);
+        const uint32_t q = q0 + 64 * qr + 16 * a + 4 * j + (lane >> 4);
+        const uint32_t i = i0 + 64 * qc + 16 * b + (lane & 15);
         if (q < nq && i < nr) out[(size_t)q * ostride + i] = acc[a][b][j];
       }
 }
 
-hipError_t launch_rbf_gemm(int dtype, const void* qx, const void* qy, const void* qz, uint32_t nq, const double* R,
-                           uint32_t nr, uint32_t LS, const uint32_t* expo, int L, int p, double* out,
+hipError_t launch_rbf_basis(int dtype, const void* x, const void* y, const void* z, uint32_t n, const uint32_t* expo,
+                            int L, uint32_t LS, double* A, hipStream_t s) {
+  const uint64_t total = (uint64_t)n * LS;
+  if (total == 0) return hipSuccess;
+  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  if (dtype == FMT_F32)
+    hipLaunchKernelGGL(k_rbf_basis<float>, grid, block, 0, s, (const float*)x, (const float*)y, (const float*)z, n,
+                       expo, L, LS, A);
+  else
+    hipLaunchKernelGGL(k_rbf_basis<double>, grid, block, 0, s, (const double*)x, (const double*)y, (const double*)z,
+                       n, expo, L, LS, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_rbf_gemm(const double* A, uint32_t nq, const double* R, uint32_t nr, uint32_t LS, double* out,
                            uint64_t ostride, hipStream_t s) {
   if (nq == 0 || nr == 0) return hipSuccess;
-  dim3 grid((nr + RBF_TILE - 1) / RBF_TILE, (nq + RBF_TILE - 1) / RBF_TILE), block(256);
-  if (dtype == FMT_F32)
-    hipLaunchKernelGGL(k_rbf_gemm<float>, grid, block, 0, s, (const float*)qx, (const float*)qy, (const float*)qz, nq,
-                       R, nr, LS, expo, L, p, out, ostride);
-  else
-    hipLaunchKernelGGL(k_rbf_gemm<double>, grid, block, 0, s, (const double*)qx, (const double*)qy,
-                       (const double*)qz, nq, R, nr, LS, expo, L, p, out, ostride);
+  dim3 grid((nr + RBF_TM - 1) / RBF_TM, (nq + RBF_TM - 1) / RBF_TM), block(256);
+  hipLaunchKernelGGL(k_rbf_gemm, grid, block, 0, s, A, nq, R, nr, LS, out, ostride);
   return hipGetLastError();
 }
 
