@@ -227,14 +227,17 @@ fmt_status fmt_rbf_factored(int p, double eps, const void* x, const void* y, con
                             void* stream);
 
 /* Wait for all work of the tree's forest and report device-side status
-   (DOMAIN for points outside the box, NUMERIC for non-finite coefficients). */
+   (DOMAIN for points outside the box, NUMERIC for non-finite coefficients).
+   The tree is the octree record P that Alg. 1 builds (per node its centre
+   P_C, scale P_Scale and coefficients P_F, created by FMT_New_Octant). */
 fmt_status fmt_tree_wait(const fmt_tree* tree);
 
-/* Host-side summary of a tree. */
+/* Host-side summary of a tree (Alg. 1's node records P, counted per level). */
 fmt_status fmt_tree_get_info(const fmt_tree* tree, fmt_tree_info* info);
 
 /*
- * Copy the tree's nodes to host buffers (any pointer may be NULL).  Nodes are
+ * Copy the tree's nodes to host buffers (any pointer may be NULL): Alg. 1's
+ * node records P, with the coefficients P_F that Alg. 2 writes.  Nodes are
  * in (level, prefix) order; each buffer holds info.nodes entries (coeffs:
  * info.nodes * info.L float64 in graded order, the Lambda basis).
  *   prefix : the node's key prefix (Morton bits of its cell, 3*level bits)
@@ -258,7 +261,9 @@ fmt_status fmt_tree_export_nodes(const fmt_tree* tree, uint8_t* level, uint32_t*
 
 /*
  * Copy per-point results to host buffers of info.n_points entries, indexed by
- * the caller's input index (any pointer may be NULL):
+ * the caller's input index (any pointer may be NULL); the residual is the f
+ * that Alg. 2 leaves after the deepest node's fit (f - Lambda P_F, summed
+ * down the tree):
  *   keys     : Morton key of the point's cell at depth D
  *   order    : order[i] = input index of the i-th point in key order (stable)
  *   leaf     : index (in export order) of the deepest node holding the point
@@ -268,7 +273,9 @@ fmt_status fmt_tree_export_points(const fmt_tree* tree, uint32_t* keys, uint32_t
                                   uint32_t* leaf, double* residual);
 
 /*
- * Rebuild an evaluable tree from exported nodes (checkpoint / resume):
+ * Rebuild an evaluable tree from exported nodes (checkpoint / resume of
+ * Alg. 1's node records P; the evaluation is Section 2's f'_q = Lambda'_q F_p
+ * summed down the tree):
  * `opts` supplies p, max_depth and the box; level, prefix and coeffs are host
  * arrays of `nodes` entries as fmt_tree_export_nodes writes them.  Every
  * non-root node's parent must be present.  Errors: INVALID_ARG, OOM, DEVICE.
