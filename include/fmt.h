@@ -199,6 +199,9 @@ fmt_status fmt_eval(const fmt_tree* tree, const void* qx, const void* qy, const 
  *   - Calls that overlap in time on one GPU share the array and race: the
  *     caller serialises them (one stream, or events).  Nothing in the array
  *     needs to start at zero; every call writes what it reads.
+ *   - The call enqueues kernels only (no allocation, copy or memset), so it
+ *     can be recorded into a HIP graph and replayed; a replay evaluates the
+ *     query arrays captured, at their current contents.
  */
 #define FMT_EVAL_NOALLOC_SCRATCH_BYTES (72u << 20)
 fmt_status fmt_eval_noalloc(const fmt_tree* tree, const void* qx, const void* qy, const void* qz,

@@ -1604,8 +1604,11 @@ void eval_tree(const fmt_tree* tree, const void* qx, const void* qy, const void*
     std::lock_guard<std::mutex> g(F.compose_mu);
     if (!F.composed || F.cell_ev.size() != F.probs.size() || !F.cell_ev[tree->problem])
       fail(FMT_E_INVALID_ARG, "the tree's evaluation tables are not built: evaluate it once with fmt_eval first");
-    HIPCHK(hipStreamWaitEvent(s, F.cell_ev[tree->problem], 0));
-    HIPCHK(hipStreamWaitEvent(s, F.composed, 0));
+    // wait for the tables only while they are still being built (a stream
+    // under graph capture may not wait on an event recorded outside it)
+    if (hipEventQuery(F.cell_ev[tree->problem]) != hipSuccess)
+      HIPCHK(hipStreamWaitEvent(s, F.cell_ev[tree->problem], 0));
+    if (hipEventQuery(F.composed) != hipSuccess) HIPCHK(hipStreamWaitEvent(s, F.composed, 0));
   } else {
     ensure_composed(F, tree->problem, s);
   }
