@@ -13,7 +13,7 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
-SOURCES = ["k_sort.hip", "k_gram.hip", "k_moments.hip", "k_pyramid.hip", "k_level.hip", "k_eval.hip", "k_wide.hip",
+SOURCES = ["k_sort.hip", "k_gram.hip", "k_moments.hip", "k_pyramid.hip", "k_level.hip", "k_solve_reg.hip", "k_eval.hip", "k_wide.hip",
            "k_rbf.hip", "fmt_host.hip"]
 # (source, extra flags, object): the moment kernels of each large order are
 # compiled in an object of their own, in parallel with the rest
