@@ -189,6 +189,9 @@ struct Workspace {
   // px, py, pz, pf: key-ordered inputs (payload set A); px2 .. pf2: set B
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status;
+  // the levels' lists of nodes that span several chunks (one written while
+  // the other is read)
+  DevBuf multi_a, multi_b;
   // refinement corrections of a level's nodes (late refinement)
   DevBuf delta;
   // float64 moment partials of the mixed path's re-solved nodes
@@ -226,8 +229,8 @@ struct Workspace {
   // the host-visible word; every few thousand spins ask whether the stream
   // has drained (then the word must be there, else read the device copy).
   // out: next level's nodes, chunks, points, small nodes; this level's
-  // nodes flagged for refinement
-  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[5]) {
+  // nodes flagged for refinement; next level's multi-chunk nodes
+  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[6]) {
     for (uint64_t it = 1;; ++it) {
       if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) {
         out[0] = __atomic_load_n(level_flag + 0, __ATOMIC_RELAXED);
@@ -235,18 +238,20 @@ struct Workspace {
         out[2] = __atomic_load_n(level_flag + 2, __ATOMIC_RELAXED);
         out[3] = __atomic_load_n(level_flag + 4, __ATOMIC_RELAXED);
         out[4] = __atomic_load_n(level_flag + 5, __ATOMIC_RELAXED);
+        out[5] = __atomic_load_n(level_flag + 6, __ATOMIC_RELAXED);
         return;
       }
       if ((it & 4095) == 0) {
         const hipError_t e = hipStreamQuery(s);
         if (e == hipSuccess) {
           if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) continue;
-          HIPCHK(hipMemcpy(host_counters, counters_dev, 24, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(host_counters, counters_dev, 28, hipMemcpyDeviceToHost));
           out[0] = host_counters[0];
           out[1] = host_counters[1];
           out[2] = host_counters[2];
           out[3] = host_counters[4];
           out[4] = host_counters[5];
+          out[5] = host_counters[6];
           return;
         }
         if (e != hipErrorNotReady) hip_check(e, "level wait");
@@ -814,6 +819,11 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
   // chunk_b in turn
   const uint32_t* cur_off = reinterpret_cast<const uint32_t*>(sm + o_off);
   DevBuf* next_off = &W.chunk_a;
+  // the level's multi-chunk nodes as the previous topology pass listed them
+  // (level 0: not listed)
+  const uint32_t* cur_multi = nullptr;
+  uint32_t cur_nmulti = 0;
+  DevBuf* next_multi = &W.multi_a;
   const size_t gpd = use_moments ? moment_partial_doubles(F->p) : gram_partial_doubles(F->p);
   const size_t fd = wide ? wide_factor_doubles(F->p) : factor_doubles(F->p);
   const size_t rbd = moment_refine_doubles(F->p);
@@ -843,12 +853,15 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     W.ccnt.reserve(4ull * 8 * nnodes);
     W.nact.reserve(4ull * nnodes);
     next_off->reserve(4ull * (8ull * nnodes + 1));
+    next_multi->reserve(4ull * 8ull * nnodes);
 
     LevelArgs a;
     a.nt = nt;
     a.node0 = node0;
     a.nnodes = nnodes;
     a.chunk_off = cur_off;
+    a.multi = cur_multi;
+    a.nmulti = cur_nmulti;
     a.nchunks = nchunks;
     a.px = W.px.p;
     a.py = W.py.p;
@@ -975,7 +988,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       break;
     }
     const uint32_t next0 = node0 + nnodes;
-    uint32_t cnt[5];
+    uint32_t cnt[6];
     auto topology = [&](void) {
       {
         ProfScope ps(KN_CHILD, nnodes, s);
@@ -986,7 +999,8 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
       {
         ProfScope ps(KN_EMIT, nnodes, s);
         HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
-                           next_off->as<uint32_t>(), W.counters.as<uint32_t>(), W.level_flag_dev, seq, s));
+                           next_off->as<uint32_t>(), W.counters.as<uint32_t>(), W.level_flag_dev, seq,
+                           next_multi->as<uint32_t>(), s));
       }
       W.counters_dev = W.counters.p;
       W.wait_level(seq, s, cnt);
@@ -1005,6 +1019,9 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     nsmall = cnt[3];
     cur_off = next_off->as<uint32_t>();
     next_off = next_off == &W.chunk_a ? &W.chunk_b : &W.chunk_a;
+    cur_multi = next_multi->as<uint32_t>();
+    cur_nmulti = cnt[5];
+    next_multi = next_multi == &W.multi_a ? &W.multi_b : &W.multi_a;
   }
   F->nodes = node0;
   F->depth_present = (int)F->level_start.size() - 1;

@@ -58,6 +58,11 @@ struct LevelArgs {
   // residual pass can subtract Lambda delta
   uint32_t sweep_current = 0;
   double* delta = nullptr;
+  // level-local indices of the nodes that span more than one chunk (the
+  // topology kernel lists them for the next level), nmulti of them; null:
+  // not listed, the chunk reduction looks at every node
+  const uint32_t* multi = nullptr;
+  uint32_t nmulti = 0;
 };
 
 // Nodes with fewer points than this take the r-weighted moments in mode 4
@@ -182,12 +187,15 @@ hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uin
                            uint32_t* nact, hipStream_t s);
 // counters[0..2] = next level's nodes, chunks, points, counters[4] = its
 // nodes with fewer than SMALL_NODE points, counters[5] = this level's nodes
-// flagged for refinement (FLAG_REFINE); with hostc (device view of
-// host-visible memory) they are also written there (same positions), and
-// the sequence number at hostc[3] last (system-scope release).
+// flagged for refinement (FLAG_REFINE), counters[6] = next level's nodes
+// that span more than one chunk, whose level-local indices go to next_multi
+// (room for 8 nnodes entries; in no fixed order); with hostc (device view
+// of host-visible memory) the counters are also written there (same
+// positions), and the sequence number at hostc[3] last (system-scope
+// release).
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
-                       uint32_t seq, hipStream_t s);
+                       uint32_t seq, uint32_t* next_multi, hipStream_t s);
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
 // Row stride (doubles) of the composite coefficient table: calL rounded up to
 // even, so that every row starts on a 16-byte boundary.

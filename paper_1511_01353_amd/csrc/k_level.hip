@@ -962,14 +962,18 @@ __global__ void __launch_bounds__(256) k_children(LevelArgs a, const double* __r
 // 64 elements of one node with 16 lane groups; group q sums chunks
 // q, q+16, ... into eight interleaved accumulators (eight loads in flight per
 // thread), and the sixteen group sums are added in a fixed tree.
-// Single-chunk nodes exit at once.
+// Single-chunk nodes exit at once; with the level's list of multi-chunk
+// nodes (multi, nmulti entries) only those are launched.
 __global__ void __launch_bounds__(1024) k_chunk_reduce(const uint32_t* __restrict__ chunk_off, uint32_t nnodes,
                                                        double* __restrict__ buf, uint32_t width, uint32_t eblocks,
                                                        uint64_t fstride, const uint32_t* __restrict__ flags,
-                                                       uint32_t only_flag) {
+                                                       uint32_t only_flag, const uint32_t* __restrict__ multi,
+                                                       uint32_t nmulti) {
   __shared__ double part[16][64];
   buf += (size_t)blockIdx.y * fstride;   // the field's partials
-  const uint32_t k = blockIdx.x / eblocks;
+  const uint32_t q0 = blockIdx.x / eblocks;
+  if (q0 >= (multi ? nmulti : nnodes)) return;
+  const uint32_t k = multi ? multi[q0] : q0;
   if (k >= nnodes) return;
   const uint32_t c0 = chunk_off[k], c1 = chunk_off[k + 1];
   if (c1 - c0 < 2) return;
@@ -1027,9 +1031,11 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
                                                uint32_t* __restrict__ nact, uint32_t next0,
                                                uint32_t* __restrict__ next_chunk_off,
                                                uint32_t* __restrict__ counters, uint32_t* __restrict__ hostc,
-                                               uint32_t seq) {
+                                               uint32_t seq, uint32_t* __restrict__ next_multi) {
   __shared__ uint32_t wsum[16];
+  __shared__ uint32_t nmulti;   // children spanning more than one chunk, listed in next_multi
   const uint32_t tid = threadIdx.x;
+  if (tid == 0) nmulti = 0;
   const uint32_t m = a.nnodes;
   const uint32_t seg = (m + 1023u) / 1024u;
   const uint32_t b = min(m, tid * seg), e = min(m, b + seg);
@@ -1074,6 +1080,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     a.nt.flags[cid] = 0;
     node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
     next_chunk_off[crun] = (cn + CHUNK - 1) / CHUNK;
+    if (cn > CHUNK) next_multi[atomicAdd(&nmulti, 1u)] = crun;   // the list's order does not matter
     pts += cn;
     small += cn < (uint32_t)SMALL_NODE ? 1u : 0u;
   }
@@ -1101,6 +1108,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     counters[2] = next_points;
     counters[4] = next_small;
     counters[5] = level_flagged;
+    counters[6] = nmulti;
     if (hostc) {
       // the same counters into host-visible (fine-grained) memory, then the
       // sequence number with a system-scope release: the host waits on it
@@ -1109,6 +1117,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
       hostc[2] = next_points;
       hostc[4] = next_small;
       hostc[5] = level_flagged;
+      hostc[6] = nmulti;
       __hip_atomic_store(hostc + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
@@ -1246,17 +1255,20 @@ hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uin
 
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
-                       uint32_t seq, hipStream_t s) {
+                       uint32_t seq, uint32_t* next_multi, hipStream_t s) {
   hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, s, a, prm, cbeg, ccnt, nact, next0, next_chunk_off, counters,
-                     hostc, seq);
+                     hostc, seq, next_multi);
   return hipGetLastError();
 }
 
 hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, hipStream_t s) {
   if (a.nnodes == 0 || a.nchunks <= a.nnodes) return hipSuccess;
+  const uint32_t nlaunch = a.multi ? a.nmulti : a.nnodes;
+  if (nlaunch == 0) return hipSuccess;
   const uint32_t eblocks = (width + 63) / 64;
-  hipLaunchKernelGGL(k_chunk_reduce, dim3(a.nnodes * eblocks, field_rows(a)), dim3(1024), 0, s, a.chunk_off,
-                     a.nnodes, buf, width, eblocks, (uint64_t)a.nchunks * width, a.nt.flags + a.node0, a.only_flag);
+  hipLaunchKernelGGL(k_chunk_reduce, dim3(nlaunch * eblocks, field_rows(a)), dim3(1024), 0, s, a.chunk_off,
+                     a.nnodes, buf, width, eblocks, (uint64_t)a.nchunks * width, a.nt.flags + a.node0, a.only_flag,
+                     a.multi, a.nmulti);
   return hipGetLastError();
 }
 
