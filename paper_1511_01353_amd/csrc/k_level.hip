@@ -1039,50 +1039,91 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
   const uint32_t m = a.nnodes;
   const uint32_t seg = (m + 1023u) / 1024u;
   const uint32_t b = min(m, tid * seg), e = min(m, b + seg);
+  // Every loop below issues the loads of EB iterations before using any:
+  // one workgroup walks a level of tens of thousands of nodes (batches of
+  // problems), and a load latency per iteration would dominate.
+  constexpr uint32_t EB = 8;
   uint32_t sum = 0, flagged = 0;
-  for (uint32_t i = b; i < e; ++i) {
-    sum += nact[i];
-    flagged += (a.nt.flags[a.node0 + i] & FLAG_REFINE) ? 1u : 0u;
+  for (uint32_t i0 = b; i0 < e; i0 += EB) {
+    uint32_t v[EB], f[EB];
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u) {
+      const uint32_t i = min(i0 + u, e - 1);
+      v[u] = nact[i];
+      f[u] = a.nt.flags[a.node0 + i];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u)
+      if (i0 + u < e) {
+        sum += v[u];
+        flagged += (f[u] & FLAG_REFINE) ? 1u : 0u;
+      }
   }
   uint32_t total, level_flagged;
   (void)scan_1024(flagged, wsum, level_flagged);
   // each node's first child index (exclusive prefix of the active counts),
   // in place of its count
   uint32_t run = scan_1024(sum, wsum, total);
-  for (uint32_t i = b; i < e; ++i) {
-    const uint32_t v = nact[i];
-    nact[i] = run;
-    run += v;
+  for (uint32_t i0 = b; i0 < e; i0 += EB) {
+    uint32_t v[EB];
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u) v[u] = nact[min(i0 + u, e - 1)];
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u)
+      if (i0 + u < e) {
+        nact[i0 + u] = run;
+        run += v[u];
+      }
   }
   __syncthreads();
-  // one thread per (node, octant): the octant's child, if active
+  // one thread per (node, octant): the octant's child, if active; four
+  // strided iterations' loads at a time (children are laid out after the
+  // level's nodes, so none of these loads reads what the iterations write)
   uint32_t pts = 0, small = 0;
-  for (uint32_t pr = tid; pr < 8u * m; pr += 1024u) {
-    const uint32_t i = pr >> 3, o = pr & 7u;
-    const uint32_t node = a.node0 + i;
-    const uint32_t mask = a.nt.child_mask[node];
-    const uint32_t first = next0 + nact[i];
-    if (o == 0 && mask) a.nt.first_child[node] = first;
-    if (!((mask >> o) & 1u)) continue;
-    const uint32_t crun = nact[i] + (uint32_t)__popc(mask & ((1u << o) - 1u));
-    const uint32_t cid = next0 + crun;
-    const uint32_t prob = a.nt.problem[node];
-    const uint32_t cpre = (a.nt.prefix[node] << 3) | o;
-    a.nt.begin[cid] = cbeg[pr];
-    const uint32_t cn = ccnt[pr];
-    a.nt.count[cid] = cn;
-    a.nt.prefix[cid] = cpre;
-    a.nt.level[cid] = (uint32_t)(a.level + 1);
-    a.nt.problem[cid] = prob;
-    a.nt.parent[cid] = node;
-    a.nt.first_child[cid] = 0;
-    a.nt.child_mask[cid] = 0;
-    a.nt.flags[cid] = 0;
-    node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
-    next_chunk_off[crun] = (cn + CHUNK - 1) / CHUNK;
-    if (cn > CHUNK) next_multi[atomicAdd(&nmulti, 1u)] = crun;   // the list's order does not matter
-    pts += cn;
-    small += cn < (uint32_t)SMALL_NODE ? 1u : 0u;
+  constexpr uint32_t CB = 4;
+  const uint32_t npr = 8u * m;
+  for (uint32_t pr0 = tid; pr0 < npr; pr0 += 1024u * CB) {
+    uint32_t mk[CB], fi[CB], pb[CB], px[CB], cb[CB], cc[CB];
+#pragma unroll
+    for (uint32_t u = 0; u < CB; ++u) {
+      const uint32_t pr = min(pr0 + 1024u * u, npr - 1), node = a.node0 + (pr >> 3);
+      mk[u] = a.nt.child_mask[node];
+      fi[u] = nact[pr >> 3];
+      pb[u] = a.nt.problem[node];
+      px[u] = a.nt.prefix[node];
+      cb[u] = cbeg[pr];
+      cc[u] = ccnt[pr];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < CB; ++u) {
+      const uint32_t pr = pr0 + 1024u * u;
+      if (pr >= npr) continue;
+      const uint32_t i = pr >> 3, o = pr & 7u;
+      const uint32_t node = a.node0 + i;
+      const uint32_t mask = mk[u];
+      const uint32_t first = next0 + fi[u];
+      if (o == 0 && mask) a.nt.first_child[node] = first;
+      if (!((mask >> o) & 1u)) continue;
+      const uint32_t crun = fi[u] + (uint32_t)__popc(mask & ((1u << o) - 1u));
+      const uint32_t cid = next0 + crun;
+      const uint32_t prob = pb[u];
+      const uint32_t cpre = (px[u] << 3) | o;
+      a.nt.begin[cid] = cb[u];
+      const uint32_t cn = cc[u];
+      a.nt.count[cid] = cn;
+      a.nt.prefix[cid] = cpre;
+      a.nt.level[cid] = (uint32_t)(a.level + 1);
+      a.nt.problem[cid] = prob;
+      a.nt.parent[cid] = node;
+      a.nt.first_child[cid] = 0;
+      a.nt.child_mask[cid] = 0;
+      a.nt.flags[cid] = 0;
+      node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
+      next_chunk_off[crun] = (cn + CHUNK - 1) / CHUNK;
+      if (cn > CHUNK) next_multi[atomicAdd(&nmulti, 1u)] = crun;   // the list's order does not matter
+      pts += cn;
+      small += cn < (uint32_t)SMALL_NODE ? 1u : 0u;
+    }
   }
   __syncthreads();
   // total points of the next level (integer sum: exact in any order)
@@ -1093,13 +1134,25 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
   const uint32_t seg2 = (total + 1023u) / 1024u;
   const uint32_t b2 = min(total, tid * seg2), e2 = min(total, b2 + seg2);
   uint32_t sum2 = 0;
-  for (uint32_t i = b2; i < e2; ++i) sum2 += next_chunk_off[i];
+  for (uint32_t i0 = b2; i0 < e2; i0 += EB) {
+    uint32_t v[EB];
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u) v[u] = next_chunk_off[min(i0 + u, e2 - 1)];
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u) sum2 += i0 + u < e2 ? v[u] : 0u;
+  }
   uint32_t nchunks_next;
   uint32_t run2 = scan_1024(sum2, wsum, nchunks_next);
-  for (uint32_t i = b2; i < e2; ++i) {
-    const uint32_t v = next_chunk_off[i];
-    next_chunk_off[i] = run2;
-    run2 += v;
+  for (uint32_t i0 = b2; i0 < e2; i0 += EB) {
+    uint32_t v[EB];
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u) v[u] = next_chunk_off[min(i0 + u, e2 - 1)];
+#pragma unroll
+    for (uint32_t u = 0; u < EB; ++u)
+      if (i0 + u < e2) {
+        next_chunk_off[i0 + u] = run2;
+        run2 += v[u];
+      }
   }
   if (tid == 1023) {
     next_chunk_off[total] = nchunks_next;
