@@ -47,7 +47,7 @@ struct LevelArgs {
   // or that deflate a pivot, and leaves their coefficients to the float64
   // re-solve
   uint32_t regram = 0;
-  // nonzero: k_moments (mode 0), k_chunk_reduce, k_solve_m and k_residual
+  // nonzero: k_moments (mode 0), k_chunk_reduce, the moment solves and k_residual
   // take only the nodes whose flags hold one of these bits (the float64
   // re-solve; the refinement's correction pass)
   uint32_t only_flag = 0;
@@ -138,16 +138,16 @@ hipError_t launch_solve(int p, const LevelArgs& a, const double* partial, double
 // the mode-2 partials part_b.
 hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part_m, const double* part_b,
                                 const double* pyr, double* fac, hipStream_t s);
-// Moment pyramid (k_pyramid.hip): moment_base_doubles(p) doubles per entry.
-// The finest cells of all pyramids (flat numbering): point range, frame (6
-// doubles), chunk count and pyramid entry.  begin and count must hold zeros
-// on entry (empty cells are never written by the boundary pass).
 // The same solve with the matrix in one wave's registers (k_solve_reg.hip),
 // for the orders solve_reg_order accepts (p <= 6); launch_solve_moments
 // takes it for those orders.
 bool solve_reg_order(int p);
 hipError_t launch_solve_reg(int p, const LevelArgs& a, const double* part_m, const double* part_b, const double* pyr,
                             double* fac, hipStream_t s);
+// Moment pyramid (k_pyramid.hip): moment_base_doubles(p) doubles per entry.
+// The finest cells of all pyramids (flat numbering): point range, frame (6
+// doubles), chunk count and pyramid entry.  begin and count must hold zeros
+// on entry (empty cells are never written by the boundary pass).
 hipError_t launch_pyr_cells(const uint32_t* skey, uint32_t n, int D, int nprob, const ProblemParams* prm,
                             const PyrTab& pt, uint32_t ncell, uint32_t* begin, uint32_t* count, double* geo,
                             uint32_t* nchk, uint32_t* dst, hipStream_t s);

@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(256) k_solve_ahead(LevelArgs a, const double* 
   const uint32_t k = blockIdx.x;
   const uint32_t node = a.node0 + k;
   const uint32_t* pt = a.pyr_tab + PYR_TAB_WORDS * a.nt.problem[node];
-  if (!((pt[3] >> 28) > (uint32_t)a.level)) return;   // whole workgroup: factored in this level's k_solve_m
+  if (!((pt[3] >> 28) > (uint32_t)a.level)) return;   // whole workgroup: factored in this level's solve
   const uint32_t c0 = a.chunk_off[k];   // chunks of the node were summed into this one
   const uint32_t slot = (pt[3] & 0x0FFFFFFFu) + level_first(a.level) + a.nt.prefix[node];
   const double* fo = a.fac_up + (size_t)slot * FW;
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(256) k_factor_m(LevelArgs a, const double* __r
 // Factors made ahead of the level loop: one workgroup per listed pyramid
 // entry (a cell of a level above the pyramid's finest), its M taken from
 // the pyramid, the factor and the flags of its condition estimate stored in
-// slot g.  The level's solve then only applies them (k_solve_m).
+// slot g.  The level's solve then only applies them (k_solve_ahead).
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ void __launch_bounds__(256) k_factor_cells(const double* __restrict__ pyr,
