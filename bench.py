@@ -522,6 +522,7 @@ def main():
         return
     paths = [args.path] if args.no_compare else [args.path] + [p for p in ("fp64", "mixed") if p != args.path]
     results = {}
+    kept = {}
     for path in paths:
         opts = fmt.fmt_default_opts(p=pr.p, tol=pr.tol, max_depth=pr.max_depth,
                                     path=fmt.FMT_PATH_MIXED if path == "mixed" else fmt.FMT_PATH_FP64,
@@ -566,6 +567,8 @@ def main():
         fq = out.cpu().numpy()
         e_rms = float(np.sqrt(np.mean((fq - pr.qf_true) ** 2)))
         e_inf = float(np.max(np.abs(fq - pr.qf_true)))
+        # kept for the comparison with the oracle's fit of the same workload
+        kept[path] = dict(residual=last.export_points()["residual"], nodes=last.export_nodes(), fq=fq)
         last.close()
         results[path] = dict(
             fit_pts_per_s=args.n * len(fit_t) / sum(fit_t),
@@ -621,8 +624,10 @@ def main():
         others["rbf_check"] = rbf_leg(fmt, 3)
 
     cpu = None
+    vs_oracle = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pr, args.cpu_sample)
+        cpu, ot = cpu_baseline(pr, args.cpu_sample)
+        vs_oracle = oracle_comparison(pr, ot, kept)
 
     cmp = None
     if "fp64" in results and "mixed" in results:
@@ -653,6 +658,7 @@ def main():
         "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in st.items()}
                     for k, st in h["kernels"].items()},
         "mixed_vs_fp64": cmp,
+        "vs_oracle": vs_oracle,
         "refit": refit,
         **others,
         "cpu_baseline": cpu,
@@ -683,13 +689,16 @@ def cpu_baseline(pr, sample: int):
         threadpool_limits = None
         threads = os.cpu_count() or 1
 
+    kept = {}
+
     def timed(p, n=None):
         n = p.n if n is None else min(n, p.n)
         t0 = time.perf_counter()
-        oracle.fit(p.x[:n], p.y[:n], p.z[:n], p.f[:n], p.p, p.tol, p.max_depth)
+        kept["tree"] = oracle.fit(p.x[:n], p.y[:n], p.z[:n], p.f[:n], p.p, p.tol, p.max_depth)
         return n, time.perf_counter() - t0
 
     n_all, dt_all = timed(pr)
+    ot = kept["tree"]
     _progress(f"cpu oracle, {n_all} points, {threads} threads: {dt_all:.1f} s")
     small = synthetic.config1()
     variants = []
@@ -707,7 +716,31 @@ def cpu_baseline(pr, sample: int):
     return {"value": n_all / dt_all, "unit": "fit points/s", "cores": int(threads), "kind": "oracle",
             "sample": f"all {n_all} points of the benchmark workload (p={pr.p}, depth<={pr.max_depth}, "
                       f"tol={pr.tol}; the same tree as the GPU fit); {dt_all:.1f} s",
-            "variants": variants}
+            "variants": variants}, ot
+
+
+def oracle_comparison(pr, ot, kept, nsample: int = 1 << 14):
+    """Each path's last fit of the benchmark workload against the oracle's fit
+    of the same workload (the baseline leg's): node set, fitted values at the
+    points, and evaluation at a seeded sample of the queries."""
+    import numpy as np
+
+    import oracle
+    sel = np.sort(np.random.default_rng(20).choice(pr.qx.shape[0], nsample, replace=False))
+    want = oracle.evaluate(ot, pr.qx[sel], pr.qy[sel], pr.qz[sel])
+    out = {}
+    for path, k in kept.items():
+        nd = k["nodes"]
+        same = (nd["level"].shape[0] == ot.nodes and np.array_equal(nd["level"].astype(np.int64), ot.level)
+                and np.array_equal(nd["prefix"].astype(np.int64), ot.prefix)
+                and np.array_equal(nd["begin"].astype(np.int64), ot.begin)
+                and np.array_equal(nd["count"].astype(np.int64), ot.count))
+        d = k["fq"][sel] - want
+        out[path] = {"nodes_equal": bool(same),
+                     "fitted_rms_diff": float(np.sqrt(np.mean((k["residual"] - ot.residual) ** 2))),
+                     "eval_rms_diff": float(np.sqrt(np.mean(d ** 2))), "eval_max_diff": float(np.max(np.abs(d))),
+                     "queries": int(nsample)}
+    return out
 
 
 if __name__ == "__main__":
