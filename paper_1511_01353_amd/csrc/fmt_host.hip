@@ -189,6 +189,10 @@ struct Workspace {
   // px, py, pz, pf: key-ordered inputs (payload set A); px2 .. pf2: set B
   DevBuf keys_alt, vals_alt, sort_scratch, px, py, pz, pf, px2, py2, pz2, pf2;
   DevBuf partial, fac, part_b, part_ss, cbeg, ccnt, nact, chunk_a, chunk_b, counters, status;
+  // the level's nodes flagged for the late refinement and their chunk offsets
+  // among them, as the topology kernel lists them; the tiled topology
+  // launches' per-tile sums
+  DevBuf fsel, emit_tiles;
   // the levels' lists of nodes that span several chunks (one written while
   // the other is read)
   DevBuf multi_a, multi_b;
@@ -229,8 +233,9 @@ struct Workspace {
   // the host-visible word; every few thousand spins ask whether the stream
   // has drained (then the word must be there, else read the device copy).
   // out: next level's nodes, chunks, points, small nodes; this level's
-  // nodes flagged for refinement; next level's multi-chunk nodes
-  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[6]) {
+  // nodes flagged for refinement; next level's multi-chunk nodes; the
+  // flagged nodes' chunks
+  void wait_level(uint32_t seq, hipStream_t s, uint32_t out[7]) {
     for (uint64_t it = 1;; ++it) {
       if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) {
         out[0] = __atomic_load_n(level_flag + 0, __ATOMIC_RELAXED);
@@ -239,19 +244,21 @@ struct Workspace {
         out[3] = __atomic_load_n(level_flag + 4, __ATOMIC_RELAXED);
         out[4] = __atomic_load_n(level_flag + 5, __ATOMIC_RELAXED);
         out[5] = __atomic_load_n(level_flag + 6, __ATOMIC_RELAXED);
+        out[6] = __atomic_load_n(level_flag + 7, __ATOMIC_RELAXED);
         return;
       }
       if ((it & 4095) == 0) {
         const hipError_t e = hipStreamQuery(s);
         if (e == hipSuccess) {
           if (__atomic_load_n(level_flag + 3, __ATOMIC_ACQUIRE) == seq) continue;
-          HIPCHK(hipMemcpy(host_counters, counters_dev, 28, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(host_counters, counters_dev, 32, hipMemcpyDeviceToHost));
           out[0] = host_counters[0];
           out[1] = host_counters[1];
           out[2] = host_counters[2];
           out[3] = host_counters[4];
           out[4] = host_counters[5];
           out[5] = host_counters[6];
+          out[6] = host_counters[7];
           return;
         }
         if (e != hipErrorNotReady) hip_check(e, "level wait");
@@ -854,6 +861,8 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     W.nact.reserve(4ull * nnodes);
     next_off->reserve(4ull * (8ull * nnodes + 1));
     next_multi->reserve(4ull * 8ull * nnodes);
+    W.fsel.reserve(4ull * (2ull * nnodes + 2));
+    W.emit_tiles.reserve(4ull * emit_tile_words(nnodes));
 
     LevelArgs a;
     a.nt = nt;
@@ -941,11 +950,21 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     // flagged nodes, topology again).  The mixed path (every node) and the
     // large bases refine before the residual update.
     const bool late_refine = a.refine == 1 && !wide;
-    auto refine_late = [&](void) {
+    // the topology pass's counters (see wait_level)
+    uint32_t cnt[7];
+    // listed: the topology pass has listed the flagged nodes (cnt holds their
+    // numbers), and the passes launch over those alone
+    auto refine_late = [&](bool listed) {
       W.delta.reserve(8ull * L * nnodes);
       LevelArgs r = a;
       r.sweep_current = 1;
       r.delta = W.delta.as<double>();
+      if (listed) {
+        r.sel = W.fsel.as<uint32_t>();
+        r.sel_off = r.sel + nnodes + 1;
+        r.nsel = cnt[4];
+        r.nsel_chunks = cnt[6];
+      }
       for (int it = 0; it < F->refine; ++it) {
         {
           ProfScope ps(KN_RSWEEP, level_points, s);
@@ -959,6 +978,11 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
         LevelArgs c = r;
         c.only_flag = FLAG_REFINE;
         HIPCHK(launch_residual(F->p, dtype, c, W.part_ss.as<double>(), s));
+        if (listed) {
+          // the listed nodes that span several chunks
+          c.multi = r.sel;
+          c.nmulti = r.nsel;
+        }
         if (multi && d < F->D) HIPCHK(launch_chunk_reduce(c, W.part_ss.as<double>(), 16, s));
       }
     };
@@ -983,12 +1007,11 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     }
     F->level_points.push_back(level_points);
     if (d == F->D) {
-      if (late_refine && F->refine > 0) refine_late();   // no topology pass to report the flagged count
+      if (late_refine && F->refine > 0) refine_late(false);   // no topology pass to list the flagged nodes
       node0 += nnodes;
       break;
     }
     const uint32_t next0 = node0 + nnodes;
-    uint32_t cnt[6];
     auto topology = [&](void) {
       {
         ProfScope ps(KN_CHILD, nnodes, s);
@@ -1000,7 +1023,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
         ProfScope ps(KN_EMIT, nnodes, s);
         HIPCHK(launch_emit(a, d_prm, W.cbeg.as<uint32_t>(), W.ccnt.as<uint32_t>(), W.nact.as<uint32_t>(), next0,
                            next_off->as<uint32_t>(), W.counters.as<uint32_t>(), W.level_flag_dev, seq,
-                           next_multi->as<uint32_t>(), s));
+                           next_multi->as<uint32_t>(), W.fsel.as<uint32_t>(), W.emit_tiles.as<uint32_t>(), s));
       }
       W.counters_dev = W.counters.p;
       W.wait_level(seq, s, cnt);
@@ -1009,7 +1032,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     if (late_refine && F->refine > 0 && cnt[4] > 0) {
       // flagged nodes: refine them and take the topology of the corrected
       // residual
-      refine_late();
+      refine_late(true);
       topology();
     }
     node0 = next0;
@@ -1457,11 +1480,11 @@ fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const v
       groups[std::make_tuple(opts[k].p, opts[k].path, opts[k].max_depth, opts[k].refine_steps, opts[k].tol,
                              opts[k].gram)]
           .push_back(k);
-    std::vector<const std::vector<int>*> glist;
-    for (auto& kv : groups) glist.push_back(&kv.second);
+    std::vector<std::vector<int>> glist;
+    for (auto& kv : groups) glist.push_back(std::move(kv.second));
     std::vector<std::shared_ptr<Forest>> forests(glist.size());
     auto run_group = [&](size_t g, hipStream_t s) {
-      const std::vector<int>& ids = *glist[g];
+      const std::vector<int>& ids = glist[g];
       std::vector<fmt_fit_opts> per;
       std::vector<FitInput> in;
       for (int k : ids) {
@@ -1510,7 +1533,7 @@ fmt_status fmt_fit_batch(const fmt_fit_opts* opts, const void* const* x, const v
     std::vector<fmt_tree*> made(count, nullptr);
     try {
       for (size_t g = 0; g < glist.size(); ++g) {
-        const std::vector<int>& ids = *glist[g];
+        const std::vector<int>& ids = glist[g];
         for (size_t j = 0; j < ids.size(); ++j) {
           fmt_tree* t = new fmt_tree();
           t->forest = forests[g];

@@ -63,6 +63,15 @@ struct LevelArgs {
   // not listed, the chunk reduction looks at every node
   const uint32_t* multi = nullptr;
   uint32_t nmulti = 0;
+  // non-null: the launch covers only the listed nodes of the level (the
+  // late refinement's passes over the nodes flagged for it, as the topology
+  // kernel lists them): level-local indices sel[0 .. nsel), ascending, and
+  // sel_off[j] the first work item of node sel[j] (its chunks in order;
+  // sel_off[nsel] = nsel_chunks).  Chunk-wide launches then have
+  // nsel_chunks workgroups, node-wide ones nsel.
+  const uint32_t* sel = nullptr;
+  const uint32_t* sel_off = nullptr;
+  uint32_t nsel = 0, nsel_chunks = 0;
 };
 
 // Nodes with fewer points than this take the r-weighted moments in mode 4
@@ -189,13 +198,20 @@ hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uin
 // nodes with fewer than SMALL_NODE points, counters[5] = this level's nodes
 // flagged for refinement (FLAG_REFINE), counters[6] = next level's nodes
 // that span more than one chunk, whose level-local indices go to next_multi
-// (room for 8 nnodes entries; in no fixed order); with hostc (device view
-// of host-visible memory) the counters are also written there (same
-// positions), and the sequence number at hostc[3] last (system-scope
-// release).
+// (room for 8 nnodes entries; in no fixed order), counters[7] = the chunks
+// of this level's flagged nodes; those nodes go to sel (level-local
+// indices, ascending) and their first chunk numbers among them to
+// sel + nnodes + 1 (LevelArgs::sel, sel_off; room for 2 nnodes + 2
+// entries).  With hostc (device view of host-visible memory) the counters
+// are also written there (same positions), and the sequence number at
+// hostc[3] last (system-scope release), once the launch has written
+// everything else.  Large levels take the tiled launches, whose scratch is
+// tiles (emit_tile_words(a.nnodes) words; may be null when that is 0) and
+// counters[8].
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
-                       uint32_t seq, uint32_t* next_multi, hipStream_t s);
+                       uint32_t seq, uint32_t* next_multi, uint32_t* sel, uint32_t* tiles, hipStream_t s);
+size_t emit_tile_words(uint32_t nnodes);
 hipError_t launch_check_coef(int p, const NodeTable& nt, uint32_t nnodes, uint32_t* status, hipStream_t s);
 // Row stride (doubles) of the composite coefficient table: calL rounded up to
 // even, so that every row starts on a 16-byte boundary.
@@ -267,6 +283,17 @@ __device__ __forceinline__ uint32_t chunk_node(const uint32_t* chunk_off, uint32
     hi = min(hi, lo + step);
   }
   return lo;
+}
+
+// Work item w of a launch over the listed nodes' chunks (LevelArgs::sel):
+// the node k (level-local) and its chunk g among the level's chunks.
+// False past the last listed chunk.
+__device__ __forceinline__ bool listed_chunk(const LevelArgs& a, uint32_t w, uint32_t& k, uint32_t& g) {
+  if (w >= a.nsel_chunks) return false;
+  const uint32_t j = chunk_node(a.sel_off, a.nsel, w);
+  k = a.sel[j];
+  g = a.chunk_off[k] + (w - a.sel_off[j]);
+  return true;
 }
 
 // Cell coordinates (i, j, k) of a Morton prefix with `level` triples.

@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(256) k_refine_solve(LevelArgs a, const double*
   __shared__ double A[S::WORDS + 16];   // + the zero row
   __shared__ double b[L], z[L], iv[L], sc[L];
   const int tid = threadIdx.x;
-  const uint32_t k = blockIdx.x;
+  const uint32_t k = a.sel ? a.sel[blockIdx.x] : blockIdx.x;
   const uint32_t node = a.node0 + k;
   if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
   // with a.refine == 2 (every node refined) the chunk partials were summed
@@ -748,8 +748,12 @@ __global__ void __launch_bounds__(ResidualShape<P>::THREADS) k_residual(LevelArg
   __shared__ double red[NW][8];
   __shared__ uint32_t redc[NW][8];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const uint32_t g = blockIdx.x;
-  const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
+  uint32_t g = blockIdx.x, k;
+  if (a.sel) {
+    if (!listed_chunk(a, blockIdx.x, k, g)) return;
+  } else {
+    k = chunk_node(a.chunk_off, a.nnodes, g);
+  }
   const uint32_t node = a.node0 + k;
   if (a.only_flag && !(a.nt.flags[node] & a.only_flag)) return;   // whole workgroup: not this pass's node
   const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
@@ -854,11 +858,12 @@ __global__ void __launch_bounds__(ResidualShape<P>::THREADS) k_residual(LevelArg
   }
 }
 
-// Exclusive prefix sum of one value per thread over a 1024-thread workgroup:
-// inclusive scans inside each wave (shuffles), then the wave totals from LDS.
-// Returns the thread's exclusive prefix and sets total; wsum holds 16 words.
-// Every thread must call it (two barriers inside).
-__device__ __forceinline__ uint32_t scan_1024(uint32_t x, uint32_t* wsum, uint32_t& total) {
+// Exclusive prefix sum of one value per thread over a workgroup of NT
+// threads: inclusive scans inside each wave (shuffles), then the wave totals
+// from LDS.  Returns the thread's exclusive prefix and sets total; wsum holds
+// NT / 64 words.  Every thread must call it (two barriers inside).
+template <uint32_t NT>
+__device__ __forceinline__ uint32_t scan_block(uint32_t x, uint32_t* wsum, uint32_t& total) {
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   uint32_t v = x;
 #pragma unroll
@@ -870,7 +875,7 @@ __device__ __forceinline__ uint32_t scan_1024(uint32_t x, uint32_t* wsum, uint32
   __syncthreads();
   uint32_t base = 0, all = 0;
 #pragma unroll
-  for (uint32_t q = 0; q < 16; ++q) {
+  for (uint32_t q = 0; q < NT / 64; ++q) {
     const uint32_t t = wsum[q];
     base += q < w ? t : 0u;
     all += t;
@@ -878,6 +883,9 @@ __device__ __forceinline__ uint32_t scan_1024(uint32_t x, uint32_t* wsum, uint32
   __syncthreads();   // wsum may be reused after this
   total = all;
   return base + v - x;
+}
+__device__ __forceinline__ uint32_t scan_1024(uint32_t x, uint32_t* wsum, uint32_t& total) {
+  return scan_block<1024>(x, wsum, total);
 }
 
 // ---------------------------------------------------------------------------
@@ -1031,7 +1039,8 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
                                                uint32_t* __restrict__ nact, uint32_t next0,
                                                uint32_t* __restrict__ next_chunk_off,
                                                uint32_t* __restrict__ counters, uint32_t* __restrict__ hostc,
-                                               uint32_t seq, uint32_t* __restrict__ next_multi) {
+                                               uint32_t seq, uint32_t* __restrict__ next_multi,
+                                               uint32_t* __restrict__ sel) {
   __shared__ uint32_t wsum[16];
   __shared__ uint32_t nmulti;   // children spanning more than one chunk, listed in next_multi
   const uint32_t tid = threadIdx.x;
@@ -1043,7 +1052,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
   // one workgroup walks a level of tens of thousands of nodes (batches of
   // problems), and a load latency per iteration would dominate.
   constexpr uint32_t EB = 8;
-  uint32_t sum = 0, flagged = 0;
+  uint32_t sum = 0, flagged = 0, fchunks = 0;
   for (uint32_t i0 = b; i0 < e; i0 += EB) {
     uint32_t v[EB], f[EB];
 #pragma unroll
@@ -1056,11 +1065,28 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     for (uint32_t u = 0; u < EB; ++u)
       if (i0 + u < e) {
         sum += v[u];
-        flagged += (f[u] & FLAG_REFINE) ? 1u : 0u;
+        if (f[u] & FLAG_REFINE) {
+          ++flagged;
+          fchunks += a.chunk_off[i0 + u + 1] - a.chunk_off[i0 + u];
+        }
       }
   }
-  uint32_t total, level_flagged;
-  (void)scan_1024(flagged, wsum, level_flagged);
+  uint32_t total, level_flagged, flagged_chunks;
+  uint32_t fpos = scan_1024(flagged, wsum, level_flagged);
+  uint32_t cpos = scan_1024(fchunks, wsum, flagged_chunks);
+  // the flagged nodes in order and their first chunk numbers among them,
+  // for the late refinement's launches
+  if (sel && flagged) {
+    uint32_t* sel_off = sel + m + 1;
+    for (uint32_t i = b; i < e; ++i)
+      if (a.nt.flags[a.node0 + i] & FLAG_REFINE) {
+        sel[fpos] = i;
+        sel_off[fpos] = cpos;
+        ++fpos;
+        cpos += a.chunk_off[i + 1] - a.chunk_off[i];
+      }
+  }
+  if (sel && tid == 0) sel[m + 1 + level_flagged] = flagged_chunks;
   // each node's first child index (exclusive prefix of the active counts),
   // in place of its count
   uint32_t run = scan_1024(sum, wsum, total);
@@ -1162,6 +1188,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     counters[4] = next_small;
     counters[5] = level_flagged;
     counters[6] = nmulti;
+    counters[7] = flagged_chunks;
     if (hostc) {
       // the same counters into host-visible (fine-grained) memory, then the
       // sequence number with a system-scope release: the host waits on it
@@ -1171,8 +1198,175 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
       hostc[4] = next_small;
       hostc[5] = level_flagged;
       hostc[6] = nmulti;
+      hostc[7] = flagged_chunks;
       __hip_atomic_store(hostc + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same layout for a level of more than EMIT_TILED_MIN nodes, in three
+// launches over tiles of EMIT_TILE nodes instead of one workgroup walking
+// them all: the tiles' sums (k_emit_count), their exclusive scan and the
+// counters (k_emit_scan, one workgroup), then every tile's records from its
+// offsets (k_emit_write).  The records, offsets and counters are those of
+// k_emit; the multi-chunk list comes out ascending.
+// ---------------------------------------------------------------------------
+constexpr uint32_t EMIT_TILE = 256;
+constexpr uint32_t EMIT_TILED_MIN = 4096;
+// per tile: children, their chunks, their points, small children,
+// multi-chunk children, flagged nodes, the flagged nodes' chunks
+constexpr int EMIT_SUMS = 7;
+
+__device__ __forceinline__ void emit_node_sums(const LevelArgs& a, const uint32_t* __restrict__ ccnt, uint32_t i,
+                                               uint32_t mask, uint32_t flags, uint32_t s[EMIT_SUMS]) {
+#pragma unroll
+  for (int q = 0; q < EMIT_SUMS; ++q) s[q] = 0;
+  s[0] = (uint32_t)__popc(mask);
+#pragma unroll
+  for (uint32_t o = 0; o < 8u; ++o)
+    if ((mask >> o) & 1u) {
+      const uint32_t cn = ccnt[(size_t)i * 8 + o];
+      s[1] += (cn + CHUNK - 1) / CHUNK;
+      s[2] += cn;
+      s[3] += cn < (uint32_t)SMALL_NODE ? 1u : 0u;
+      s[4] += cn > (uint32_t)CHUNK ? 1u : 0u;
+    }
+  if (flags & FLAG_REFINE) {
+    s[5] = 1;
+    s[6] = a.chunk_off[i + 1] - a.chunk_off[i];
+  }
+}
+
+__global__ void __launch_bounds__(EMIT_TILE) k_emit_count(LevelArgs a, const uint32_t* __restrict__ ccnt,
+                                                          uint32_t* __restrict__ tsum) {
+  __shared__ uint32_t wsum[EMIT_TILE / 64];
+  const uint32_t i = blockIdx.x * EMIT_TILE + threadIdx.x;
+  uint32_t mask = 0, flags = 0;
+  if (i < a.nnodes) {
+    mask = a.nt.child_mask[a.node0 + i];
+    flags = a.nt.flags[a.node0 + i];
+  }
+  uint32_t s[EMIT_SUMS];
+  emit_node_sums(a, ccnt, i, mask, flags, s);
+#pragma unroll
+  for (int q = 0; q < EMIT_SUMS; ++q) {
+    uint32_t t;
+    (void)scan_block<EMIT_TILE>(s[q], wsum, t);
+    if (threadIdx.x == 0) tsum[(size_t)blockIdx.x * 8 + q] = t;
+  }
+}
+
+// tsum: the tiles' sums in, their exclusive prefixes out (in place);
+// counters as k_emit's, and counters[8] = 0 for k_emit_write's count of
+// finished workgroups
+__global__ void __launch_bounds__(1024) k_emit_scan(uint32_t ntiles, uint32_t m, uint32_t* __restrict__ tsum,
+                                                    uint32_t* __restrict__ next_chunk_off,
+                                                    uint32_t* __restrict__ sel, uint32_t* __restrict__ counters) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t seg = (ntiles + 1023u) / 1024u;
+  const uint32_t b = min(ntiles, tid * seg), e = min(ntiles, b + seg);
+  uint32_t tot[EMIT_SUMS];
+#pragma unroll
+  for (int q = 0; q < EMIT_SUMS; ++q) {
+    uint32_t x = 0;
+    for (uint32_t t = b; t < e; ++t) x += tsum[(size_t)t * 8 + q];
+    uint32_t run = scan_1024(x, wsum, tot[q]);
+    for (uint32_t t = b; t < e; ++t) {
+      const uint32_t v = tsum[(size_t)t * 8 + q];
+      tsum[(size_t)t * 8 + q] = run;
+      run += v;
+    }
+  }
+  if (tid == 0) {
+    next_chunk_off[tot[0]] = tot[1];
+    if (sel) sel[m + 1 + tot[5]] = tot[6];
+    counters[0] = tot[0];
+    counters[1] = tot[1];
+    counters[2] = tot[2];
+    counters[4] = tot[3];
+    counters[5] = tot[5];
+    counters[6] = tot[4];
+    counters[7] = tot[6];
+    counters[8] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(EMIT_TILE) k_emit_write(LevelArgs a, const ProblemParams* __restrict__ prm,
+                                                          const uint32_t* __restrict__ cbeg,
+                                                          const uint32_t* __restrict__ ccnt, uint32_t next0,
+                                                          const uint32_t* __restrict__ toff, uint32_t ntiles,
+                                                          uint32_t* __restrict__ next_chunk_off,
+                                                          uint32_t* __restrict__ next_multi, uint32_t* __restrict__ sel,
+                                                          uint32_t* __restrict__ counters, uint32_t* __restrict__ hostc,
+                                                          uint32_t seq) {
+  __shared__ uint32_t wsum[EMIT_TILE / 64];
+  __shared__ uint32_t last;
+  const uint32_t tile = blockIdx.x, i = tile * EMIT_TILE + threadIdx.x;
+  const bool in = i < a.nnodes;
+  const uint32_t node = a.node0 + i;
+  uint32_t mask = 0, flags = 0;
+  if (in) {
+    mask = a.nt.child_mask[node];
+    flags = a.nt.flags[node];
+  }
+  uint32_t s[EMIT_SUMS];
+  emit_node_sums(a, ccnt, i, mask, flags, s);
+  // the node's first child, first child chunk, first multi-chunk list entry,
+  // flagged-list entry and first flagged chunk
+  uint32_t ex[EMIT_SUMS] = {};
+#pragma unroll
+  for (int q = 0; q < EMIT_SUMS; ++q) {
+    if (q == 2 || q == 3) continue;   // totals only
+    uint32_t t;
+    ex[q] = scan_block<EMIT_TILE>(s[q], wsum, t) + toff[(size_t)tile * 8 + q];
+  }
+  if (in && mask) {
+    a.nt.first_child[node] = next0 + ex[0];
+    const uint32_t prob = a.nt.problem[node], pre = a.nt.prefix[node];
+    uint32_t crun = ex[0], chunk = ex[1], mrun = ex[4];
+    for (uint32_t o = 0; o < 8u; ++o) {
+      if (!((mask >> o) & 1u)) continue;
+      const uint32_t cid = next0 + crun;
+      const uint32_t cpre = (pre << 3) | o;
+      const uint32_t cn = ccnt[(size_t)i * 8 + o];
+      a.nt.begin[cid] = cbeg[(size_t)i * 8 + o];
+      a.nt.count[cid] = cn;
+      a.nt.prefix[cid] = cpre;
+      a.nt.level[cid] = (uint32_t)(a.level + 1);
+      a.nt.problem[cid] = prob;
+      a.nt.parent[cid] = node;
+      a.nt.first_child[cid] = 0;
+      a.nt.child_mask[cid] = 0;
+      a.nt.flags[cid] = 0;
+      node_geo(prm[prob], a.level + 1, cpre, a.nt.geo + 6 * (size_t)cid);
+      next_chunk_off[crun] = chunk;
+      chunk += (cn + CHUNK - 1) / CHUNK;
+      if (cn > (uint32_t)CHUNK) next_multi[mrun++] = crun;
+      ++crun;
+    }
+  }
+  if (sel && in && (flags & FLAG_REFINE)) {
+    sel[ex[5]] = i;
+    sel[a.nnodes + 1 + ex[5]] = ex[6];
+  }
+  // the last workgroup to finish hands the counters to the host (after it,
+  // this launch writes nothing the host could release)
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(counters + 8, 1u) == ntiles - 1 ? 1u : 0u;
+  __syncthreads();
+  if (last && threadIdx.x == 0 && hostc) {
+    __threadfence();
+    hostc[0] = counters[0];
+    hostc[1] = counters[1];
+    hostc[2] = counters[2];
+    hostc[4] = counters[4];
+    hostc[5] = counters[5];
+    hostc[6] = counters[6];
+    hostc[7] = counters[7];
+    __hip_atomic_store(hostc + 3, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -1220,8 +1414,9 @@ hipError_t launch_solve_moments(int p, const LevelArgs& a, const double* part_m,
 
 template <int P>
 static hipError_t rsolve_impl(const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
-  if (a.nnodes == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_refine_solve<P>, dim3(a.nnodes, field_rows(a)), dim3(256), 0, s, a, part_b, fac);
+  const uint32_t n = a.sel ? a.nsel : a.nnodes;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine_solve<P>, dim3(n, field_rows(a)), dim3(256), 0, s, a, part_b, fac);
   return hipGetLastError();
 }
 hipError_t launch_refine_solve(int p, const LevelArgs& a, const double* part_b, const double* fac, hipStream_t s) {
@@ -1272,8 +1467,9 @@ hipError_t launch_factor_solve(int p, const LevelArgs& a, const double* part_b, 
 
 template <int P>
 static hipError_t resid_impl(int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {
-  if (a.nchunks == 0) return hipSuccess;
-  const dim3 grid(a.nchunks, field_rows(a));
+  const uint32_t n = a.sel ? a.nsel_chunks : a.nchunks;
+  if (n == 0) return hipSuccess;
+  const dim3 grid(n, field_rows(a));
   const dim3 block(ResidualShape<P>::THREADS);
   if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float>), grid, block, 0, s, a, part_ss);
   else hipLaunchKernelGGL((k_residual<P, double>), grid, block, 0, s, a, part_ss);
@@ -1308,10 +1504,23 @@ hipError_t launch_children(int p, const LevelArgs& a, const double* part_ss, uin
 
 hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint32_t* cbeg, const uint32_t* ccnt,
                        uint32_t* nact, uint32_t next0, uint32_t* next_chunk_off, uint32_t* counters, uint32_t* hostc,
-                       uint32_t seq, uint32_t* next_multi, hipStream_t s) {
-  hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, s, a, prm, cbeg, ccnt, nact, next0, next_chunk_off, counters,
-                     hostc, seq, next_multi);
+                       uint32_t seq, uint32_t* next_multi, uint32_t* sel, uint32_t* tiles, hipStream_t s) {
+  if (a.nnodes <= EMIT_TILED_MIN) {
+    hipLaunchKernelGGL(k_emit, dim3(1), dim3(1024), 0, s, a, prm, cbeg, ccnt, nact, next0, next_chunk_off, counters,
+                       hostc, seq, next_multi, sel);
+    return hipGetLastError();
+  }
+  if (!tiles) return hipErrorInvalidValue;
+  const uint32_t ntiles = (a.nnodes + EMIT_TILE - 1) / EMIT_TILE;
+  hipLaunchKernelGGL(k_emit_count, dim3(ntiles), dim3(EMIT_TILE), 0, s, a, ccnt, tiles);
+  hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(1024), 0, s, ntiles, a.nnodes, tiles, next_chunk_off, sel, counters);
+  hipLaunchKernelGGL(k_emit_write, dim3(ntiles), dim3(EMIT_TILE), 0, s, a, prm, cbeg, ccnt, next0, tiles, ntiles,
+                     next_chunk_off, next_multi, sel, counters, hostc, seq);
   return hipGetLastError();
+}
+
+size_t emit_tile_words(uint32_t nnodes) {
+  return nnodes <= EMIT_TILED_MIN ? 0 : 8ull * ((nnodes + EMIT_TILE - 1) / EMIT_TILE);
 }
 
 hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, hipStream_t s) {

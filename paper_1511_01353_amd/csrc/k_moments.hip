@@ -267,10 +267,14 @@ k_moments(LevelArgs a, double* __restrict__ part) {
   constexpr size_t SMEM_B = ALIAS ? (ST::BYTES > RED_B ? ST::BYTES : RED_B) : ST::BYTES + RED_B;
   __shared__ __attribute__((aligned(16))) char smem[SMEM_B];
   __shared__ double comb[MP::SPLIT > 1 ? MP::SPLIT * MP::NOUT : 1];
-  const uint32_t g = blockIdx.x;
-  // the grid may be an upper bound on the chunk count (pyramid cells)
-  if (g >= a.chunk_off[a.nnodes]) return;
-  const uint32_t k = chunk_node(a.chunk_off, a.nnodes, g);
+  uint32_t g = blockIdx.x, k;
+  if (a.sel) {
+    if (!listed_chunk(a, blockIdx.x, k, g)) return;
+  } else {
+    // the grid may be an upper bound on the chunk count (pyramid cells)
+    if (g >= a.chunk_off[a.nnodes]) return;
+    k = chunk_node(a.chunk_off, a.nnodes, g);
+  }
   const uint32_t node = a.node0 + k;
   const uint32_t nb = a.nt.begin[node], nc = a.nt.count[node];
   const uint32_t start = nb + (g - a.chunk_off[k]) * CHUNK;
@@ -392,7 +396,8 @@ k_moments(LevelArgs a, double* __restrict__ part) {
 
 template <int P, int MODE>
 static void launch_mode(int dtype, const LevelArgs& a, double* part, hipStream_t s) {
-  dim3 grid(a.nchunks, field_rows(a)), block(MomentPlan<P, MODE>::NTHR);
+  dim3 grid(a.sel ? a.nsel_chunks : a.nchunks, field_rows(a)), block(MomentPlan<P, MODE>::NTHR);
+  if (grid.x == 0) return;
   if (dtype == FMT_F32) hipLaunchKernelGGL((k_moments<P, MODE, float>), grid, block, 0, s, a, part);
   else hipLaunchKernelGGL((k_moments<P, MODE, double>), grid, block, 0, s, a, part);
 }

@@ -171,6 +171,21 @@ def test_batched_workload(fmt):
             want = oracle.evaluate(ot, pr.qx, pr.qy, pr.qz)
             got = tr.eval(dev(pr.qx), dev(pr.qy), dev(pr.qz)).cpu().numpy()
             compare_eval(ot, nodes, pr, got, want, FP64_RMS, min_frac=0.3)
+    # a problem's bits do not depend on its batch: at this size the levels
+    # are laid out by the tiled topology launches and the late refinement
+    # runs over listed nodes, neither of which a single fit of one of these
+    # problems does
+    for p in (4, 5, 6):
+        ks = sorted([k for k, pr in enumerate(probs) if pr.p == p], key=lambda k: probs[k].n)
+        for k in (ks[len(ks) // 2], ks[-1]):
+            pr, tb = probs[k], trees[k]
+            print(f"[case] batched problem {k} against its single fit: n={pr.n} p={pr.p}", flush=True)
+            ts = fmt.fmt_fit(opts[k], X[k], Y[k], Z[k], Fv[k])
+            a, b = tb.export_points(), ts.export_points()
+            for key in ("keys", "leaf", "residual"):
+                np.testing.assert_array_equal(a[key], b[key])
+            np.testing.assert_array_equal(tb.export_nodes()["coeffs"], ts.export_nodes()["coeffs"])
+            ts.close()
     for tr in trees:
         tr.close()
 
