@@ -1260,19 +1260,21 @@ __global__ void __launch_bounds__(EMIT_TILE) k_emit_count(LevelArgs a, const uin
 // tsum: the tiles' sums in, their exclusive prefixes out (in place);
 // counters as k_emit's, and counters[8] = 0 for k_emit_write's count of
 // finished workgroups
-__global__ void __launch_bounds__(1024) k_emit_scan(uint32_t ntiles, uint32_t m, uint32_t* __restrict__ tsum,
-                                                    uint32_t* __restrict__ next_chunk_off,
-                                                    uint32_t* __restrict__ sel, uint32_t* __restrict__ counters) {
-  __shared__ uint32_t wsum[16];
+// (a workgroup of four waves: on a device busy with other streams' kernels
+// it finds room on a compute unit sooner than one of sixteen)
+__global__ void __launch_bounds__(EMIT_TILE) k_emit_scan(uint32_t ntiles, uint32_t m, uint32_t* __restrict__ tsum,
+                                                         uint32_t* __restrict__ next_chunk_off,
+                                                         uint32_t* __restrict__ sel, uint32_t* __restrict__ counters) {
+  __shared__ uint32_t wsum[EMIT_TILE / 64];
   const uint32_t tid = threadIdx.x;
-  const uint32_t seg = (ntiles + 1023u) / 1024u;
+  const uint32_t seg = (ntiles + EMIT_TILE - 1) / EMIT_TILE;
   const uint32_t b = min(ntiles, tid * seg), e = min(ntiles, b + seg);
   uint32_t tot[EMIT_SUMS];
 #pragma unroll
   for (int q = 0; q < EMIT_SUMS; ++q) {
     uint32_t x = 0;
     for (uint32_t t = b; t < e; ++t) x += tsum[(size_t)t * 8 + q];
-    uint32_t run = scan_1024(x, wsum, tot[q]);
+    uint32_t run = scan_block<EMIT_TILE>(x, wsum, tot[q]);
     for (uint32_t t = b; t < e; ++t) {
       const uint32_t v = tsum[(size_t)t * 8 + q];
       tsum[(size_t)t * 8 + q] = run;
@@ -1513,7 +1515,8 @@ hipError_t launch_emit(const LevelArgs& a, const ProblemParams* prm, const uint3
   if (!tiles) return hipErrorInvalidValue;
   const uint32_t ntiles = (a.nnodes + EMIT_TILE - 1) / EMIT_TILE;
   hipLaunchKernelGGL(k_emit_count, dim3(ntiles), dim3(EMIT_TILE), 0, s, a, ccnt, tiles);
-  hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(1024), 0, s, ntiles, a.nnodes, tiles, next_chunk_off, sel, counters);
+  hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(EMIT_TILE), 0, s, ntiles, a.nnodes, tiles, next_chunk_off, sel,
+                     counters);
   hipLaunchKernelGGL(k_emit_write, dim3(ntiles), dim3(EMIT_TILE), 0, s, a, prm, cbeg, ccnt, next0, tiles, ntiles,
                      next_chunk_off, next_multi, sel, counters, hostc, seq);
   return hipGetLastError();
