@@ -887,6 +887,7 @@ std::shared_ptr<Forest> fit_group(const fmt_fit_opts& o, const std::vector<fmt_f
     a.fac_up = up_cells ? W.fac_up.as<double>() : nullptr;
     a.up_flags = up_cells ? d_upflags : nullptr;
     a.status = d_status;
+    a.nsmall = nsmall;
     // the mixed path's float32 Gram: too ill-conditioned nodes go to a
     // float64 re-solve
     a.regram = F->path == FMT_PATH_MIXED ? 1u : 0u;

@@ -72,6 +72,9 @@ struct LevelArgs {
   const uint32_t* sel = nullptr;
   const uint32_t* sel_off = nullptr;
   uint32_t nsel = 0, nsel_chunks = 0;
+  // the level's nodes with fewer than SMALL_NODE points (UINT32_MAX: not
+  // counted); the moment launches skip a size class the level lacks
+  uint32_t nsmall = UINT32_MAX;
 };
 
 // Nodes with fewer points than this take the r-weighted moments in mode 4
@@ -131,9 +134,10 @@ hipError_t launch_chunk_reduce(const LevelArgs& a, double* buf, uint32_t width, 
 hipError_t launch_node_geo(const NodeTable& nt, const ProblemParams* prm, uint32_t n, hipStream_t s);
 hipError_t launch_roots(const NodeTable& nt, const ProblemParams* prm, int nprob, hipStream_t s);
 hipError_t launch_gram(int p, int path, int dtype, const LevelArgs& a, double* partial, hipStream_t s);
-// Power moments of every chunk (mode 0: M, B, sum r^2; mode 1: B of
-// r - Lambda F; mode 2: B of the nodes with at least SMALL_NODE points;
-// mode 3: M; mode 4: B as mode 2, unstaged, of the smaller nodes).  The grid is a.nchunks workgroups,
+// Power moments of every chunk (mode 0: M, B, sum r^2 (for p <= 4 in two
+// launches by node size); mode 1: B of r - Lambda F; mode 2: B of the nodes
+// with at least SMALL_NODE points; mode 3: M; mode 4: B as mode 2, unstaged,
+// of the smaller nodes).  The grid is a.nchunks workgroups,
 // which may exceed chunk_off[nnodes] (the extra ones exit).  With
 // a.pyr_tab, mode 2 skips the nodes the pyramid does not cover and mode 0
 // those it covers.

@@ -740,7 +740,8 @@ struct ResidualShape {
   static constexpr int WAVES = THREADS / 64;
 };
 
-template <int P, typename TIN>
+// LISTED: the launch covers the listed nodes' chunks (a.sel)
+template <int P, typename TIN, bool LISTED>
 __global__ void __launch_bounds__(ResidualShape<P>::THREADS) k_residual(LevelArgs a, double* __restrict__ part_ss) {
   constexpr int L = basis_size(P);
   constexpr int NT = ResidualShape<P>::THREADS, NW = ResidualShape<P>::WAVES;
@@ -749,7 +750,7 @@ __global__ void __launch_bounds__(ResidualShape<P>::THREADS) k_residual(LevelArg
   __shared__ uint32_t redc[NW][8];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   uint32_t g = blockIdx.x, k;
-  if (a.sel) {
+  if constexpr (LISTED) {
     if (!listed_chunk(a, blockIdx.x, k, g)) return;
   } else {
     k = chunk_node(a.chunk_off, a.nnodes, g);
@@ -1052,7 +1053,7 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
   // one workgroup walks a level of tens of thousands of nodes (batches of
   // problems), and a load latency per iteration would dominate.
   constexpr uint32_t EB = 8;
-  uint32_t sum = 0, flagged = 0, fchunks = 0;
+  uint32_t sum = 0, flagged = 0;
   for (uint32_t i0 = b; i0 < e; i0 += EB) {
     uint32_t v[EB], f[EB];
 #pragma unroll
@@ -1065,26 +1066,29 @@ __global__ void __launch_bounds__(1024) k_emit(LevelArgs a, const ProblemParams*
     for (uint32_t u = 0; u < EB; ++u)
       if (i0 + u < e) {
         sum += v[u];
-        if (f[u] & FLAG_REFINE) {
-          ++flagged;
-          fchunks += a.chunk_off[i0 + u + 1] - a.chunk_off[i0 + u];
-        }
+        flagged += (f[u] & FLAG_REFINE) ? 1u : 0u;
       }
   }
-  uint32_t total, level_flagged, flagged_chunks;
+  uint32_t total, level_flagged, flagged_chunks = 0;
   uint32_t fpos = scan_1024(flagged, wsum, level_flagged);
-  uint32_t cpos = scan_1024(fchunks, wsum, flagged_chunks);
-  // the flagged nodes in order and their first chunk numbers among them,
-  // for the late refinement's launches
-  if (sel && flagged) {
-    uint32_t* sel_off = sel + m + 1;
-    for (uint32_t i = b; i < e; ++i)
-      if (a.nt.flags[a.node0 + i] & FLAG_REFINE) {
-        sel[fpos] = i;
-        sel_off[fpos] = cpos;
-        ++fpos;
-        cpos += a.chunk_off[i + 1] - a.chunk_off[i];
-      }
+  if (level_flagged) {   // (uniform) flagged nodes are rare
+    // the flagged nodes in order and their first chunk numbers among them,
+    // for the late refinement's launches
+    uint32_t fchunks = 0;
+    if (flagged)
+      for (uint32_t i = b; i < e; ++i)
+        if (a.nt.flags[a.node0 + i] & FLAG_REFINE) fchunks += a.chunk_off[i + 1] - a.chunk_off[i];
+    uint32_t cpos = scan_1024(fchunks, wsum, flagged_chunks);
+    if (sel && flagged) {
+      uint32_t* sel_off = sel + m + 1;
+      for (uint32_t i = b; i < e; ++i)
+        if (a.nt.flags[a.node0 + i] & FLAG_REFINE) {
+          sel[fpos] = i;
+          sel_off[fpos] = cpos;
+          ++fpos;
+          cpos += a.chunk_off[i + 1] - a.chunk_off[i];
+        }
+    }
   }
   if (sel && tid == 0) sel[m + 1 + level_flagged] = flagged_chunks;
   // each node's first child index (exclusive prefix of the active counts),
@@ -1473,8 +1477,13 @@ static hipError_t resid_impl(int dtype, const LevelArgs& a, double* part_ss, hip
   if (n == 0) return hipSuccess;
   const dim3 grid(n, field_rows(a));
   const dim3 block(ResidualShape<P>::THREADS);
-  if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float>), grid, block, 0, s, a, part_ss);
-  else hipLaunchKernelGGL((k_residual<P, double>), grid, block, 0, s, a, part_ss);
+  if (a.sel) {
+    if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float, true>), grid, block, 0, s, a, part_ss);
+    else hipLaunchKernelGGL((k_residual<P, double, true>), grid, block, 0, s, a, part_ss);
+  } else {
+    if (dtype == FMT_F32) hipLaunchKernelGGL((k_residual<P, float, false>), grid, block, 0, s, a, part_ss);
+    else hipLaunchKernelGGL((k_residual<P, double, false>), grid, block, 0, s, a, part_ss);
+  }
   return hipGetLastError();
 }
 hipError_t launch_residual(int p, int dtype, const LevelArgs& a, double* part_ss, hipStream_t s) {

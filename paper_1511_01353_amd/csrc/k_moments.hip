@@ -24,7 +24,13 @@
 // finest level; 4 = B only as mode 2 for the nodes with fewer than
 // SMALL_NODE points (mode 2 takes the others): two waves per chunk reading
 // their points straight from memory (no staging, so many more workgroups
-// share a compute unit).
+// share a compute unit); 5 = mode 0 for the nodes with fewer than
+// SMALL_NODE points (mode 0 then takes the others; p <= SMALL_M_P): four
+// waves, a staging buffer for SMALL_NODE points and reduction rounds of 8
+// accumulators, so that three workgroups share a compute unit where mode 0
+// fits one (levels of tens of thousands of small nodes in a batch).  At
+// p = 5 and 6 the nodes' moments take more passes over the points in four
+// waves than the split saves, and mode 0 keeps every node.
 #include <utility>
 
 #include "k_level.h"
@@ -37,11 +43,14 @@ __host__ __device__ constexpr int gidx(int a, int b, int c) {
   return k * (k + 1) * (k + 2) / 6 + (k - a) * (k - a + 1) / 2 + (k - a - b);
 }
 
+// highest order whose small nodes take mode 5
+constexpr int SMALL_M_P = 4;
+
 template <int P, int MODE>
 struct MomentPlan {
-  static constexpr bool HAS_M = MODE == 0 || MODE == 3;
+  static constexpr bool HAS_M = MODE == 0 || MODE == 3 || MODE == 5;
   static constexpr bool HAS_B = MODE != 3;
-  static constexpr bool HAS_RR = MODE == 0;
+  static constexpr bool HAS_RR = MODE == 0 || MODE == 5;
   static constexpr int P2 = 2 * P;
   static constexpr int NM = HAS_M ? basis_size(P2) : 0;
   static constexpr int NB = HAS_B ? basis_size(P) : 0;
@@ -52,7 +61,7 @@ struct MomentPlan {
   static constexpr int CAP = 64;   // accumulators per lane budget
   // waves per workgroup: mode 3 runs over many small cells, where smaller
   // workgroups let more of them share a compute unit
-  static constexpr int WAVES = MODE == 3 ? 4 : (MODE == 4 ? 2 : 8);
+  static constexpr int WAVES = MODE == 3 || MODE == 5 ? 4 : (MODE == 4 ? 2 : 8);
   static constexpr int NW_MAX = HAS_M ? WAVES : 2;
   static constexpr int NG_MIN = (NOUT + CAP - 1) / CAP;
   static constexpr int NW = NG_MIN < NW_MAX ? (NG_MIN < 1 ? 1 : NG_MIN) : NW_MAX;
@@ -63,7 +72,7 @@ struct MomentPlan {
   static constexpr int NTHR = NW * SPLIT * 64;
   // accumulators per reduction round: 16 when the reduction buffer can
   // share the LDS of the staged points (one pass over the groups), else 8
-  static constexpr int RROWS = HAS_M && NPASS == 1 ? 16 : 8;
+  static constexpr int RROWS = HAS_M && NPASS == 1 && MODE != 5 ? 16 : 8;
   static constexpr int PMAX = HAS_M ? P2 : P;    // highest power used
 
   // items: kind 0 = M run, 1 = B run, 2 = sum r^2
@@ -159,12 +168,14 @@ __device__ __forceinline__ void accumulate(std::index_sequence<T...>, const doub
 }
 
 // The chunk's points staged in LDS: coordinates in the input type, and the
-// weight (r, or r' in mode 1) in float64 except in mode 3.
+// weight (r, or r' in mode 1) in float64 except in mode 3; room for CAP
+// points (a chunk; mode 5's nodes have fewer than SMALL_NODE).
 template <int MODE, typename TIN>
 struct Staged {
   static constexpr bool HAS_W = MODE != 3;
   static constexpr bool IN_LDS = MODE != 4;   // mode 4 reads the points where they are
-  static constexpr size_t BYTES = IN_LDS ? (size_t)CHUNK * (3 * sizeof(TIN) + (HAS_W ? sizeof(double) : 0)) : 0;
+  static constexpr uint32_t CAP = MODE == 5 ? (uint32_t)SMALL_NODE : (uint32_t)CHUNK;
+  static constexpr size_t BYTES = IN_LDS ? (size_t)CAP * (3 * sizeof(TIN) + (HAS_W ? sizeof(double) : 0)) : 0;
   const TIN* x;
   const TIN* y;
   const TIN* z;
@@ -172,9 +183,9 @@ struct Staged {
   __device__ Staged(char* base) {
     TIN* p = reinterpret_cast<TIN*>(base);
     x = p;
-    y = p + CHUNK;
-    z = p + 2 * CHUNK;
-    w = reinterpret_cast<const double*>(p + 3 * CHUNK);
+    y = p + CAP;
+    z = p + 2 * CAP;
+    w = reinterpret_cast<const double*>(p + 3 * CAP);
   }
   __device__ Staged(const TIN* gx, const TIN* gy, const TIN* gz, const double* gw) : x(gx), y(gy), z(gz), w(gw) {}
 };
@@ -268,7 +279,8 @@ k_moments(LevelArgs a, double* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) char smem[SMEM_B];
   __shared__ double comb[MP::SPLIT > 1 ? MP::SPLIT * MP::NOUT : 1];
   uint32_t g = blockIdx.x, k;
-  if (a.sel) {
+  if (MODE == 1 && a.sel) {
+    // the late refinement's sweep over the listed nodes
     if (!listed_chunk(a, blockIdx.x, k, g)) return;
   } else {
     // the grid may be an upper bound on the chunk count (pyramid cells)
@@ -282,25 +294,26 @@ k_moments(LevelArgs a, double* __restrict__ part) {
   const double* geo = a.nt.geo + 6 * (size_t)node;
   const uint32_t fj = blockIdx.y;   // field of a multi-field launch
   const double* rin = a.r + (size_t)fj * a.rstride;
-  if constexpr (MODE == 0 || MODE == 2 || MODE == 4) {
+  if constexpr (MODE == 0 || MODE == 2 || MODE == 4 || MODE == 5) {
     // a level split between the pyramid's nodes (modes 2, 4) and the others
-    if (a.pyr_tab && pyramid_covers(a.pyr_tab[PYR_TAB_WORDS * a.nt.problem[node] + 1], a.level) != (MODE != 0)) return;
+    constexpr bool PYR_NODES = MODE == 2 || MODE == 4;
+    if (a.pyr_tab && pyramid_covers(a.pyr_tab[PYR_TAB_WORDS * a.nt.problem[node] + 1], a.level) != PYR_NODES) return;
   }
-  if constexpr (MODE == 0) {
+  if constexpr (MODE == 0 || MODE == 5) {
     if (a.only_flag && !(a.nt.flags[node] & a.only_flag)) return;   // not this pass's node
   }
-  // modes 2 and 4 split the nodes by size
-  if constexpr (MODE == 2) {
+  // modes 2 and 4, and 0 and 5 (p <= SMALL_M_P), split the nodes by size
+  if constexpr (MODE == 2 || (MODE == 0 && P <= SMALL_M_P)) {
     if (nc < SMALL_NODE) return;
   }
-  if constexpr (MODE == 4) {
+  if constexpr (MODE == 4 || MODE == 5) {
     if (nc >= SMALL_NODE) return;
   }
   if constexpr (MODE == 1) {
     if (!(a.nt.flags[node] & FLAG_REFINE)) return;   // whole workgroup: its node needs no refinement
   }
   TIN* sxw = reinterpret_cast<TIN*>(smem);
-  double* sww = reinterpret_cast<double*>(sxw + 3 * CHUNK);
+  double* sww = reinterpret_cast<double*>(sxw + 3 * ST::CAP);
   const TIN* gx = (const TIN*)a.px + start;
   const TIN* gy = (const TIN*)a.py + start;
   const TIN* gz = (const TIN*)a.pz + start;
@@ -341,8 +354,8 @@ k_moments(LevelArgs a, double* __restrict__ part) {
         const uint32_t i = i0 + q * NT;
         if (i < n) {
           sxw[i] = vx[q];
-          sxw[CHUNK + i] = vy[q];
-          sxw[2 * CHUNK + i] = vz[q];
+          sxw[ST::CAP + i] = vy[q];
+          sxw[2 * ST::CAP + i] = vz[q];
           sww[i] = r[q] - val[q];
         }
       }
@@ -364,8 +377,8 @@ k_moments(LevelArgs a, double* __restrict__ part) {
         const uint32_t i = i0 + q * NT;
         if (i < n) {
           sxw[i] = vx[q];
-          sxw[CHUNK + i] = vy[q];
-          sxw[2 * CHUNK + i] = vz[q];
+          sxw[ST::CAP + i] = vy[q];
+          sxw[2 * ST::CAP + i] = vz[q];
           if constexpr (ST::HAS_W) sww[i] = r[q];
         }
       }
@@ -396,7 +409,7 @@ k_moments(LevelArgs a, double* __restrict__ part) {
 
 template <int P, int MODE>
 static void launch_mode(int dtype, const LevelArgs& a, double* part, hipStream_t s) {
-  dim3 grid(a.sel ? a.nsel_chunks : a.nchunks, field_rows(a)), block(MomentPlan<P, MODE>::NTHR);
+  dim3 grid(MODE == 1 && a.sel ? a.nsel_chunks : a.nchunks, field_rows(a)), block(MomentPlan<P, MODE>::NTHR);
   if (grid.x == 0) return;
   if (dtype == FMT_F32) hipLaunchKernelGGL((k_moments<P, MODE, float>), grid, block, 0, s, a, part);
   else hipLaunchKernelGGL((k_moments<P, MODE, double>), grid, block, 0, s, a, part);
@@ -414,7 +427,12 @@ static hipError_t moments_impl(int mode, int dtype, const LevelArgs& a, double* 
     }
   } else {
     switch (mode) {
-      case 0: launch_mode<P, 0>(dtype, a, part, s); break;
+      case 0:
+        // up to SMALL_M_P the larger nodes in mode 0, those under SMALL_NODE
+        // points in mode 5
+        if (P > SMALL_M_P || a.nsmall == UINT32_MAX || a.nsmall < a.nnodes) launch_mode<P, 0>(dtype, a, part, s);
+        if (P <= SMALL_M_P && a.nsmall > 0) launch_mode<P, 5>(dtype, a, part, s);
+        break;
       case 1: launch_mode<P, 1>(dtype, a, part, s); break;
       case 2: launch_mode<P, 2>(dtype, a, part, s); break;
       case 3: launch_mode<P, 3>(dtype, a, part, s); break;
