@@ -60,11 +60,11 @@ struct MomentPlan {
   static constexpr int NI = NI_M + NI_B + (HAS_RR ? 1 : 0);
   static constexpr int CAP = 64;   // accumulators per lane budget
   // waves per workgroup: mode 3 runs over many small cells, where smaller
-  // workgroups let more of them share a compute unit; mode 2 (B of the
-  // large nodes, two groups of runs) splits a chunk's points over two
-  // slices (four over eight waves measured ~1% slower per fit, eight over
-  // sixteen 7%)
-  static constexpr int WAVES = MODE == 3 || MODE == 5 || MODE == 2 ? 4 : (MODE == 4 ? 2 : 8);
+  // workgroups let more of them share a compute unit; modes 1 and 2 (B, two
+  // groups of runs) split a chunk's points over two slices (four slices over
+  // eight waves measured ~1% slower per float64 fit and 6% slower per mixed
+  // fit, whose refinement sweeps every node; eight over sixteen 7% slower)
+  static constexpr int WAVES = MODE == 3 || MODE == 5 || MODE == 2 || MODE == 1 ? 4 : (MODE == 4 ? 2 : 8);
   static constexpr int NW_MAX = HAS_M ? WAVES : 2;
   static constexpr int NG_MIN = (NOUT + CAP - 1) / CAP;
   static constexpr int NW = NG_MIN < NW_MAX ? (NG_MIN < 1 ? 1 : NG_MIN) : NW_MAX;
