@@ -25,12 +25,12 @@
 // SMALL_NODE points (mode 2 takes the others): two waves per chunk reading
 // their points straight from memory (no staging, so many more workgroups
 // share a compute unit); 5 = mode 0 for the nodes with fewer than
-// SMALL_NODE points (mode 0 then takes the others; p <= SMALL_M_P): four
-// waves, a staging buffer for SMALL_NODE points and reduction rounds of 8
-// accumulators, so that three workgroups share a compute unit where mode 0
-// fits one (levels of tens of thousands of small nodes in a batch).  At
-// p = 5 and 6 the nodes' moments take more passes over the points in four
-// waves than the split saves, and mode 0 keeps every node.
+// SMALL_NODE points (mode 0 then takes the others; p <= SMALL_M_P): a
+// staging buffer for SMALL_NODE points and reduction rounds of 8
+// accumulators, 20 KB of LDS against mode 0's 40 KB (levels of tens of
+// thousands of small nodes in a batch; measured with mode 0 in eight-wave
+// workgroups, when it fitted one workgroup per compute unit).  At p = 5
+// and 6 the split cost more than it saved, and mode 0 keeps every node.
 #include <utility>
 
 #include "k_level.h"
@@ -59,12 +59,14 @@ struct MomentPlan {
   static constexpr int NI_B = HAS_B ? (P + 1) * (P + 2) / 2 : 0;
   static constexpr int NI = NI_M + NI_B + (HAS_RR ? 1 : 0);
   static constexpr int CAP = 64;   // accumulators per lane budget
-  // waves per workgroup: mode 3 runs over many small cells, where smaller
-  // workgroups let more of them share a compute unit; modes 1 and 2 (B, two
-  // groups of runs) split a chunk's points over two slices (four slices over
-  // eight waves measured ~1% slower per float64 fit and 6% slower per mixed
-  // fit, whose refinement sweeps every node; eight over sixteen 7% slower)
-  static constexpr int WAVES = MODE == 3 || MODE == 5 || MODE == 2 || MODE == 1 ? 4 : (MODE == 4 ? 2 : 8);
+  // waves per workgroup, measured: four (mode 4: two).  Workgroups of eight
+  // waves were ~1% slower per float64 fit in the B passes (modes 1 and 2:
+  // four point slices of two groups of runs instead of two), 6% slower per
+  // mixed fit (whose refinement sweeps every node) and 2% slower per batch
+  // in mode 0 (whose 70 KB tile then left one workgroup per compute unit);
+  // sixteen were 7% slower.  Mode 3 runs over many small cells, where small
+  // workgroups let more of them share a compute unit.
+  static constexpr int WAVES = MODE == 4 ? 2 : 4;
   static constexpr int NW_MAX = HAS_M ? WAVES : 2;
   static constexpr int NG_MIN = (NOUT + CAP - 1) / CAP;
   static constexpr int NW = NG_MIN < NW_MAX ? (NG_MIN < 1 ? 1 : NG_MIN) : NW_MAX;
