@@ -59,14 +59,15 @@ struct MomentPlan {
   static constexpr int NI_B = HAS_B ? (P + 1) * (P + 2) / 2 : 0;
   static constexpr int NI = NI_M + NI_B + (HAS_RR ? 1 : 0);
   static constexpr int CAP = 64;   // accumulators per lane budget
-  // waves per workgroup, measured: four (mode 4: two).  Workgroups of eight
-  // waves were ~1% slower per float64 fit in the B passes (modes 1 and 2:
-  // four point slices of two groups of runs instead of two), 6% slower per
-  // mixed fit (whose refinement sweeps every node) and 2% slower per batch
-  // in mode 0 (whose 70 KB tile then left one workgroup per compute unit);
-  // sixteen were 7% slower.  Mode 3 runs over many small cells, where small
-  // workgroups let more of them share a compute unit.
-  static constexpr int WAVES = MODE == 4 ? 2 : 4;
+  // waves per workgroup, measured up to p = 8: four (mode 4: two).
+  // Workgroups of eight waves were ~1% slower per float64 fit in the B
+  // passes (modes 1 and 2: four point slices of two groups of runs instead
+  // of two), 6% slower per mixed fit (whose refinement sweeps every node)
+  // and 2% slower per batch in mode 0 (whose 70 KB tile then left one
+  // workgroup per compute unit); sixteen were 7% slower.  Mode 3 runs over
+  // many small cells, where small workgroups let more of them share a
+  // compute unit.  The large bases (p > 8) keep eight waves.
+  static constexpr int WAVES = MODE == 4 ? 2 : (P > 8 ? 8 : 4);
   static constexpr int NW_MAX = HAS_M ? WAVES : 2;
   static constexpr int NG_MIN = (NOUT + CAP - 1) / CAP;
   static constexpr int NW = NG_MIN < NW_MAX ? (NG_MIN < 1 ? 1 : NG_MIN) : NW_MAX;
