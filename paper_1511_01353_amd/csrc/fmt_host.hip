@@ -328,6 +328,9 @@ struct Forest {
   // composite coefficients (each node's chain of polynomials in its own
   // frame), built on the first evaluation; `composed` marks their completion
   std::mutex compose_mu;
+  // a single tree's composite coefficients and cell table in one allocation
+  // (nb_ccoef and cell_tab[0] are views of it)
+  DevBuf eval_mem;
   DevBuf nb_ccoef;
   hipEvent_t composed = nullptr;
   // per problem: cell table (cell of depth T -> deepest node), its depth and
@@ -1566,7 +1569,17 @@ static void ensure_composed(Forest& F, int problem, hipStream_t s) {
     // [frame table | cells]; the frames use the problem's box, the same
     // scale as the fit's node frames
     DevBuf& b = F.cell_tab[problem];
-    b.alloc(1024 + (sizeof(uint32_t) << (3 * T)));
+    const size_t cell_bytes = 1024 + (sizeof(uint32_t) << (3 * T));
+    if (F.probs.size() == 1 && !F.composed && !F.nb_ccoef.p) {
+      // one allocation for the tree's cell table and composite coefficients
+      const size_t cb = (cell_bytes + 255) & ~(size_t)255;
+      const size_t ccb = sizeof(double) * (size_t)ccoef_stride(F.L) * std::max<uint32_t>(F.nodes, 1);
+      F.eval_mem.alloc(cb + ccb);
+      b = DevBuf::view(F.eval_mem.p, 0, cell_bytes);
+      F.nb_ccoef = DevBuf::view(F.eval_mem.p, cb, ccb);
+    } else {
+      b.alloc(cell_bytes);
+    }
     HIPCHK(launch_cell_table(F.table(), F.probs[problem].root, T, F.probs[problem].prm, b.as<double>(),
                              (uint32_t*)(b.as<char>() + 1024), s));
     hipEvent_t ev = nullptr;
@@ -1577,7 +1590,7 @@ static void ensure_composed(Forest& F, int problem, hipStream_t s) {
   }
   HIPCHK(hipStreamWaitEvent(s, F.cell_ev[problem], 0));
   if (!F.composed) {
-    F.nb_ccoef.alloc(sizeof(double) * (size_t)ccoef_stride(F.L) * std::max<uint32_t>(F.nodes, 1));
+    if (!F.nb_ccoef.p) F.nb_ccoef.alloc(sizeof(double) * (size_t)ccoef_stride(F.L) * std::max<uint32_t>(F.nodes, 1));
     {
       ProfScope ps(KN_COMPOSE, F.nodes, s);
       HIPCHK(launch_compose(F.p, F.table(), 0, F.nodes, F.nb_ccoef.as<double>(), s));
